@@ -1,0 +1,86 @@
+"""Seeded synthetic workloads shared by the tests, the bench and the smoke run.
+
+This module holds parameters and seeded random inputs only -- none of the
+method's arithmetic.  Both the HIP library's callers and the oracle's callers
+take their inputs from here; neither side imports the other.
+
+Workloads (all periodic, rho0 = 1, fluid initially at rest, lattice units):
+
+* ``d2q9_32_fp64``     D2Q9 ideal gas 32x32, FP64, all rates 1.0, kT 1e-4,
+                        seed 1234, 1000 steps (FDT and conservation case).
+* ``d3q19_128``         D3Q19 ideal gas 128^3, FP32 shifted storage (and the
+                        FP64 step beside it), rates bulk/shear/ghost
+                        1.2/1.6/1.0, kT 1e-5, seed 7, 2000 steps.
+* ``d3q19_256_landau``  D3Q19 non-ideal 256^3, FP32, psi = a(r-rc)^2 + b(r-rc)^4
+                        with a -0.01, b 0.1, rc 1, kappa 0.05, all rates 1.0,
+                        rho = rc + 0.01 N(0,1), kT 1e-6, seed 7, 5000 steps.
+* ``d3q19_batch64``     64 ideal-gas D3Q19 replicas of edge drawn uniformly
+                        from {32, 48, 64, 80, 96}, seeds 0..63, rates as
+                        d3q19_128, kT 1e-5, FP32, 1000 steps.
+* ``d2q9_256_adjoint``  D2Q9 non-ideal 256x256 (Landau as above), FP32, all
+                        rates 1.0 at the evaluation point, target density from
+                        the same run at shear rate 1.5, kT 1e-6, seed 1234,
+                        400 steps, checkpoint every 20.
+
+The paper's own runs use no public dataset; its 2-D demonstrations (128^2
+homogeneous fluid, 1024x400 liquid stripe) are parameter sets, not data.
+"""
+
+import numpy as np
+
+LANDAU = dict(force_model=1, a=-0.01, b=0.1, rho_c=1.0, kappa=0.05, eta=0)
+
+WORKLOADS = {
+    "d2q9_32_fp64": dict(lattice="D2Q9", precision="fp64", nx=32, ny=32, nz=1, rho0=1.0,
+                         kT=1e-4, rate_bulk=1.0, rate_shear=1.0, rate_ghost=1.0,
+                         seed=1234, steps=1000),
+    "d3q19_128": dict(lattice="D3Q19", precision="fp32", nx=128, ny=128, nz=128, rho0=1.0,
+                      kT=1e-5, rate_bulk=1.2, rate_shear=1.6, rate_ghost=1.0,
+                      seed=7, steps=2000),
+    "d3q19_256_landau": dict(lattice="D3Q19", precision="fp32", nx=256, ny=256, nz=256,
+                             rho0=1.0, kT=1e-6, rate_bulk=1.0, rate_shear=1.0,
+                             rate_ghost=1.0, seed=7, steps=5000, init_noise=0.01, **LANDAU),
+    "d3q19_batch64": dict(lattice="D3Q19", precision="fp32", replicas=64,
+                          edges=(32, 48, 64, 80, 96), size_seed=2024, rho0=1.0, kT=1e-5,
+                          rate_bulk=1.2, rate_shear=1.6, rate_ghost=1.0, steps=1000),
+    "d2q9_256_adjoint": dict(lattice="D2Q9", precision="fp32", nx=256, ny=256, nz=1,
+                             rho0=1.0, kT=1e-6, rate_bulk=1.0, rate_shear=1.0,
+                             rate_ghost=1.0, target_rate_shear=1.5, seed=1234, steps=400,
+                             checkpoint_every=20, init_noise=0.01, **LANDAU),
+}
+
+PARAM_KEYS = ("lattice", "nx", "ny", "nz", "rho0", "kT", "rate_bulk", "rate_shear",
+              "rate_ghost", "force_model", "a", "b", "rho_c", "kappa", "eta", "seed")
+
+
+def params_of(name, **override):
+    """The FLB parameters of a workload as a plain dict (keys of PARAM_KEYS)."""
+    w = dict(WORKLOADS[name])
+    w.update(override)
+    return {k: w[k] for k in PARAM_KEYS if k in w}
+
+
+def initial_drho(shape, seed, amplitude=0.01, offset=0.0):
+    """rho(x) - rho0 for an initial state: offset + amplitude * N(0,1) per site,
+    float64 array of ``shape`` (nz, ny, nx), from numpy's PCG64 with ``seed``."""
+    rng = np.random.default_rng(seed)
+    return offset + amplitude * rng.standard_normal(shape)
+
+
+def batch_edges(replicas=64, edges=(32, 48, 64, 80, 96), seed=2024):
+    """Cubic edge length of every replica, drawn uniformly from ``edges``."""
+    rng = np.random.default_rng(seed)
+    return [int(edges[k]) for k in rng.integers(0, len(edges), size=replicas)]
+
+
+def random_populations(q, shape, seed, amplitude):
+    """A seeded non-equilibrium perturbation of the populations, shape (q, *shape)."""
+    rng = np.random.default_rng(seed)
+    return amplitude * rng.standard_normal((q,) + tuple(shape))
+
+
+def unit_direction(shape, seed):
+    """A seeded unit-norm direction (float64) for directional derivatives."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(shape)
+    return v / np.linalg.norm(v)
