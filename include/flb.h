@@ -1,0 +1,241 @@
+/*
+ * flb.h -- C ABI of the MI355X (gfx950) fluctuating lattice Boltzmann library.
+ *
+ * The library integrates the fluctuating lattice Boltzmann equation in moment
+ * space (Gross, Cates, Varnik, Adhikari, "Langevin theory of fluctuations in
+ * the discrete Boltzmann equation", Sec. V eq. lbe-mom) on periodic D2Q9 or
+ * D3Q19 lattices, for the ideal gas (Sec. IV.A) and for the force-based
+ * non-ideal fluid (Sec. IV.B.1) with the square-gradient force of App. A
+ * (eq. he-force) and the Landau double well of Sec. VI (eq. f0-bulk).
+ *
+ * One time step with index n maps the post-collision populations S_n to S_{n+1}:
+ *   pull      f_i(x) = S_{n,i}(x - c_i)                         (periodic)
+ *   moments   m_a = sum_i T_ai f_i                              (Sec. III eq. moments)
+ *   hydro     rho = m_0, rho u = j + F/2                        (Sec. V eq. lbe-moments)
+ *   update    m*_a = m_a - lam_a (m_a - m^eq_a) + (1 - lam_a/2) m^F_a + xi_a
+ *             lam_a = 0 for rho and j; <xi_a xi_b> = rho kT N_a lam_a (2 - lam_a)/cs2 delta_ab
+ *                                                                (Sec. V eq. noise-lbe, Delta V = 1)
+ *   back      S_{n+1,i}(x) = w_i sum_a T_ai m*_a / N_a          (Sec. III eq. moments-inv)
+ * with cs2 = 1/3, the ideal-gas equilibrium moments of Sec. III eq. feq and the
+ * second-order (Guo) forcing moments {0, F, uF + Fu, 0 on ghosts}.
+ *
+ * Non-ideal force (force_model = 1), evaluated on the density after streaming:
+ *   mu = psi'(rho) - kappa lap_h rho,   psi = a (rho - rho_c)^2 + b (rho - rho_c)^4
+ *   F  = -rho grad_h mu + eta cs2 grad_h rho
+ *   grad_h phi = (1/cs2) sum_i w_i c_i phi(x + c_i),
+ *   lap_h  phi = (2/cs2) sum_i w_i (phi(x + c_i) - phi(x))   (9- or 19-point)
+ *
+ * Noise: every non-conserved mode a (in basis order, k = a - d - 1) draws a
+ * standard normal z_k from Philox4x32-10 (Salmon et al., SC'11) with counter
+ * (site, step, k/4 | tag << 16, replica) and key (seed mod 2^32, seed >> 32),
+ * site = x + nx (y + ny z), tag = 0; words r of one block give uniforms
+ * ((r >> 8) + 1) 2^-24 (FP32) or (r + 1) 2^-32 (FP64), and Box-Muller pairs
+ * (r0, r1) -> z_{4k}, z_{4k+1} = sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1),
+ * (r2, r3) -> z_{4k+2}, z_{4k+3}.
+ *
+ * Storage: populations are stored shifted, delta f_i = f_i - w_i rho0, in
+ * structure-of-arrays order f[i * V + site] (V = nx ny nz sites, x fastest),
+ * in FP32 or FP64.  Statistics are accumulated in FP64.
+ *
+ * Conventions for every call:
+ *  - Device buffers are allocated and owned by the caller; the library never
+ *    allocates or frees device memory.  Pointers must be 256-byte aligned.
+ *  - "stream" is a hipStream_t (NULL = the null stream).  Calls are
+ *    stream-ordered and asynchronous unless stated otherwise.
+ *  - Every call returns an flb_status; nothing throws across the ABI.
+ *    flb_last_error() gives a text description of the last failure of the
+ *    calling thread.
+ *  - A handle is host-side state only; it is not thread-safe.
+ */
+#ifndef FLB_H
+#define FLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FLB_OK = 0,
+    FLB_ERR_INVALID_ARG = -1, /* a parameter, size or pointer was rejected     */
+    FLB_ERR_HIP = -2,         /* a HIP runtime call failed                      */
+    FLB_ERR_NONFINITE = -3,   /* statistics contain NaN or Inf                  */
+    FLB_ERR_UNSUPPORTED = -4, /* combination not implemented                   */
+    FLB_ERR_STATE = -5        /* call not valid in the handle's current state   */
+} flb_status;
+
+enum { FLB_D2Q9 = 0, FLB_D3Q19 = 1 };
+enum { FLB_FP32 = 0, FLB_FP64 = 1 };
+enum { FLB_IDEAL = 0, FLB_LANDAU = 1 };
+
+/* Parameters of one run.  Rates are the lattice rates lam^LB in (0, 2)
+ * (Sec. V: lam^LB = 2 lam / (2 + lam)), one per mode class of App. B:
+ * bulk (trace of the stress), shear (traceless stress), ghost (all ghosts).
+ * kT must satisfy 0 <= kT < rho0 cs2 (stability bound stated in Sec. VI.A). */
+typedef struct flb_params {
+    int32_t lattice;          /* FLB_D2Q9 or FLB_D3Q19                          */
+    int32_t precision;        /* FLB_FP32 or FLB_FP64                           */
+    int32_t nx, ny, nz;       /* periodic box; nz = 1 for D2Q9                  */
+    int32_t force_model;      /* FLB_IDEAL or FLB_LANDAU                        */
+    int32_t eta;              /* 0: F = -rho grad mu; 1: + cs2 grad rho         */
+    int32_t noise_rho_local;  /* 1: noise variance uses local rho(x); 0: rho0   */
+    double rho0;              /* reference density (> 0)                        */
+    double kT;                /* fluctuation temperature                        */
+    double rate_bulk, rate_shear, rate_ghost;
+    double a, b, rho_c, kappa;/* Landau psi and square-gradient coefficient    */
+    uint64_t seed;            /* Philox key                                     */
+    uint64_t step0;           /* index of the first step (resume)               */
+    uint32_t replica;         /* Philox counter word 3                          */
+    uint32_t reserved;
+} flb_params;
+
+typedef struct flb_handle flb_handle;
+
+/* Sizes (bytes) of the caller-allocated device buffers for parameters p:
+ * pop_bytes for each of the two population buffers (Q V reals), scratch_bytes
+ * for the work area (counters and, for the non-ideal fluid, the density and
+ * adjoint fields), stats_bytes for the FP64 statistics partials.
+ * Returns FLB_ERR_INVALID_ARG for invalid parameters (see flb_init). Host only. */
+flb_status flb_query_sizes(const flb_params* p, size_t* pop_bytes, size_t* scratch_bytes,
+                           size_t* stats_bytes);
+
+/* Create a handle and write the initial state S_0,i(x) = w_i rho(x) (the u = 0
+ * equilibrium of Sec. III eq. feq) into f_a, with rho = rho0 + drho_init[x]
+ * (drho_init: device pointer to V doubles, or NULL for rho = rho0).  Clears the
+ * statistics.  f_a, f_b, scratch and stats must have the sizes given by
+ * flb_query_sizes and stay valid for the handle's life.
+ * Rejects (FLB_ERR_INVALID_ARG): unknown lattice/precision/force model, sizes
+ * < 1 or nz != 1 for D2Q9 or sites >= 2^31, rates outside (0, 2), kT < 0 or
+ * kT >= rho0/3, rho0 <= 0, null or misaligned buffers. */
+flb_status flb_init(const flb_params* p, void* f_a, void* f_b, void* scratch, void* stats,
+                    const double* drho_init, void* stream, flb_handle** out);
+
+/* Advance nsteps time steps.  If stats_stride > 0, the pre-collision moments
+ * of every step k (0-based in this call) with (k + 1) % stats_stride == 0 are
+ * accumulated into the FP64 statistics (sum and sum of squares per mode over
+ * sites, with m_0 taken as rho - rho0).  Asynchronous. */
+flb_status flb_step(flb_handle* h, int64_t nsteps, int32_t stats_stride, void* stream);
+
+/* Current state: *cur receives the device buffer holding S_n, *other the
+ * second buffer, *step the index n of the next step.  Host only. */
+flb_status flb_state(const flb_handle* h, void** cur, void** other, uint64_t* step);
+
+/* Finalize the statistics in a fixed order and copy them to the host:
+ * mode_sum[Q], mode_sumsq[Q] (either may be NULL), *nsamples the number of
+ * sampled steps.  Synchronizes the stream.  Returns FLB_ERR_NONFINITE if a
+ * sum is not finite. */
+flb_status flb_moments(flb_handle* h, double* mode_sum, double* mode_sumsq, int64_t* nsamples,
+                       void* stream);
+
+/* Zero the statistics.  Asynchronous. */
+flb_status flb_reset_stats(flb_handle* h, void* stream);
+
+/* Hydrodynamic fields of the current state after streaming (Sec. V
+ * eq. lbe-moments): out[0..V) = rho, out[(1 + a) V ..) = rho u_a for a < d,
+ * rho u = sum_i c_i f_i + F/2, in the handle's precision (device pointer to
+ * (1 + d) V reals).  Asynchronous. */
+flb_status flb_fields(flb_handle* h, void* out, void* stream);
+
+/* Verification: the raw Philox4x32-10 words the step draws for noise block
+ * `block` (tag `tag`) at step `step` for sites site0 .. site0 + nsites - 1,
+ * written to out_dev[4 * s + k] (device, uint32).  Uses p->seed and
+ * p->replica.  Asynchronous. */
+flb_status flb_noise_words(const flb_params* p, uint64_t step, uint32_t block, uint32_t tag,
+                           uint64_t site0, uint64_t nsites, uint32_t* out_dev, void* stream);
+
+/* Verification: the library's constant tables for a lattice, written to host
+ * arrays: c[3 Q] (int, z = 0 in 2-D), w[Q], T[Q Q] (row-major, rows = modes),
+ * N[Q], cls[Q] (0 rho, 1 momentum, 2 bulk, 3 shear, 4 ghost); *q receives Q.
+ * Any output may be NULL.  Host only. */
+flb_status flb_lattice_tables(int32_t lattice, int32_t* q, int32_t* c, double* w, double* T,
+                              double* N, int32_t* cls);
+
+/* Record nsteps steps (same meaning as flb_step) into a HIP graph owned by the
+ * handle, replacing any previous one.  The step index is read from device
+ * memory, so every replay continues the noise sequence.  Nothing runs. */
+flb_status flb_graph_capture(flb_handle* h, int64_t nsteps, int32_t stats_stride, void* stream);
+
+/* Replay the captured graph once (advances the state by its nsteps). */
+flb_status flb_graph_launch(flb_handle* h, void* stream);
+
+/* Adjoint of one time step (reverse mode), for the gradient of a scalar loss.
+ * Given S_n = s_n (device, Q V reals, shifted populations: the state the step
+ * with index n starts from) and abar_np1 = dL/dS_{n+1} (device, Q V reals),
+ * writes abar_n = dL/dS_n (device, Q V reals; must not alias the inputs) and
+ * accumulates the parameter derivatives of this step, with the same noise
+ * (regenerated from Philox), into FP64 device accumulators.  If grad is not
+ * NULL the accumulators are finalized and ADDED to grad[4] on the host
+ * (order: d/d rate_shear, d/d kT, d/d rate_bulk, d/d rate_ghost) and cleared;
+ * that form synchronizes the stream.  FP32 and FP64, ideal and Landau force
+ * (eta = 0 or 1).  Returns FLB_ERR_INVALID_ARG if kT > 0 is required for the
+ * kT derivative and kT == 0 (the derivative is then reported as 0). */
+flb_status flb_adjoint_step(flb_handle* h, const void* s_n, const void* abar_np1, void* abar_n,
+                            double* grad, uint64_t n, void* stream);
+
+/* Adjoint seed of the loss of the final density: given S_N (device) and
+ * rhobar[V] = dL/drho_N (device, handle precision), where
+ * rho_N(x) = rho0 + sum_i delta S_{N,i}(x - c_i), writes abar_N = dL/dS_N
+ * (device, Q V reals): abar_{N,i}(y) = rhobar(y + c_i).  Asynchronous. */
+flb_status flb_adjoint_density_seed(flb_handle* h, const void* rhobar, void* abar_N,
+                                    void* stream);
+
+/* Density after streaming of an arbitrary state s (device, Q V reals):
+ * out[x] = sum_i delta s_i(x - c_i) (= rho(x) - rho0), handle precision. */
+flb_status flb_density(flb_handle* h, const void* s, void* out, void* stream);
+
+/* Release the handle (host memory and any captured graph). */
+flb_status flb_destroy(flb_handle* h);
+
+/* ---------------------------------------------------------------------------
+ * Batched replicas: R independent lattices (same lattice type, precision and
+ * physical parameters, each with its own box and seed) advanced by one
+ * persistent launch per step over a flattened tile table.  Replica r uses
+ * Philox key seeds[r] and counter word 3 = r; its populations occupy
+ * Q V_r consecutive reals starting at element offset Q * sum_{s<r} V_s of
+ * each population buffer (replica-major, then SoA within the replica).
+ * -------------------------------------------------------------------------*/
+typedef struct flb_batch flb_batch;
+
+/* dims[3 r + 0..2] = (nx, ny, nz) of replica r.  Host only. */
+flb_status flb_batch_query_sizes(const flb_params* base, int32_t nrep, const int32_t* dims,
+                                 size_t* pop_bytes, size_t* scratch_bytes, size_t* stats_bytes);
+
+/* Initial state w_i rho0 in every replica; ideal gas only (force_model 0). */
+flb_status flb_batch_init(const flb_params* base, int32_t nrep, const int32_t* dims,
+                          const uint64_t* seeds, void* f_a, void* f_b, void* scratch,
+                          void* stats, void* stream, flb_batch** out);
+
+flb_status flb_batch_step(flb_batch* b, int64_t nsteps, int32_t stats_stride, void* stream);
+
+/* Per-replica statistics: mode_sum[r Q + a], mode_sumsq[r Q + a]; synchronizes. */
+flb_status flb_batch_moments(flb_batch* b, double* mode_sum, double* mode_sumsq,
+                             int64_t* nsamples, void* stream);
+
+flb_status flb_batch_state(const flb_batch* b, void** cur, void** other, uint64_t* step);
+flb_status flb_batch_graph_capture(flb_batch* b, int64_t nsteps, int32_t stats_stride,
+                                   void* stream);
+flb_status flb_batch_graph_launch(flb_batch* b, void* stream);
+flb_status flb_batch_destroy(flb_batch* b);
+
+/* Launch shape in use and autotuning.  flb_autotune times every candidate
+ * launch shape of the handle's step kernel (block size, sites per thread;
+ * tile shape for the force kernel) on its own buffers without changing the
+ * state, keeps the fastest and returns its index and time per step (ms).
+ * Synchronizes the stream. */
+flb_status flb_autotune(flb_handle* h, int32_t repeats, int32_t* best, double* best_ms,
+                        void* stream);
+flb_status flb_set_launch(flb_handle* h, int32_t config);
+flb_status flb_launch_configs(const flb_handle* h, int32_t* count, int32_t* current);
+flb_status flb_batch_autotune(flb_batch* b, int32_t repeats, int32_t* best, double* best_ms,
+                              void* stream);
+
+/* Text of a status code; last error text (thread-local) with HIP details. */
+const char* flb_strerror(flb_status s);
+const char* flb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLB_H */

@@ -1,0 +1,519 @@
+// C ABI of the fluctuating LB library (declarations and contracts in
+// include/flb.h).  Host-side state only: the caller owns every device buffer.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/flb.h"
+#include "internal.h"
+#include "lattice.h"
+
+using namespace flb;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+flb_status fail(flb_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(FLB_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+constexpr double CS2 = 1.0 / 3.0;
+constexpr size_t ALIGN = 256;
+constexpr size_t SCRATCH_HEADER = 256;   // step counter for graph replays
+
+int lattice_q(int lat) { return lat == FLB_D2Q9 ? 9 : 19; }
+int lattice_d(int lat) { return lat == FLB_D2Q9 ? 2 : 3; }
+
+template <int LAT>
+void fill_amp(const flb_params& p, double (&amp)[15]) {
+    using L = Lattice<LAT>;
+    int k = 0;
+    for (int a = L::D + 1; a < L::Q; ++a, ++k) {
+        const double lam = L::cls[a] == CLS_BULK ? p.rate_bulk
+                           : L::cls[a] == CLS_SHEAR ? p.rate_shear
+                                                    : p.rate_ghost;
+        amp[k] = std::sqrt(p.kT * L::N[a] * lam * (2.0 - lam) / CS2);
+    }
+    for (; k < 15; ++k) amp[k] = 0.0;
+}
+
+flb_status validate(const flb_params* p) {
+    if (!p) return fail(FLB_ERR_INVALID_ARG, "params is NULL");
+    if (p->lattice != FLB_D2Q9 && p->lattice != FLB_D3Q19)
+        return fail(FLB_ERR_INVALID_ARG, "unknown lattice %d", p->lattice);
+    if (p->precision != FLB_FP32 && p->precision != FLB_FP64)
+        return fail(FLB_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+    if (p->force_model != FLB_IDEAL && p->force_model != FLB_LANDAU)
+        return fail(FLB_ERR_INVALID_ARG, "unknown force model %d", p->force_model);
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+        return fail(FLB_ERR_INVALID_ARG, "box %d x %d x %d", p->nx, p->ny, p->nz);
+    if (p->lattice == FLB_D2Q9 && p->nz != 1)
+        return fail(FLB_ERR_INVALID_ARG, "D2Q9 needs nz = 1 (got %d)", p->nz);
+    const double V = (double)p->nx * p->ny * p->nz;
+    if (V >= 2147483648.0) return fail(FLB_ERR_INVALID_ARG, "too many sites (%.0f)", V);
+    if ((double)lattice_q(p->lattice) * V * (p->precision ? 8.0 : 4.0) >= 1.0e15)
+        return fail(FLB_ERR_INVALID_ARG, "population buffer too large");
+    if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0))
+        return fail(FLB_ERR_INVALID_ARG, "rho0 = %g must be positive", p->rho0);
+    if (!(p->kT >= 0.0) || !(p->kT < p->rho0 * CS2))
+        return fail(FLB_ERR_INVALID_ARG, "kT = %g outside [0, rho0 cs2 = %g)", p->kT,
+                    p->rho0 * CS2);
+    const double r[3] = {p->rate_bulk, p->rate_shear, p->rate_ghost};
+    for (double x : r)
+        if (!(x > 0.0 && x < 2.0)) return fail(FLB_ERR_INVALID_ARG, "rate %g outside (0, 2)", x);
+    if (p->force_model == FLB_LANDAU) {
+        const double f[4] = {p->a, p->b, p->rho_c, p->kappa};
+        for (double x : f)
+            if (!std::isfinite(x)) return fail(FLB_ERR_INVALID_ARG, "non-finite force parameter");
+        if (p->kappa < 0.0) return fail(FLB_ERR_INVALID_ARG, "kappa = %g < 0", p->kappa);
+        if (p->eta != 0 && p->eta != 1) return fail(FLB_ERR_INVALID_ARG, "eta = %d", p->eta);
+    }
+    return FLB_OK;
+}
+
+StepSpec spec_of(const flb_params& p) {
+    StepSpec s{};
+    s.lat = p.lattice;
+    s.prec = p.precision;
+    s.force = p.force_model;
+    s.nx = p.nx;
+    s.ny = p.ny;
+    s.nz = p.nz;
+    s.rho0 = p.rho0;
+    s.lam_bulk = p.rate_bulk;
+    s.lam_shear = p.rate_shear;
+    s.lam_ghost = p.rate_ghost;
+    if (p.lattice == FLB_D2Q9) fill_amp<0>(p, s.amp);
+    else fill_amp<1>(p, s.amp);
+    s.noise_on = p.kT > 0.0;
+    s.noise_local = p.noise_rho_local ? 1 : 0;
+    s.key0 = (uint32_t)(p.seed & 0xffffffffu);
+    s.key1 = (uint32_t)(p.seed >> 32);
+    s.replica = p.replica;
+    s.a = p.a;
+    s.b = p.b;
+    s.rho_c = p.rho_c;
+    s.kappa = p.kappa;
+    s.eta = p.eta;
+    return s;
+}
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+uint32_t max_slots(const StepSpec& s) {
+    uint32_t m = 0;
+    for (int c = 0; c < n_configs(s.lat, s.force); ++c) m = std::max(m, config_blocks(s, c));
+    return m;
+}
+
+bool aligned(const void* p) { return p && ((uintptr_t)p % ALIGN) == 0; }
+
+}  // namespace
+
+struct flb_handle {
+    flb_params p;
+    StepSpec spec;
+    int q, d;
+    size_t V, real_bytes;
+    void* fa;
+    void* fb;
+    bool cur_a;
+    char* scratch;
+    double* stats;          // [slots][2q] partials, then [2q] finalized
+    uint32_t slots;
+    uint64_t step;
+    int64_t nsamples;
+    int cfg;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+    int64_t graph_steps, graph_samples;
+    // scratch regions
+    unsigned long long* step_dev;
+    void* drho;             // V reals (force model)
+    void* adj_work;
+    double* gpartial;       // adjoint gradient partials
+    uint32_t gslots;
+
+    void* cur() const { return cur_a ? fa : fb; }
+    void* other() const { return cur_a ? fb : fa; }
+};
+
+namespace {
+
+void scratch_layout(const StepSpec& s, size_t V, size_t rb, size_t* drho_off, size_t* adj_off,
+                    size_t* gpart_off, size_t* total) {
+    size_t off = SCRATCH_HEADER;
+    *drho_off = off;
+    off += align_up(V * rb);
+    *adj_off = off;
+    off += align_up(adjoint_work_bytes(s));
+    *gpart_off = off;
+    off += align_up(((size_t)adjoint_slots(s) + 1) * 4 * sizeof(double));
+    *total = off;
+}
+
+// One forward step of the handle: cur -> other, then swap.
+flb_status do_step(flb_handle* h, bool sample, const unsigned long long* step_dev,
+                   unsigned long long step_host, hipStream_t st) {
+    if (h->spec.force) HIP_TRY(launch_density(h->spec, h->cur(), h->drho, st));
+    HIP_TRY(launch_step(h->spec, h->cfg, h->cur(), h->other(), h->drho, step_dev, step_host,
+                        sample ? h->stats : nullptr, st));
+    h->cur_a = !h->cur_a;
+    return FLB_OK;
+}
+
+flb_status run_steps(flb_handle* h, int64_t nsteps, int32_t stride, bool graph_mode,
+                     hipStream_t st, int64_t* samples) {
+    int64_t ns = 0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const bool sample = stride > 0 && ((k + 1) % stride) == 0;
+        flb_status r;
+        if (graph_mode) r = do_step(h, sample, h->step_dev, (unsigned long long)k, st);
+        else r = do_step(h, sample, nullptr, (unsigned long long)(h->step + k), st);
+        if (r != FLB_OK) return r;
+        ns += sample;
+    }
+    if (graph_mode) HIP_TRY(launch_add_u64(h->step_dev, (unsigned long long)nsteps, st));
+    *samples = ns;
+    return FLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* flb_strerror(flb_status s) {
+    switch (s) {
+        case FLB_OK: return "ok";
+        case FLB_ERR_INVALID_ARG: return "invalid argument";
+        case FLB_ERR_HIP: return "HIP runtime error";
+        case FLB_ERR_NONFINITE: return "non-finite statistics";
+        case FLB_ERR_UNSUPPORTED: return "unsupported";
+        case FLB_ERR_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* flb_last_error(void) { return g_last_error.c_str(); }
+
+flb_status flb_lattice_tables(int32_t lattice, int32_t* q, int32_t* c, double* w, double* T,
+                              double* N, int32_t* cls) {
+    auto emit = [&](auto L) {
+        using LL = decltype(L);
+        if (q) *q = LL::Q;
+        for (int i = 0; i < LL::Q; ++i) {
+            if (c) {
+                c[3 * i + 0] = LL::cx[i];
+                c[3 * i + 1] = LL::cy[i];
+                c[3 * i + 2] = LL::cz[i];
+            }
+            if (w) w[i] = LL::w[i];
+            if (N) N[i] = LL::N[i];
+            if (cls) cls[i] = LL::cls[i];
+            if (T)
+                for (int j = 0; j < LL::Q; ++j) T[i * LL::Q + j] = LL::T[i][j];
+        }
+    };
+    if (lattice == FLB_D2Q9) emit(Lattice<0>{});
+    else if (lattice == FLB_D3Q19) emit(Lattice<1>{});
+    else return fail(FLB_ERR_INVALID_ARG, "unknown lattice %d", lattice);
+    return FLB_OK;
+}
+
+flb_status flb_query_sizes(const flb_params* p, size_t* pop_bytes, size_t* scratch_bytes,
+                           size_t* stats_bytes) {
+    flb_status r = validate(p);
+    if (r != FLB_OK) return r;
+    const StepSpec s = spec_of(*p);
+    const size_t V = (size_t)p->nx * p->ny * p->nz;
+    const size_t rb = p->precision == FLB_FP64 ? 8 : 4;
+    const int q = lattice_q(p->lattice);
+    size_t a, b, c, total;
+    scratch_layout(s, V, rb, &a, &b, &c, &total);
+    if (pop_bytes) *pop_bytes = align_up((size_t)q * V * rb);
+    if (scratch_bytes) *scratch_bytes = total;
+    if (stats_bytes) *stats_bytes = align_up(((size_t)max_slots(s) + 1) * 2 * q * sizeof(double));
+    return FLB_OK;
+}
+
+flb_status flb_init(const flb_params* p, void* f_a, void* f_b, void* scratch, void* stats,
+                    const double* drho_init, void* stream, flb_handle** out) {
+    if (!out) return fail(FLB_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    flb_status r = validate(p);
+    if (r != FLB_OK) return r;
+    if (!aligned(f_a) || !aligned(f_b) || !aligned(scratch) || !aligned(stats))
+        return fail(FLB_ERR_INVALID_ARG, "buffers must be non-NULL and 256-byte aligned");
+    if (f_a == f_b) return fail(FLB_ERR_INVALID_ARG, "f_a and f_b must differ");
+    hipStream_t st = (hipStream_t)stream;
+    flb_handle* h = new (std::nothrow) flb_handle();
+    if (!h) return fail(FLB_ERR_INVALID_ARG, "out of host memory");
+    h->p = *p;
+    h->spec = spec_of(*p);
+    h->q = lattice_q(p->lattice);
+    h->d = lattice_d(p->lattice);
+    h->V = (size_t)p->nx * p->ny * p->nz;
+    h->real_bytes = p->precision == FLB_FP64 ? 8 : 4;
+    h->fa = f_a;
+    h->fb = f_b;
+    h->cur_a = true;
+    h->scratch = (char*)scratch;
+    h->stats = (double*)stats;
+    h->slots = max_slots(h->spec);
+    h->step = p->step0;
+    h->nsamples = 0;
+    h->cfg = 0;
+    h->graph = nullptr;
+    h->gexec = nullptr;
+    size_t drho_off, adj_off, gp_off, total;
+    scratch_layout(h->spec, h->V, h->real_bytes, &drho_off, &adj_off, &gp_off, &total);
+    h->step_dev = (unsigned long long*)h->scratch;
+    h->drho = h->scratch + drho_off;
+    h->adj_work = h->scratch + adj_off;
+    h->gpartial = (double*)(h->scratch + gp_off);
+    h->gslots = adjoint_slots(h->spec);
+    const size_t stats_bytes = ((size_t)h->slots + 1) * 2 * h->q * sizeof(double);
+    hipError_t e = launch_init(h->spec, f_a, drho_init, st);
+    if (e == hipSuccess) e = launch_fill_zero(stats, stats_bytes, st);
+    if (e == hipSuccess) e = launch_fill_zero(h->scratch, total, st);
+    if (e == hipSuccess) e = launch_set_u64(h->step_dev, h->step, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(FLB_ERR_HIP, "flb_init: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return FLB_OK;
+}
+
+flb_status flb_step(flb_handle* h, int64_t nsteps, int32_t stats_stride, void* stream) {
+    if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
+    if (nsteps < 0 || stats_stride < 0)
+        return fail(FLB_ERR_INVALID_ARG, "nsteps %lld, stats_stride %d", (long long)nsteps,
+                    stats_stride);
+    int64_t ns = 0;
+    flb_status r = run_steps(h, nsteps, stats_stride, false, (hipStream_t)stream, &ns);
+    if (r != FLB_OK) return r;
+    h->step += (uint64_t)nsteps;
+    h->nsamples += ns;
+    // keep the device step counter in step with the host (graph replays read it)
+    HIP_TRY(launch_set_u64(h->step_dev, h->step, (hipStream_t)stream));
+    return FLB_OK;
+}
+
+flb_status flb_state(const flb_handle* h, void** cur, void** other, uint64_t* step) {
+    if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
+    if (cur) *cur = h->cur();
+    if (other) *other = h->other();
+    if (step) *step = h->step;
+    return FLB_OK;
+}
+
+flb_status flb_moments(flb_handle* h, double* mode_sum, double* mode_sumsq, int64_t* nsamples,
+                       void* stream) {
+    if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const int nv = 2 * h->q;
+    double* out = h->stats + (size_t)h->slots * nv;
+    HIP_TRY(launch_stats_finalize(h->stats, h->slots, nv, out, st));
+    std::vector<double> host(nv);
+    HIP_TRY(hipMemcpyAsync(host.data(), out, nv * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (mode_sum) std::memcpy(mode_sum, host.data(), h->q * sizeof(double));
+    if (mode_sumsq) std::memcpy(mode_sumsq, host.data() + h->q, h->q * sizeof(double));
+    if (nsamples) *nsamples = h->nsamples;
+    for (double v : host)
+        if (!std::isfinite(v)) return fail(FLB_ERR_NONFINITE, "statistics are not finite");
+    return FLB_OK;
+}
+
+flb_status flb_reset_stats(flb_handle* h, void* stream) {
+    if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
+    HIP_TRY(launch_fill_zero(h->stats, ((size_t)h->slots + 1) * 2 * h->q * sizeof(double),
+                             (hipStream_t)stream));
+    h->nsamples = 0;
+    return FLB_OK;
+}
+
+flb_status flb_fields(flb_handle* h, void* out, void* stream) {
+    if (!h || !out) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    if (h->spec.force) HIP_TRY(launch_density(h->spec, h->cur(), h->drho, st));
+    HIP_TRY(launch_fields(h->spec, h->cur(), h->drho, out, st));
+    return FLB_OK;
+}
+
+flb_status flb_density(flb_handle* h, const void* s, void* out, void* stream) {
+    if (!h || !s || !out) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    HIP_TRY(launch_density(h->spec, s, out, (hipStream_t)stream));
+    return FLB_OK;
+}
+
+flb_status flb_noise_words(const flb_params* p, uint64_t step, uint32_t block, uint32_t tag,
+                           uint64_t site0, uint64_t nsites, uint32_t* out_dev, void* stream) {
+    flb_status r = validate(p);
+    if (r != FLB_OK) return r;
+    if (!out_dev && nsites) return fail(FLB_ERR_INVALID_ARG, "out_dev is NULL");
+    if (block > 0xffffu || tag > 0xffffu) return fail(FLB_ERR_INVALID_ARG, "block/tag > 16 bit");
+    HIP_TRY(launch_noise_words(spec_of(*p), step, block, tag, site0, nsites, out_dev,
+                               (hipStream_t)stream));
+    return FLB_OK;
+}
+
+flb_status flb_graph_capture(flb_handle* h, int64_t nsteps, int32_t stats_stride, void* stream) {
+    if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
+    if (nsteps <= 0 || stats_stride < 0)
+        return fail(FLB_ERR_INVALID_ARG, "nsteps %lld", (long long)nsteps);
+    if (nsteps % 2 != 0)
+        return fail(FLB_ERR_INVALID_ARG, "graph step count must be even (buffers alternate)");
+    hipStream_t st = (hipStream_t)stream;
+    if (!st) return fail(FLB_ERR_INVALID_ARG, "graph capture needs a non-null stream");
+    if (h->gexec) {
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    if (h->graph) {
+        (void)hipGraphDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    const bool cur_a = h->cur_a;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int64_t ns = 0;
+    flb_status r = run_steps(h, nsteps, stats_stride, true, st, &ns);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    h->cur_a = cur_a;   // nothing ran
+    if (r != FLB_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return fail(FLB_ERR_HIP, "capture: %s", hipGetErrorString(e));
+    h->graph = g;
+    HIP_TRY(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+    h->graph_steps = nsteps;
+    h->graph_samples = ns;
+    return FLB_OK;
+}
+
+flb_status flb_graph_launch(flb_handle* h, void* stream) {
+    if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
+    if (!h->gexec) return fail(FLB_ERR_STATE, "no graph captured");
+    HIP_TRY(hipGraphLaunch(h->gexec, (hipStream_t)stream));
+    h->step += (uint64_t)h->graph_steps;
+    h->nsamples += h->graph_samples;
+    // graph_steps is even, so the current buffer is unchanged
+    return FLB_OK;
+}
+
+flb_status flb_autotune(flb_handle* h, int32_t repeats, int32_t* best, double* best_ms,
+                        void* stream) {
+    if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
+    if (repeats < 1) repeats = 1;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int ncfg = n_configs(h->spec.lat, h->spec.force);
+    int bi = h->cfg;
+    float bt = 1e30f;
+    // each trial writes cur -> other without swapping or counting: the state is unchanged
+    if (h->spec.force) HIP_TRY(launch_density(h->spec, h->cur(), h->drho, st));
+    for (int c = 0; c < ncfg; ++c) {
+        HIP_TRY(launch_step(h->spec, c, h->cur(), h->other(), h->drho, nullptr, h->step, nullptr,
+                            st));
+        HIP_TRY(hipEventRecord(e0, st));
+        for (int r = 0; r < repeats; ++r)
+            HIP_TRY(launch_step(h->spec, c, h->cur(), h->other(), h->drho, nullptr, h->step,
+                                nullptr, st));
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms /= repeats;
+        if (ms < bt) {
+            bt = ms;
+            bi = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->cfg = bi;
+    if (best) *best = bi;
+    if (best_ms) *best_ms = bt;
+    return FLB_OK;
+}
+
+flb_status flb_set_launch(flb_handle* h, int32_t config) {
+    if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
+    if (config < 0 || config >= n_configs(h->spec.lat, h->spec.force))
+        return fail(FLB_ERR_INVALID_ARG, "launch config %d out of range", config);
+    h->cfg = config;
+    return FLB_OK;
+}
+
+flb_status flb_launch_configs(const flb_handle* h, int32_t* count, int32_t* current) {
+    if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
+    if (count) *count = n_configs(h->spec.lat, h->spec.force);
+    if (current) *current = h->cfg;
+    return FLB_OK;
+}
+
+flb_status flb_adjoint_density_seed(flb_handle* h, const void* rhobar, void* abar_N,
+                                    void* stream) {
+    if (!h || !rhobar || !abar_N) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    HIP_TRY(launch_adjoint_seed(h->spec, rhobar, abar_N, (hipStream_t)stream));
+    return FLB_OK;
+}
+
+flb_status flb_adjoint_step(flb_handle* h, const void* s_n, const void* abar_np1, void* abar_n,
+                            double* grad, uint64_t n, void* stream) {
+    if (!h || !s_n || !abar_np1 || !abar_n) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    if (abar_n == abar_np1 || abar_n == s_n)
+        return fail(FLB_ERR_INVALID_ARG, "abar_n must not alias the inputs");
+    hipStream_t st = (hipStream_t)stream;
+    if (h->spec.force) HIP_TRY(launch_density(h->spec, s_n, h->drho, st));
+    uint32_t ns = 0;
+    HIP_TRY(launch_adjoint_step(h->spec, s_n, h->drho, abar_np1, abar_n, h->adj_work,
+                                (unsigned long long)n, h->gpartial, &ns, st));
+    if (grad) {
+        double* out = h->gpartial + (size_t)h->gslots * 4;
+        HIP_TRY(launch_stats_finalize(h->gpartial, h->gslots, 4, out, st));
+        double host[4];
+        HIP_TRY(hipMemcpyAsync(host, out, sizeof host, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int k = 0; k < 4; ++k) grad[k] += host[k];
+        HIP_TRY(launch_fill_zero(h->gpartial, (size_t)h->gslots * 4 * sizeof(double), st));
+    }
+    return FLB_OK;
+}
+
+flb_status flb_destroy(flb_handle* h) {
+    if (!h) return FLB_OK;
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    delete h;
+    return FLB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,196 @@
+// Per-site collision of the fluctuating LB step in moment space (device side).
+//
+// Works on shifted populations delta f_i = f_i - w_i rho0.  Because
+// sum_i T_ai w_i = N_a delta_a0, the moments of delta f equal those of f except
+// m_0, which becomes delta rho = rho - rho0; the inverse transform maps the
+// shifted moments back to shifted populations (Sec. III eqs. moments,
+// moments-inv).
+//
+// The update is Sec. V eq. lbe-mom:
+//   m*_a = m_a - lam_a (m_a - m^eq_a) + (1 - lam_a/2) m^F_a + sigma_a z_a,
+// lam_a = 0 on rho and j (so rho* = rho and j* = j + F), with the equilibrium
+// moments of Sec. III eq. feq (zero on ghosts for the w-weighted basis), the
+// forcing moments {0, F, uF + Fu, 0} and u = (j + F/2)/rho (Sec. V
+// eq. lbe-moments).  sigma_a^2 = rho kT N_a lam_a (2 - lam_a)/cs2 (Sec. V
+// eq. noise-lbe), with rho the local density or rho0.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice.h"
+#include "philox.h"
+
+namespace flb {
+
+constexpr int QMAX = 19;
+constexpr int KMAX = 15;
+
+// Physical parameters of the collision, uniform over a launch.
+template <typename Real>
+struct CollideParams {
+    Real rho0;
+    Real lam_bulk, lam_shear, lam_ghost;
+    Real amp[KMAX];     // sqrt(kT N_a lam_a (2 - lam_a) / cs2), non-conserved modes in order
+    int32_t noise_on;   // kT > 0
+    int32_t noise_local;
+    uint32_t key0, key1, replica;
+};
+
+template <int LAT, typename Real>
+struct Moments {
+    using L = Lattice<LAT>;
+    static constexpr int Q = L::Q;
+    static constexpr int NP = L::NP;
+
+    // m_a = sum_i T_ai f_i via opposite-pair sums and differences.
+    static __device__ __forceinline__ void forward(const Real (&f)[Q], Real (&m)[Q]) {
+        Real s[NP], d[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            s[p] = f[L::pair[p][0]] + f[L::pair[p][1]];
+            d[p] = f[L::pair[p][0]] - f[L::pair[p][1]];
+        }
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            Real acc = Real(0);
+            if (!L::odd[a] && L::T[a][0] != 0) acc = Real(L::T[a][0]) * f[0];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                constexpr int dummy = 0;
+                (void)dummy;
+                const int t = L::T[a][L::pair[p][0]];
+                if (t == 0) continue;
+                const Real v = L::odd[a] ? d[p] : s[p];
+                if (t == 1) acc += v;
+                else if (t == -1) acc -= v;
+                else acc += Real(t) * v;
+            }
+            m[a] = acc;
+        }
+    }
+
+    // f_i = w_i sum_a T_ai m_a / N_a, pairwise: f_i = w (E + O), f_ibar = w (E - O).
+    static __device__ __forceinline__ void inverse(const Real (&m)[Q], Real (&f)[Q]) {
+        Real mt[Q];
+#pragma unroll
+        for (int a = 0; a < Q; ++a) mt[a] = m[a] * Real(1.0 / L::N[a]);
+        {
+            Real acc = Real(0);
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                const int t = L::T[a][0];
+                if (t == 0) continue;
+                if (t == 1) acc += mt[a];
+                else if (t == -1) acc -= mt[a];
+                else acc += Real(t) * mt[a];
+            }
+            f[0] = Real(L::w[0]) * acc;
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int i = L::pair[p][0], j = L::pair[p][1];
+            Real E = Real(0), O = Real(0);
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                const int t = L::T[a][i];
+                if (t == 0) continue;
+                if (L::odd[a]) {
+                    if (t == 1) O += mt[a];
+                    else if (t == -1) O -= mt[a];
+                    else O += Real(t) * mt[a];
+                } else {
+                    if (t == 1) E += mt[a];
+                    else if (t == -1) E -= mt[a];
+                    else E += Real(t) * mt[a];
+                }
+            }
+            f[i] = Real(L::w[i]) * (E + O);
+            f[j] = Real(L::w[i]) * (E - O);
+        }
+    }
+};
+
+// Equilibrium (m^eq) and forcing (m^F) moments of the stress modes.
+// Row a = sum Gamma_ab c_a c_b + gamma gives m^eq = Gamma:(rho cs2 I + rho u u) + gamma rho
+// and m^F = Gamma:(uF + Fu).
+template <int LAT, typename Real> struct Stress;
+
+template <typename Real> struct Stress<0, Real> {
+    static constexpr int first = 3, count = 3;
+    static __device__ __forceinline__ void eval(Real rho, const Real (&u)[2], const Real (&F)[2],
+                                                Real (&meq)[3], Real (&mF)[3]) {
+        const Real uxx = u[0] * u[0], uyy = u[1] * u[1];
+        meq[0] = Real(3) * rho * (uxx + uyy);          // e = 3c^2 - 2
+        meq[1] = rho * (uxx - uyy);                    // p_ww = c_x^2 - c_y^2
+        meq[2] = rho * u[0] * u[1];                    // p_xy = c_x c_y
+        const Real fxx = u[0] * F[0], fyy = u[1] * F[1];
+        mF[0] = Real(6) * (fxx + fyy);
+        mF[1] = Real(2) * (fxx - fyy);
+        mF[2] = u[0] * F[1] + u[1] * F[0];
+    }
+};
+
+template <typename Real> struct Stress<1, Real> {
+    static constexpr int first = 4, count = 6;
+    static __device__ __forceinline__ void eval(Real rho, const Real (&u)[3], const Real (&F)[3],
+                                                Real (&meq)[6], Real (&mF)[6]) {
+        const Real uxx = u[0] * u[0], uyy = u[1] * u[1], uzz = u[2] * u[2];
+        const Real usq = uxx + uyy + uzz;
+        meq[0] = rho * usq;                            // c^2 - 1
+        meq[1] = rho * (Real(3) * uxx - usq);          // 3c_x^2 - c^2
+        meq[2] = rho * (uyy - uzz);                    // c_y^2 - c_z^2
+        meq[3] = rho * u[0] * u[1];                    // c_x c_y
+        meq[4] = rho * u[1] * u[2];                    // c_y c_z
+        meq[5] = rho * u[2] * u[0];                    // c_z c_x
+        const Real fxx = u[0] * F[0], fyy = u[1] * F[1], fzz = u[2] * F[2];
+        const Real uF = fxx + fyy + fzz;
+        mF[0] = Real(2) * uF;
+        mF[1] = Real(2) * (Real(3) * fxx - uF);
+        mF[2] = Real(2) * (fyy - fzz);
+        mF[3] = u[0] * F[1] + u[1] * F[0];
+        mF[4] = u[1] * F[2] + u[2] * F[1];
+        mF[5] = u[2] * F[0] + u[0] * F[2];
+    }
+};
+
+// Collide the moments of one site in place.  m[0] is delta rho on entry and
+// exit; F is the force density (zero for the ideal gas); z the site's normals.
+template <int LAT, typename Real, bool FORCE>
+__device__ __forceinline__ void collide_moments(Real (&m)[Lattice<LAT>::Q],
+                                                const Real (&F)[Lattice<LAT>::D],
+                                                const Real* z, const CollideParams<Real>& P) {
+    using L = Lattice<LAT>;
+    using S = Stress<LAT, Real>;
+    constexpr int D = L::D;
+    const Real rho = P.rho0 + m[0];
+    const Real inv_rho = Real(1) / rho;
+    Real u[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) u[a] = (FORCE ? (m[1 + a] + Real(0.5) * F[a]) : m[1 + a]) * inv_rho;
+    Real meq[S::count], mF[S::count];
+    S::eval(rho, u, F, meq, mF);
+    // conserved: rho unchanged, j* = j + F
+    if (FORCE) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) m[1 + a] += F[a];
+    }
+    // stress modes
+#pragma unroll
+    for (int k = 0; k < S::count; ++k) {
+        const int a = S::first + k;
+        const Real lam = (L::cls[a] == CLS_BULK) ? P.lam_bulk : P.lam_shear;
+        Real v = m[a] - lam * (m[a] - meq[k]);
+        if (FORCE) v += (Real(1) - Real(0.5) * lam) * mF[k];
+        m[a] = v;
+    }
+    // ghost modes: m^eq = m^F = 0
+#pragma unroll
+    for (int a = S::first + S::count; a < L::Q; ++a) m[a] = m[a] - P.lam_ghost * m[a];
+    if (P.noise_on) {
+        const Real sr = P.noise_local ? sqrt(rho) : sqrt(P.rho0);
+#pragma unroll
+        for (int k = 0; k < L::K; ++k) m[D + 1 + k] += sr * P.amp[k] * z[k];
+    }
+}
+
+}  // namespace flb

@@ -1,0 +1,65 @@
+// Host-side interface between the C ABI (api.hip) and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace flb {
+
+// Launch shapes of the step kernels: tile TX x TY x TZ sites, one site per thread.
+struct TileShape {
+    int tx, ty, tz;
+};
+
+// Candidate tiles (the autotuner picks one per handle).
+constexpr int N_IDEAL_CFG = 4;
+constexpr TileShape IDEAL_CFG[N_IDEAL_CFG] = {{64, 4, 1}, {128, 2, 1}, {256, 1, 1}, {32, 8, 1}};
+constexpr int N_FORCE3_CFG = 3;
+constexpr TileShape FORCE3_CFG[N_FORCE3_CFG] = {{32, 4, 2}, {16, 4, 4}, {64, 2, 2}};
+constexpr int N_FORCE2_CFG = 3;
+constexpr TileShape FORCE2_CFG[N_FORCE2_CFG] = {{64, 4, 1}, {32, 8, 1}, {128, 2, 1}};
+
+// Everything a forward launch needs, in FP64 on the host (converted per precision).
+struct StepSpec {
+    int lat;           // 0 D2Q9, 1 D3Q19
+    int prec;          // 0 FP32, 1 FP64
+    int force;         // 0 ideal, 1 Landau
+    int nx, ny, nz;
+    double rho0, lam_bulk, lam_shear, lam_ghost;
+    double amp[15];
+    int noise_on, noise_local;
+    uint32_t key0, key1, replica;
+    double a, b, rho_c, kappa, eta;
+};
+
+int n_configs(int lat, int force);
+TileShape config_shape(int lat, int force, int cfg);
+uint32_t config_blocks(const StepSpec& s, int cfg);
+
+hipError_t launch_init(const StepSpec& s, void* f, const double* drho, hipStream_t st);
+hipError_t launch_density(const StepSpec& s, const void* fin, void* drho_out, hipStream_t st);
+// One step fin -> fout.  drho: density field of fin after streaming (force only).
+// step_dev/step_host: step index (device counter + offset).  partial: stats slots or null.
+hipError_t launch_step(const StepSpec& s, int cfg, const void* fin, void* fout, const void* drho,
+                       const unsigned long long* step_dev, unsigned long long step_host,
+                       double* partial, hipStream_t st);
+hipError_t launch_fields(const StepSpec& s, const void* fin, const void* drho, void* out,
+                         hipStream_t st);
+hipError_t launch_stats_finalize(const double* partial, uint32_t nslots, int nvals, double* out,
+                                 hipStream_t st);
+hipError_t launch_noise_words(const StepSpec& s, unsigned long long step, uint32_t block,
+                              uint32_t tag, unsigned long long site0, unsigned long long nsites,
+                              uint32_t* out, hipStream_t st);
+hipError_t launch_add_u64(unsigned long long* ctr, unsigned long long inc, hipStream_t st);
+hipError_t launch_set_u64(unsigned long long* ctr, unsigned long long v, hipStream_t st);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+
+// Adjoint launchers (adjoint.hip).
+hipError_t launch_adjoint_seed(const StepSpec& s, const void* rhobar, void* abar, hipStream_t st);
+hipError_t launch_adjoint_step(const StepSpec& s, const void* s_n, const void* drho,
+                               const void* abar_np1, void* abar_n, void* work,
+                               unsigned long long step, double* gpartial, uint32_t* nslots_out,
+                               hipStream_t st);
+size_t adjoint_work_bytes(const StepSpec& s);
+uint32_t adjoint_slots(const StepSpec& s);
+
+}  // namespace flb

@@ -1,0 +1,527 @@
+// Forward kernels of the fluctuating LB step for gfx950 and their launchers.
+//
+// Layout: shifted populations delta f in structure-of-arrays order
+// f[i * V + site], site = x + nx (y + ny z).  A launch covers the box with
+// tiles of TX x TY x TZ sites, one site per thread, so that a wavefront reads
+// 64 (or more) consecutive x-sites of every population plane: every load and
+// store of the pull step is a coalesced row segment (the +-x neighbours are
+// the same segment shifted by one element).  The order of tiles is remapped so
+// that each XCD walks a contiguous slab of the box (shared L2 for the y/z
+// neighbour rows).
+//
+// Force model: the density after streaming is produced by k_density; the
+// step kernel stages a tile of it with a two-site halo in LDS, evaluates the
+// chemical potential on the tile plus a one-site halo in LDS, and forms the
+// force at each site from those (no extra HBM pass for mu).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "step.h"
+
+namespace flb {
+
+// ------------------------------------------------------------------ helpers
+
+template <int LAT>
+__device__ __forceinline__ uint32_t site_index(int x, int y, int z, const Geom& g) {
+    return (uint32_t)((z * g.ny + y) * g.nx + x);
+}
+
+// f_i(x) = S_i(x - c_i), periodic.
+template <int LAT, typename Real>
+__device__ __forceinline__ void pull(const Real* __restrict__ fin, int x, int y, int z,
+                                     const Geom& g, Real (&f)[Lattice<LAT>::Q]) {
+    using L = Lattice<LAT>;
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int sx = L::cx[i] == 0 ? x : (L::cx[i] > 0 ? xm : xp);
+        const int sy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? ym : yp);
+        const int sz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zm : zp);
+        f[i] = fin[(size_t)i * g.V + (uint32_t)((sz * g.ny + sy) * g.nx + sx)];
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ Real wave_sum(Real v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Reduce NV doubles over the block in a fixed order and add them to slot[0..NV).
+template <int NV, int NT>
+__device__ __forceinline__ void block_accumulate(double (&v)[NV], double* __restrict__ slot,
+                                                 double* lds) {
+    constexpr int NW = (NT + 63) / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double s = wave_sum(v[k]);
+        if (lane == 0) lds[wave * NV + k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double acc = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) acc += lds[w * NV + threadIdx.x];
+        slot[threadIdx.x] += acc;
+    }
+}
+
+template <int LAT, int TX, int TY, int TZ>
+__device__ __forceinline__ void tile_origin(const Geom& g, int& x0, int& y0, int& z0) {
+    const uint32_t b = xcd_remap(blockIdx.x, g.nblocks);
+    const uint32_t bx = b % (uint32_t)g.nbx;
+    const uint32_t r = b / (uint32_t)g.nbx;
+    const uint32_t by = r % (uint32_t)g.nby;
+    const uint32_t bz = r / (uint32_t)g.nby;
+    x0 = (int)bx * TX;
+    y0 = (int)by * TY;
+    z0 = (int)bz * TZ;
+}
+
+__device__ __forceinline__ int wrap_any(int v, int n) {
+    while (v < 0) v += n;
+    while (v >= n) v -= n;
+    return v;
+}
+
+// ------------------------------------------------------------------ force tile
+
+// Chemical potential mu = psi'(rho) - kappa lap_h rho on the tile plus a
+// one-site halo, from the density on the tile plus a two-site halo, both in
+// LDS; then F = -rho grad_h mu + eta grad_h(cs2 rho) at a site of the tile.
+template <int LAT, typename Real, int TX, int TY, int TZ>
+struct ForceTile {
+    using L = Lattice<LAT>;
+    static constexpr int D = L::D;
+    static constexpr int HZ = (LAT == 0) ? 0 : 1;
+    static constexpr int RX = TX + 4, RY = TY + 4, RZ = TZ + 4 * HZ;
+    static constexpr int MX = TX + 2, MY = TY + 2, MZ = TZ + 2 * HZ;
+    static constexpr int NR = RX * RY * RZ, NM = MX * MY * MZ;
+    static constexpr int NT = TX * TY * TZ;
+
+    static __device__ __forceinline__ void stage(const Real* __restrict__ drho, const Geom& g,
+                                                 const ForceParams<Real>& fp, int x0, int y0,
+                                                 int z0, Real* rs, Real* ms) {
+        const int tid = threadIdx.x;
+        for (int l = tid; l < NR; l += NT) {
+            const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
+            const int gx = wrap_any(x0 + lx - 2, g.nx);
+            const int gy = wrap_any(y0 + ly - 2, g.ny);
+            const int gz = wrap_any(z0 + lz - 2 * HZ, g.nz);
+            rs[l] = drho[(uint32_t)((gz * g.ny + gy) * g.nx + gx)];
+        }
+        __syncthreads();
+        for (int l = tid; l < NM; l += NT) {
+            const int mx = l % MX, my = (l / MX) % MY, mz = l / (MX * MY);
+            const int c = ((mz + HZ) * RY + (my + 1)) * RX + (mx + 1);
+            const Real rc = rs[c];
+            Real lap = Real(0);
+#pragma unroll
+            for (int i = 1; i < L::Q; ++i) {
+                const int n = c + (L::cz[i] * RY + L::cy[i]) * RX + L::cx[i];
+                lap += Real(L::w[i]) * (rs[n] - rc);
+            }
+            lap *= Real(6);   // 2 / cs2
+            const Real d = rc + fp.shift;
+            ms[l] = Real(2) * fp.a * d + Real(4) * fp.b * d * d * d - fp.kappa * lap;
+        }
+        __syncthreads();
+    }
+
+    // Force at tile-local site (lx, ly, lz); also returns delta rho there.
+    static __device__ __forceinline__ void force(const Real* rs, const Real* ms,
+                                                 const ForceParams<Real>& fp, Real rho0, int lx,
+                                                 int ly, int lz, Real (&F)[D]) {
+        const int cm = ((lz + HZ) * MY + (ly + 1)) * MX + (lx + 1);
+        const int cr = ((lz + 2 * HZ) * RY + (ly + 2)) * RX + (lx + 2);
+        Real gm[D], gr[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) gm[a] = gr[a] = Real(0);
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            const Real mu = ms[cm + (L::cz[i] * MY + L::cy[i]) * MX + L::cx[i]];
+            const Real rn = rs[cr + (L::cz[i] * RY + L::cy[i]) * RX + L::cx[i]];
+            const int c3[3] = {L::cx[i], L::cy[i], L::cz[i]};
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                if (c3[a] == 0) continue;
+                const Real wc = Real(L::w[i] * c3[a]);
+                gm[a] += wc * mu;
+                gr[a] += wc * rn;
+            }
+        }
+        const Real rho = rho0 + rs[cr];
+#pragma unroll
+        for (int a = 0; a < D; ++a) F[a] = -rho * Real(3) * gm[a] + fp.eta * gr[a];
+    }
+};
+
+// ------------------------------------------------------------------ kernels
+
+template <int LAT, typename Real>
+__global__ void k_init(Real* __restrict__ f, const double* __restrict__ drho, uint32_t V) {
+    using L = Lattice<LAT>;
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    const double d = drho ? drho[s] : 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) f[(size_t)i * V + s] = (Real)(L::w[i] * d);
+}
+
+// delta rho(x) = sum_i delta S_i(x - c_i)
+template <int LAT, typename Real>
+__global__ void k_density(const Real* __restrict__ fin, Real* __restrict__ out, Geom g) {
+    using L = Lattice<LAT>;
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V) return;
+    const int x = (int)(s % (uint32_t)g.nx);
+    const uint32_t r = s / (uint32_t)g.nx;
+    const int y = (int)(r % (uint32_t)g.ny), z = (int)(r / (uint32_t)g.ny);
+    Real f[L::Q];
+    pull<LAT, Real>(fin, x, y, z, g, f);
+    Real acc = Real(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) acc += f[i];
+    out[s] = acc;
+}
+
+template <int LAT, typename Real, bool FORCE, bool STATS, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX* TY* TZ) void k_step(
+    const Real* __restrict__ fin, Real* __restrict__ fout, const Real* __restrict__ drho, Geom g,
+    CollideParams<Real> P, ForceParams<Real> fp, StepIndex st, double* __restrict__ partial) {
+    using L = Lattice<LAT>;
+    using M = Moments<LAT, Real>;
+    using FT = ForceTile<LAT, Real, TX, TY, TZ>;
+    constexpr int Q = L::Q, D = L::D, NT = TX * TY * TZ;
+    constexpr int LDS_F = FORCE ? (FT::NR + FT::NM) : 1;
+    constexpr int LDS_S = STATS ? ((NT + 63) / 64) * 2 * Q : 1;
+    __shared__ Real lds_force[LDS_F];
+    __shared__ double lds_stats[LDS_S];
+
+    int x0, y0, z0;
+    tile_origin<LAT, TX, TY, TZ>(g, x0, y0, z0);
+    const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
+    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+    const bool inside = x < g.nx && y < g.ny && z < g.nz;
+
+    Real F[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) F[a] = Real(0);
+    if constexpr (FORCE) {
+        FT::stage(drho, g, fp, x0, y0, z0, lds_force, lds_force + FT::NR);
+        if (inside) FT::force(lds_force, lds_force + FT::NR, fp, P.rho0, tx, ty, tz, F);
+    }
+
+    double v[2 * Q];
+    if (inside) {
+        Real f[Q], m[Q];
+        pull<LAT, Real>(fin, x, y, z, g, f);
+        M::forward(f, m);
+        if constexpr (STATS) {
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                const double ma = (double)m[a];
+                v[a] = ma;
+                v[Q + a] = ma * ma;
+            }
+        }
+        const uint32_t site = site_index<LAT>(x, y, z, g);
+        Real zn[4 * L::NBLK];
+        if (P.noise_on)
+            site_normals<L::NBLK, Real>(site, st.get(), 0u, P.replica, P.key0, P.key1, zn);
+        collide_moments<LAT, Real, FORCE>(m, F, zn, P);
+        M::inverse(m, f);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fout[(size_t)i * g.V + site] = f[i];
+    } else if constexpr (STATS) {
+#pragma unroll
+        for (int k = 0; k < 2 * Q; ++k) v[k] = 0.0;
+    }
+    if constexpr (STATS) {
+        const uint32_t b = xcd_remap(blockIdx.x, g.nblocks);
+        block_accumulate<2 * Q, NT>(v, partial + (size_t)b * 2 * Q, lds_stats);
+    }
+}
+
+// rho and rho u = sum c f + F/2 after streaming of state fin.
+template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX* TY* TZ) void k_fields(const Real* __restrict__ fin,
+                                                        const Real* __restrict__ drho,
+                                                        Real* __restrict__ out, Geom g, Real rho0,
+                                                        ForceParams<Real> fp) {
+    using L = Lattice<LAT>;
+    using FT = ForceTile<LAT, Real, TX, TY, TZ>;
+    constexpr int Q = L::Q, D = L::D;
+    constexpr int LDS_F = FORCE ? (FT::NR + FT::NM) : 1;
+    __shared__ Real lds_force[LDS_F];
+    int x0, y0, z0;
+    tile_origin<LAT, TX, TY, TZ>(g, x0, y0, z0);
+    const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
+    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+    const bool inside = x < g.nx && y < g.ny && z < g.nz;
+    Real F[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) F[a] = Real(0);
+    if constexpr (FORCE) {
+        FT::stage(drho, g, fp, x0, y0, z0, lds_force, lds_force + FT::NR);
+        if (inside) FT::force(lds_force, lds_force + FT::NR, fp, rho0, tx, ty, tz, F);
+    }
+    if (!inside) return;
+    Real f[Q];
+    pull<LAT, Real>(fin, x, y, z, g, f);
+    Real rho = Real(0), j[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) j[a] = Real(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rho += f[i];
+        const int c3[3] = {L::cx[i], L::cy[i], L::cz[i]};
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (c3[a] == 1) j[a] += f[i];
+            else if (c3[a] == -1) j[a] -= f[i];
+        }
+    }
+    const uint32_t s = site_index<LAT>(x, y, z, g);
+    out[s] = rho0 + rho;
+#pragma unroll
+    for (int a = 0; a < D; ++a) out[(size_t)(1 + a) * g.V + s] = j[a] + Real(0.5) * F[a];
+}
+
+// Fixed-order reduction of the statistics slots: out[k] = sum_b partial[b][k].
+__global__ void k_stats_finalize(const double* __restrict__ partial, uint32_t nslots, int nvals,
+                                 double* __restrict__ out) {
+    __shared__ double red[256];
+    const int k = blockIdx.x;
+    double acc = 0.0;
+    for (uint32_t b = threadIdx.x; b < nslots; b += 256) acc += partial[(size_t)b * nvals + k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = red[0];
+}
+
+__global__ void k_noise_words(unsigned long long site0, unsigned long long nsites, uint32_t step,
+                              uint32_t word2, uint32_t replica, uint32_t k0, uint32_t k1,
+                              uint32_t* __restrict__ out) {
+    const unsigned long long s = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsites) return;
+    const Philox4 r = philox4x32_10((uint32_t)(site0 + s), step, word2, replica, k0, k1);
+    out[4 * s + 0] = r.x;
+    out[4 * s + 1] = r.y;
+    out[4 * s + 2] = r.z;
+    out[4 * s + 3] = r.w;
+}
+
+__global__ void k_add_u64(unsigned long long* ctr, unsigned long long inc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr += inc;
+}
+
+__global__ void k_set_u64(unsigned long long* ctr, unsigned long long v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = v;
+}
+
+__global__ void k_fill_zero(uint32_t* __restrict__ p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// ------------------------------------------------------------------ launchers
+
+int n_configs(int lat, int force) {
+    if (!force) return N_IDEAL_CFG;
+    return lat == 1 ? N_FORCE3_CFG : N_FORCE2_CFG;
+}
+
+TileShape config_shape(int lat, int force, int cfg) {
+    if (!force) return IDEAL_CFG[cfg];
+    return lat == 1 ? FORCE3_CFG[cfg] : FORCE2_CFG[cfg];
+}
+
+static Geom make_geom(const StepSpec& s, TileShape t) {
+    Geom g;
+    g.nx = s.nx;
+    g.ny = s.ny;
+    g.nz = s.nz;
+    g.nbx = (s.nx + t.tx - 1) / t.tx;
+    g.nby = (s.ny + t.ty - 1) / t.ty;
+    g.nbz = (s.nz + t.tz - 1) / t.tz;
+    g.nblocks = (uint32_t)g.nbx * g.nby * g.nbz;
+    g.V = (uint32_t)s.nx * s.ny * s.nz;
+    return g;
+}
+
+uint32_t config_blocks(const StepSpec& s, int cfg) {
+    return make_geom(s, config_shape(s.lat, s.force, cfg)).nblocks;
+}
+
+template <typename Real>
+static CollideParams<Real> collide_params(const StepSpec& s) {
+    CollideParams<Real> P;
+    P.rho0 = (Real)s.rho0;
+    P.lam_bulk = (Real)s.lam_bulk;
+    P.lam_shear = (Real)s.lam_shear;
+    P.lam_ghost = (Real)s.lam_ghost;
+    for (int k = 0; k < KMAX; ++k) P.amp[k] = (Real)s.amp[k];
+    P.noise_on = s.noise_on;
+    P.noise_local = s.noise_local;
+    P.key0 = s.key0;
+    P.key1 = s.key1;
+    P.replica = s.replica;
+    return P;
+}
+
+template <typename Real>
+static ForceParams<Real> force_params(const StepSpec& s) {
+    ForceParams<Real> f;
+    f.a = (Real)s.a;
+    f.b = (Real)s.b;
+    f.shift = (Real)(s.rho0 - s.rho_c);
+    f.kappa = (Real)s.kappa;
+    f.eta = (Real)s.eta;
+    return f;
+}
+
+hipError_t launch_init(const StepSpec& s, void* f, const double* drho, hipStream_t st) {
+    const uint32_t V = (uint32_t)s.nx * s.ny * s.nz;
+    const dim3 grid((V + 255) / 256), block(256);
+    if (s.lat == 0 && s.prec == 0) hipLaunchKernelGGL((k_init<0, float>), grid, block, 0, st, (float*)f, drho, V);
+    else if (s.lat == 0) hipLaunchKernelGGL((k_init<0, double>), grid, block, 0, st, (double*)f, drho, V);
+    else if (s.prec == 0) hipLaunchKernelGGL((k_init<1, float>), grid, block, 0, st, (float*)f, drho, V);
+    else hipLaunchKernelGGL((k_init<1, double>), grid, block, 0, st, (double*)f, drho, V);
+    return hipGetLastError();
+}
+
+hipError_t launch_density(const StepSpec& s, const void* fin, void* out, hipStream_t st) {
+    const Geom g = make_geom(s, TileShape{1, 1, 1});
+    const dim3 grid((g.V + 255) / 256), block(256);
+    if (s.lat == 0 && s.prec == 0) hipLaunchKernelGGL((k_density<0, float>), grid, block, 0, st, (const float*)fin, (float*)out, g);
+    else if (s.lat == 0) hipLaunchKernelGGL((k_density<0, double>), grid, block, 0, st, (const double*)fin, (double*)out, g);
+    else if (s.prec == 0) hipLaunchKernelGGL((k_density<1, float>), grid, block, 0, st, (const float*)fin, (float*)out, g);
+    else hipLaunchKernelGGL((k_density<1, double>), grid, block, 0, st, (const double*)fin, (double*)out, g);
+    return hipGetLastError();
+}
+
+template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ>
+static void step_tile(const StepSpec& s, const void* fin, void* fout, const void* drho,
+                      StepIndex si, double* partial, hipStream_t st) {
+    const Geom g = make_geom(s, TileShape{TX, TY, TZ});
+    const dim3 grid(g.nblocks), block(TX * TY * TZ);
+    const CollideParams<Real> P = collide_params<Real>(s);
+    const ForceParams<Real> fp = force_params<Real>(s);
+    if (partial)
+        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, true, TX, TY, TZ>), grid, block, 0, st,
+                           (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
+    else
+        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, false, TX, TY, TZ>), grid, block, 0, st,
+                           (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
+}
+
+template <int LAT, typename Real>
+static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fout,
+                          const void* drho, StepIndex si, double* partial, hipStream_t st) {
+    if (!s.force) {
+        switch (cfg) {
+            case 0: step_tile<LAT, Real, false, 64, 4, 1>(s, fin, fout, drho, si, partial, st); break;
+            case 1: step_tile<LAT, Real, false, 128, 2, 1>(s, fin, fout, drho, si, partial, st); break;
+            case 2: step_tile<LAT, Real, false, 256, 1, 1>(s, fin, fout, drho, si, partial, st); break;
+            default: step_tile<LAT, Real, false, 32, 8, 1>(s, fin, fout, drho, si, partial, st); break;
+        }
+    } else if constexpr (LAT == 1) {
+        switch (cfg) {
+            case 0: step_tile<LAT, Real, true, 32, 4, 2>(s, fin, fout, drho, si, partial, st); break;
+            case 1: step_tile<LAT, Real, true, 16, 4, 4>(s, fin, fout, drho, si, partial, st); break;
+            default: step_tile<LAT, Real, true, 64, 2, 2>(s, fin, fout, drho, si, partial, st); break;
+        }
+    } else {
+        switch (cfg) {
+            case 0: step_tile<LAT, Real, true, 64, 4, 1>(s, fin, fout, drho, si, partial, st); break;
+            case 1: step_tile<LAT, Real, true, 32, 8, 1>(s, fin, fout, drho, si, partial, st); break;
+            default: step_tile<LAT, Real, true, 128, 2, 1>(s, fin, fout, drho, si, partial, st); break;
+        }
+    }
+}
+
+hipError_t launch_step(const StepSpec& s, int cfg, const void* fin, void* fout, const void* drho,
+                       const unsigned long long* step_dev, unsigned long long step_host,
+                       double* partial, hipStream_t st) {
+    StepIndex si{step_dev, step_host};
+    if (s.lat == 0 && s.prec == 0) step_dispatch<0, float>(s, cfg, fin, fout, drho, si, partial, st);
+    else if (s.lat == 0) step_dispatch<0, double>(s, cfg, fin, fout, drho, si, partial, st);
+    else if (s.prec == 0) step_dispatch<1, float>(s, cfg, fin, fout, drho, si, partial, st);
+    else step_dispatch<1, double>(s, cfg, fin, fout, drho, si, partial, st);
+    return hipGetLastError();
+}
+
+template <int LAT, typename Real, bool FORCE>
+static void fields_launch(const StepSpec& s, const void* fin, const void* drho, void* out,
+                          hipStream_t st) {
+    constexpr int TX = (LAT == 1) ? 32 : 64, TY = 4, TZ = (LAT == 1) ? 2 : 1;
+    const Geom g = make_geom(s, TileShape{TX, TY, TZ});
+    hipLaunchKernelGGL((k_fields<LAT, Real, FORCE, TX, TY, TZ>), dim3(g.nblocks),
+                       dim3(TX * TY * TZ), 0, st, (const Real*)fin, (const Real*)drho, (Real*)out,
+                       g, (Real)s.rho0, force_params<Real>(s));
+}
+
+hipError_t launch_fields(const StepSpec& s, const void* fin, const void* drho, void* out,
+                         hipStream_t st) {
+    if (s.lat == 0 && s.prec == 0) {
+        if (s.force) fields_launch<0, float, true>(s, fin, drho, out, st);
+        else fields_launch<0, float, false>(s, fin, drho, out, st);
+    } else if (s.lat == 0) {
+        if (s.force) fields_launch<0, double, true>(s, fin, drho, out, st);
+        else fields_launch<0, double, false>(s, fin, drho, out, st);
+    } else if (s.prec == 0) {
+        if (s.force) fields_launch<1, float, true>(s, fin, drho, out, st);
+        else fields_launch<1, float, false>(s, fin, drho, out, st);
+    } else {
+        if (s.force) fields_launch<1, double, true>(s, fin, drho, out, st);
+        else fields_launch<1, double, false>(s, fin, drho, out, st);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_finalize(const double* partial, uint32_t nslots, int nvals, double* out,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(k_stats_finalize, dim3(nvals), dim3(256), 0, st, partial, nslots, nvals,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise_words(const StepSpec& s, unsigned long long step, uint32_t block,
+                              uint32_t tag, unsigned long long site0, unsigned long long nsites,
+                              uint32_t* out, hipStream_t st) {
+    if (nsites == 0) return hipSuccess;
+    const dim3 grid((unsigned)((nsites + 255) / 256)), blk(256);
+    hipLaunchKernelGGL(k_noise_words, grid, blk, 0, st, site0, nsites, (uint32_t)step,
+                       block | (tag << 16), s.replica, s.key0, s.key1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_u64(unsigned long long* ctr, unsigned long long inc, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(64), 0, st, ctr, inc);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_u64(unsigned long long* ctr, unsigned long long v, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, st, ctr, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
+    const size_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       (uint32_t*)p, n);
+    return hipGetLastError();
+}
+
+}  // namespace flb

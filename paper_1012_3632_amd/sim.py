@@ -1,0 +1,267 @@
+"""Python front end of the HIP library: torch provides device memory and the
+stream, every step of the method runs in libflb.so.
+
+    sim = Simulation(Params(lattice="D3Q19", precision="fp32", nx=128, ny=128, nz=128,
+                            kT=1e-5, rate_bulk=1.2, rate_shear=1.6, seed=7))
+    sim.step(1000, stats_stride=1)
+    msum, msq, n = sim.moments()
+"""
+
+import ctypes as C
+from dataclasses import asdict, dataclass, fields, replace
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import call, lib
+
+LATTICES = {"D2Q9": (_lib.FLB_D2Q9, 9, 2), "D3Q19": (_lib.FLB_D3Q19, 19, 3)}
+PRECISIONS = {"fp32": (_lib.FLB_FP32, torch.float32), "fp64": (_lib.FLB_FP64, torch.float64)}
+
+
+@dataclass
+class Params:
+    """Run parameters (see include/flb.h, struct flb_params)."""
+
+    lattice: str = "D2Q9"
+    precision: str = "fp64"
+    nx: int = 32
+    ny: int = 32
+    nz: int = 1
+    rho0: float = 1.0
+    kT: float = 0.0
+    rate_bulk: float = 1.0
+    rate_shear: float = 1.0
+    rate_ghost: float = 1.0
+    force_model: int = 0
+    a: float = 0.0
+    b: float = 0.0
+    rho_c: float = 1.0
+    kappa: float = 0.0
+    eta: int = 0
+    noise_rho_local: int = 1
+    seed: int = 0
+    step0: int = 0
+    replica: int = 0
+
+    @classmethod
+    def from_dict(cls, d):
+        names = {f.name for f in fields(cls)}
+        return cls(**{k: v for k, v in d.items() if k in names})
+
+    def with_(self, **kw):
+        return replace(self, **kw)
+
+    @property
+    def q(self):
+        return LATTICES[self.lattice][1]
+
+    @property
+    def d(self):
+        return LATTICES[self.lattice][2]
+
+    @property
+    def dtype(self):
+        return PRECISIONS[self.precision][1]
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def to_c(self):
+        p = _lib.flb_params()
+        p.lattice = LATTICES[self.lattice][0]
+        p.precision = PRECISIONS[self.precision][0]
+        p.nx, p.ny, p.nz = int(self.nx), int(self.ny), int(self.nz)
+        p.force_model = int(self.force_model)
+        p.eta = int(self.eta)
+        p.noise_rho_local = int(self.noise_rho_local)
+        p.rho0, p.kT = float(self.rho0), float(self.kT)
+        p.rate_bulk, p.rate_shear, p.rate_ghost = (float(self.rate_bulk), float(self.rate_shear),
+                                                    float(self.rate_ghost))
+        p.a, p.b, p.rho_c, p.kappa = float(self.a), float(self.b), float(self.rho_c), float(self.kappa)
+        p.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
+        p.step0 = int(self.step0)
+        p.replica = int(self.replica)
+        return p
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def query_sizes(params):
+    pop, scr, sta = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    call("flb_query_sizes", C.byref(params.to_c()), C.byref(pop), C.byref(scr), C.byref(sta))
+    return pop.value, scr.value, sta.value
+
+
+def lattice_tables(lattice):
+    """The library's constant tables (host call, no GPU needed)."""
+    code, q, d = LATTICES[lattice]
+    qq = C.c_int32()
+    c = (C.c_int32 * (3 * q))()
+    w = (C.c_double * q)()
+    T = (C.c_double * (q * q))()
+    N = (C.c_double * q)()
+    cls = (C.c_int32 * q)()
+    call("flb_lattice_tables", code, C.byref(qq), c, w, T, N, cls)
+    return dict(q=qq.value, c=np.array(c[:]).reshape(q, 3), w=np.array(w[:]),
+                T=np.array(T[:]).reshape(q, q), N=np.array(N[:]), cls=np.array(cls[:]))
+
+
+def noise_words(params, step, block, site0, nsites, tag=0, device="cuda", stream=None):
+    """Raw Philox words of noise block ``block`` at ``step`` for a range of sites:
+    uint32 values as an int64 CPU tensor of shape (nsites, 4)."""
+    out = torch.empty((nsites, 4), dtype=torch.int32, device=device)
+    call("flb_noise_words", C.byref(params.to_c()), int(step), int(block), int(tag), int(site0),
+         int(nsites), _ptr(out), _stream(stream))
+    return out.cpu().to(torch.int64) & 0xFFFFFFFF
+
+
+class Simulation:
+    """One lattice advanced by the HIP library; buffers are torch tensors."""
+
+    def __init__(self, params, drho_init=None, device="cuda", stream=None):
+        self.params = params
+        self.device = torch.device(device)
+        pop, scr, sta = query_sizes(params)
+        self._pop_bytes = pop
+        mk = lambda n: torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
+        self.fa, self.fb = mk(pop), mk(pop)
+        self.scratch, self.stats = mk(scr), mk(sta)
+        drho = None
+        if drho_init is not None:
+            drho = torch.as_tensor(np.asarray(drho_init, dtype=np.float64).reshape(-1),
+                                   device=self.device).contiguous()
+            assert drho.numel() == params.nx * params.ny * params.nz
+        h = C.c_void_p()
+        call("flb_init", C.byref(params.to_c()), _ptr(self.fa), _ptr(self.fb), _ptr(self.scratch),
+             _ptr(self.stats), _ptr(drho), _stream(stream), C.byref(h))
+        self._h = h
+        self._bufs = {self.fa.data_ptr(): self.fa, self.fb.data_ptr(): self.fb}
+
+    # -- helpers
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("simulation is closed")
+        return self._h
+
+    def _view(self, buf):
+        p = self.params
+        n = p.q * p.nx * p.ny * p.nz
+        return buf.view(p.dtype)[:n].view(p.q, *p.shape)
+
+    # -- API
+    def step(self, nsteps, stats_stride=0, stream=None):
+        call("flb_step", self.handle, int(nsteps), int(stats_stride), _stream(stream))
+
+    @property
+    def step_index(self):
+        s = C.c_uint64()
+        call("flb_state", self.handle, None, None, C.byref(s))
+        return s.value
+
+    def state(self):
+        """View of the current shifted populations delta f, shape (q, nz, ny, nx)."""
+        cur = C.c_void_p()
+        call("flb_state", self.handle, C.byref(cur), None, None)
+        return self._view(self._bufs[cur.value])
+
+    def other(self):
+        oth = C.c_void_p()
+        call("flb_state", self.handle, None, C.byref(oth), None)
+        return self._view(self._bufs[oth.value])
+
+    def populations(self):
+        """Unshifted populations f = delta f + w rho0 as float64 on the CPU."""
+        w = torch.as_tensor(lattice_tables(self.params.lattice)["w"])
+        f = self.state().detach().to("cpu", torch.float64)
+        return f + w.view(-1, 1, 1, 1) * self.params.rho0
+
+    def load_state(self, delta_f):
+        """Overwrite the current state with shifted populations (q, nz, ny, nx)."""
+        self.state().copy_(torch.as_tensor(delta_f).to(self.device, self.params.dtype))
+
+    def moments(self, stream=None):
+        q = self.params.q
+        s = (C.c_double * q)()
+        s2 = (C.c_double * q)()
+        n = C.c_int64()
+        call("flb_moments", self.handle, s, s2, C.byref(n), _stream(stream))
+        return np.array(s[:]), np.array(s2[:]), n.value
+
+    def reset_stats(self, stream=None):
+        call("flb_reset_stats", self.handle, _stream(stream))
+
+    def fields(self, stream=None):
+        """rho and rho u after streaming (rho u = sum c f + F/2): (1 + d, nz, ny, nx)."""
+        p = self.params
+        out = torch.empty((1 + p.d,) + p.shape, dtype=p.dtype, device=self.device)
+        call("flb_fields", self.handle, _ptr(out), _stream(stream))
+        return out
+
+    def density(self, s, stream=None):
+        """rho - rho0 after streaming of state s (q, nz, ny, nx)."""
+        p = self.params
+        out = torch.empty(p.shape, dtype=p.dtype, device=self.device)
+        call("flb_density", self.handle, _ptr(s.contiguous()), _ptr(out), _stream(stream))
+        return out
+
+    def graph_capture(self, nsteps, stats_stride=0, stream=None):
+        call("flb_graph_capture", self.handle, int(nsteps), int(stats_stride), _stream(stream))
+
+    def graph_launch(self, stream=None):
+        call("flb_graph_launch", self.handle, _stream(stream))
+
+    def autotune(self, repeats=5, stream=None):
+        best, ms = C.c_int32(), C.c_double()
+        call("flb_autotune", self.handle, int(repeats), C.byref(best), C.byref(ms), _stream(stream))
+        return best.value, ms.value
+
+    def set_launch(self, config):
+        call("flb_set_launch", self.handle, int(config))
+
+    def launch_configs(self):
+        n, cur = C.c_int32(), C.c_int32()
+        call("flb_launch_configs", self.handle, C.byref(n), C.byref(cur))
+        return n.value, cur.value
+
+    def adjoint_seed(self, rhobar, stream=None):
+        p = self.params
+        out = torch.empty((p.q,) + p.shape, dtype=p.dtype, device=self.device)
+        call("flb_adjoint_density_seed", self.handle, _ptr(rhobar.contiguous()), _ptr(out),
+             _stream(stream))
+        return out
+
+    def adjoint_step(self, s_n, abar_np1, n, out=None, grad=None, stream=None):
+        """abar_n = dL/dS_n from abar_{n+1}; if ``grad`` (a length-4 float64
+        numpy array) is given, this step's parameter derivatives are added to it
+        (order: rate_shear, kT, rate_bulk, rate_ghost)."""
+        p = self.params
+        if out is None:
+            out = torch.empty((p.q,) + p.shape, dtype=p.dtype, device=self.device)
+        g = (C.c_double * 4)(*(grad if grad is not None else [0.0] * 4)) if grad is not None else None
+        call("flb_adjoint_step", self.handle, _ptr(s_n.contiguous()), _ptr(abar_np1.contiguous()),
+             _ptr(out), g, int(n), _stream(stream))
+        if grad is not None:
+            grad[:] = np.array(g[:])
+        return out
+
+    def close(self):
+        if self._h is not None:
+            lib.flb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,227 @@
+"""GPU parity of the HIP library against the FP64 oracle (through the C ABI).
+
+Bars: Philox words bit-exact; populations within 1e-12 (FP64) / 1e-5 (FP32)
+relative to max|f| on unshifted populations; statistics to FP64 rounding.
+Sizes span several tiles with ragged edges in every direction.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import flb_workloads as W
+from helpers import gpu_params, oracle_params, rel_err, run_pair, tol
+
+pytestmark = pytest.mark.gpu
+
+C2 = dict(lattice="D3Q19", rho0=1.0, kT=1e-5, rate_bulk=1.2, rate_shear=1.6, rate_ghost=1.0, seed=7)
+LANDAU = dict(force_model=1, a=-0.01, b=0.1, rho_c=1.0, kappa=0.05)
+
+
+def test_noise_words_bit_exact():
+    from oracle import philox
+    from paper_1012_3632_amd import noise_words
+    p = gpu_params(**C2, nx=128, ny=128, nz=128, precision="fp32")
+    for step, block, site0, n in ((0, 0, 0, 4096), (123, 3, 2_000_000, 97_152), (2**31 + 5, 1, 16_000_000, 777)):
+        got = noise_words(p, step, block, site0, n).numpy()
+        ref = philox.block_words(np.arange(site0, site0 + n, dtype=np.uint64), step, block, 7)
+        np.testing.assert_array_equal(got, ref.T.astype(np.int64))
+    p2 = gpu_params(**C2, nx=8, ny=8, nz=8, precision="fp64").with_(seed=0xDEADBEEF12345678, replica=9)
+    got = noise_words(p2, 77, 2, 0, 512, tag=1).numpy()
+    ref = philox.block_words(np.arange(512, dtype=np.uint64), 77, 2, 0xDEADBEEF12345678, tag=1,
+                             replica=9)
+    np.testing.assert_array_equal(got, ref.T.astype(np.int64))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_parity_d2q9_ideal_full_run(precision):
+    kw = dict(W.params_of("d2q9_32_fp64"), precision=precision)
+    sim, fg, fr, _ = run_pair(kw, W.WORKLOADS["d2q9_32_fp64"]["steps"])
+    assert rel_err(fg, fr) < tol(kw)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(9, 70, 5), (20, 18, 16), (3, 5, 130)])
+def test_parity_d3q19_ideal(precision, shape):
+    nz, ny, nx = shape
+    kw = dict(C2, precision=precision, nx=nx, ny=ny, nz=nz)
+    for launch in range(4):
+        sim, fg, fr, _ = run_pair(kw, 30, drho_amp=0.01, launch=launch)
+        assert rel_err(fg, fr) < tol(kw), launch
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("eta", [0, 1])
+def test_parity_d2q9_landau(precision, eta):
+    kw = dict(W.params_of("d2q9_256_adjoint", nx=70, ny=37), precision=precision, eta=eta)
+    nsteps = 200 if eta == 0 else 60
+    for launch in range(3):
+        sim, fg, fr, _ = run_pair(kw, nsteps, drho_amp=0.01, launch=launch)
+        assert rel_err(fg, fr) < tol(kw), launch
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("eta", [0, 1])
+def test_parity_d3q19_landau(precision, eta):
+    kw = dict(W.params_of("d3q19_256_landau", nx=35, ny=13, nz=11), precision=precision, eta=eta)
+    for launch in range(3):
+        sim, fg, fr, _ = run_pair(kw, 25, drho_amp=0.01, launch=launch)
+        assert rel_err(fg, fr) < tol(kw), launch
+
+
+@pytest.mark.parametrize("lattice,shape", [("D2Q9", (1, 1, 1)), ("D2Q9", (1, 3, 1)),
+                                           ("D3Q19", (1, 1, 1)), ("D3Q19", (2, 1, 3)),
+                                           ("D3Q19", (1, 2, 65))])
+@pytest.mark.parametrize("force", [0, 1])
+def test_parity_tiny_boxes(lattice, shape, force):
+    nz, ny, nx = shape
+    kw = dict(lattice=lattice, precision="fp64", nx=nx, ny=ny, nz=nz, kT=1e-4, rate_bulk=1.3,
+              rate_shear=0.7, rate_ghost=1.9, seed=5)
+    if force:
+        kw.update(LANDAU)
+    sim, fg, fr, _ = run_pair(kw, 12, drho_amp=0.01 if force else 0.0)
+    assert rel_err(fg, fr) < 1e-12
+
+
+def test_statistics_match_oracle():
+    kw = dict(W.params_of("d2q9_32_fp64"), nx=33, ny=17)
+    sim, fg, fr, st = run_pair(kw, 60, stats_stride=3)
+    s, s2, n = sim.moments()
+    assert n == st["nsamples"] == 20
+    np.testing.assert_allclose(s2, st["sumsq"], rtol=1e-11)
+    np.testing.assert_allclose(s, st["sum"], rtol=1e-9, atol=1e-13)
+
+
+@pytest.mark.parametrize("force", [0, 1])
+def test_fields_match_oracle(force):
+    from oracle import flb
+    kw = dict(C2, precision="fp64", nx=21, ny=10, nz=9)
+    if force:
+        kw.update(LANDAU, kT=1e-6)
+    sim, fg, fr, _ = run_pair(kw, 7, drho_amp=0.01)
+    rho, j = flb.fields(torch.as_tensor(fr), oracle_params(**kw))
+    out = sim.fields().cpu().numpy()
+    np.testing.assert_allclose(out[0], rho.numpy(), rtol=1e-13)
+    np.testing.assert_allclose(out[1:], j.numpy(), rtol=0, atol=1e-14)
+
+
+def test_full_size_step_parity_d3q19_128():
+    """d3q19_128 at full size in the default launch: the GPU state after 40
+    steps is advanced one step by the oracle and by the GPU; every site is
+    compared (FP32 bar)."""
+    from oracle import flb
+    from paper_1012_3632_amd import Simulation
+    kw = dict(W.params_of("d3q19_128"), precision="fp32")
+    sim = Simulation(gpu_params(**kw))
+    sim.step(40)
+    S40 = sim.populations()
+    sim.step(1)
+    got = sim.populations().numpy()
+    po = oracle_params(**kw)
+    ref = flb.step(S40, 40, po).numpy()
+    assert rel_err(got, ref) < 1e-5
+    del S40
+
+
+def test_graph_replay_matches_eager():
+    from paper_1012_3632_amd import Simulation
+    kw = dict(C2, precision="fp32", nx=40, ny=24, nz=16)
+    a = Simulation(gpu_params(**kw))
+    b = Simulation(gpu_params(**kw))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b.graph_capture(10, stats_stride=2)
+        for r in range(4):
+            a.step(10, stats_stride=2)
+            b.graph_launch()
+            torch.cuda.synchronize()
+            assert torch.equal(a.state(), b.state()), r
+            x = torch.randn(1000, device="cuda").sum()  # eager work between replays
+    torch.cuda.synchronize()
+    assert a.step_index == b.step_index == 40
+    sa, qa, na = a.moments()
+    sb, qb, nb = b.moments()
+    assert na == nb == 20
+    np.testing.assert_array_equal(qa, qb)
+
+
+def test_resume_is_bit_exact():
+    from paper_1012_3632_amd import Simulation
+    kw = dict(C2, precision="fp32", nx=30, ny=20, nz=10)
+    a = Simulation(gpu_params(**kw))
+    a.step(20)
+    b = Simulation(gpu_params(**kw))
+    b.step(10)
+    c = Simulation(gpu_params(**kw).with_(step0=10))
+    c.load_state(b.state().clone())
+    c.step(10)
+    torch.cuda.synchronize()
+    assert torch.equal(a.state(), c.state())
+
+
+def test_launch_configs_bitwise_identical_and_autotune_keeps_state():
+    from paper_1012_3632_amd import Simulation
+    kw = dict(C2, precision="fp32", nx=64, ny=32, nz=16)
+    ref = None
+    for cfg in range(4):
+        s = Simulation(gpu_params(**kw))
+        s.set_launch(cfg)
+        s.step(6)
+        st = s.state().clone()
+        if ref is None:
+            ref = st
+        assert torch.equal(st, ref), cfg
+    s = Simulation(gpu_params(**kw))
+    s.step(3)
+    before = s.state().clone()
+    best, ms = s.autotune(repeats=2)
+    assert torch.equal(s.state(), before)
+    assert ms > 0 and 0 <= best < 4
+
+
+def test_conservation_gpu():
+    from paper_1012_3632_amd import Simulation, lattice_tables
+    kw = dict(C2, precision="fp64", nx=24, ny=20, nz=16)
+    s = Simulation(gpu_params(**kw), drho_init=W.initial_drho((16, 20, 24), 1, 0.01))
+    c = torch.as_tensor(lattice_tables("D3Q19")["c"], dtype=torch.float64)
+    f0 = s.state().cpu().double()
+    s.step(200)
+    f1 = s.state().cpu().double()
+    assert abs(f1.sum() - f0.sum()) < 1e-12
+    j0 = torch.einsum("ia,i...->a", c, f0)
+    j1 = torch.einsum("ia,i...->a", c, f1)
+    assert (j1 - j0).abs().max() < 1e-13
+
+
+def test_rest_state_stays_exactly_zero():
+    from paper_1012_3632_amd import Simulation
+    for lat in ("D2Q9", "D3Q19"):
+        kw = dict(C2, lattice=lat, precision="fp32", nx=17, ny=9, nz=1 if lat == "D2Q9" else 5,
+                  kT=0.0)
+        s = Simulation(gpu_params(**kw))
+        s.step(10)
+        assert torch.count_nonzero(s.state()) == 0
+
+
+def test_determinism():
+    from paper_1012_3632_amd import Simulation
+    kw = dict(C2, precision="fp32", nx=64, ny=64, nz=64)
+    out = []
+    for _ in range(2):
+        s = Simulation(gpu_params(**kw))
+        s.step(20, stats_stride=1)
+        out.append((s.state().clone(), s.moments()))
+    assert torch.equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1][1], out[1][1][1])
+
+
+def test_invalid_arguments_rejected():
+    from paper_1012_3632_amd import Simulation
+    from paper_1012_3632_amd._lib import FLBError
+    bad = [dict(kT=0.4), dict(rate_shear=2.0), dict(rate_bulk=0.0), dict(nz=2), dict(nx=0),
+           dict(rho0=-1.0)]
+    for b in bad:
+        kw = dict(lattice="D2Q9", precision="fp64", nx=8, ny=8, nz=1)
+        kw.update(b)
+        with pytest.raises(FLBError):
+            Simulation(gpu_params(**kw))

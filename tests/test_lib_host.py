@@ -1,0 +1,66 @@
+"""Host-side checks of the HIP library (no GPU needed): the shared library
+loads, exports every symbol include/flb.h declares, its constant tables equal
+the oracle's independently built ones, and invalid parameters are rejected."""
+
+import numpy as np
+import pytest
+
+from oracle import lattice
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1012_3632_amd import _lib
+    names = _lib.declared_symbols()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(_lib.lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19"])
+def test_library_tables_equal_oracle(name):
+    from paper_1012_3632_amd import lattice_tables
+    t = lattice_tables(name)
+    lat = lattice.get(name)
+    assert t["q"] == lat.q
+    np.testing.assert_array_equal(t["c"], lat.c)
+    np.testing.assert_allclose(t["w"], lat.w, rtol=1e-15)
+    np.testing.assert_array_equal(t["T"], lat.T)
+    np.testing.assert_allclose(t["N"], lat.N, rtol=1e-15)
+    names = ["rho", "j", "bulk", "shear", "ghost"]
+    assert [names[k] for k in t["cls"]] == lat.classes
+
+
+def test_sizes_and_validation():
+    from paper_1012_3632_amd import Params, query_sizes
+    from paper_1012_3632_amd._lib import FLBError
+    pop, scr, sta = query_sizes(Params(lattice="D3Q19", precision="fp32", nx=128, ny=128, nz=128))
+    assert pop == 19 * 128 ** 3 * 4
+    pop64, _, _ = query_sizes(Params(lattice="D3Q19", precision="fp64", nx=128, ny=128, nz=128))
+    assert pop64 == 2 * pop
+    assert sta >= 2 * 19 * 8
+    bad = [dict(kT=1 / 3), dict(kT=-1e-9), dict(rate_shear=2.0), dict(rate_ghost=0.0),
+           dict(nz=2), dict(nx=0), dict(rho0=0.0), dict(lattice="D3Q19", nx=2048, ny=2048, nz=1024),
+           dict(force_model=1, kappa=-1.0), dict(force_model=1, eta=2), dict(force_model=3)]
+    for b in bad:
+        kw = dict(lattice="D2Q9", precision="fp64", nx=8, ny=8, nz=1)
+        kw.update(b)
+        with pytest.raises(FLBError):
+            query_sizes(Params(**kw))
+
+
+def test_product_path_does_not_use_oracle():
+    """The package never imports the oracle (and vice versa)."""
+    import ast
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for pkg, forbidden in (("paper_1012_3632_amd", "oracle"), ("oracle", "paper_1012_3632_amd")):
+        for dirpath, _, files in os.walk(os.path.join(root, pkg)):
+            for fn in files:
+                if not fn.endswith(".py"):
+                    continue
+                tree = ast.parse(open(os.path.join(dirpath, fn)).read())
+                for node in ast.walk(tree):
+                    if isinstance(node, ast.Import):
+                        assert all(not a.name.startswith(forbidden) for a in node.names), fn
+                    elif isinstance(node, ast.ImportFrom) and node.module:
+                        assert not node.module.startswith(forbidden), fn
