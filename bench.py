@@ -189,12 +189,46 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--profile-step", choices=["fp32", "fp64"],
+                    help="only run the d3q19_128 step (fixed launch shape, statistics on)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(domain decomposition is design only).", file=sys.stderr)
         sys.exit(2)
-    bench_main(args)
+    if args.copy_probe:
+        copy_probe()
+    elif args.profile_step:
+        profile_step(args)
+    else:
+        bench_main(args)
+
+
+def copy_probe():
+    """A plain copy of 2^28 floats (1 GiB read, 1 GiB written), 5 times."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4}))
+
+
+def profile_step(args):
+    import torch
+
+    import flb_workloads as W
+    from paper_1012_3632_amd import Params, Simulation
+    p = Params.from_dict(dict(W.params_of("d3q19_128"), precision=args.profile_step))
+    sim = Simulation(p)
+    best, _ = sim.autotune(repeats=2)
+    sim.step(args.warmup + args.steps, stats_stride=1)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_step": args.profile_step, "steps": args.warmup + args.steps,
+                      "launch_config": best}))
 
 
 if __name__ == "__main__":
