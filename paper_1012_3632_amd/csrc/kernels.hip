@@ -15,151 +15,10 @@
 // force at each site from those (no extra HBM pass for mu).
 #include <hip/hip_runtime.h>
 
+#include "device.h"
 #include "internal.h"
-#include "step.h"
 
 namespace flb {
-
-// ------------------------------------------------------------------ helpers
-
-template <int LAT>
-__device__ __forceinline__ uint32_t site_index(int x, int y, int z, const Geom& g) {
-    return (uint32_t)((z * g.ny + y) * g.nx + x);
-}
-
-// f_i(x) = S_i(x - c_i), periodic.
-template <int LAT, typename Real>
-__device__ __forceinline__ void pull(const Real* __restrict__ fin, int x, int y, int z,
-                                     const Geom& g, Real (&f)[Lattice<LAT>::Q]) {
-    using L = Lattice<LAT>;
-    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
-    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const int sx = L::cx[i] == 0 ? x : (L::cx[i] > 0 ? xm : xp);
-        const int sy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? ym : yp);
-        const int sz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zm : zp);
-        f[i] = fin[(size_t)i * g.V + (uint32_t)((sz * g.ny + sy) * g.nx + sx)];
-    }
-}
-
-template <typename Real>
-__device__ __forceinline__ Real wave_sum(Real v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Reduce NV doubles over the block in a fixed order and add them to slot[0..NV).
-template <int NV, int NT>
-__device__ __forceinline__ void block_accumulate(double (&v)[NV], double* __restrict__ slot,
-                                                 double* lds) {
-    constexpr int NW = (NT + 63) / 64;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const double s = wave_sum(v[k]);
-        if (lane == 0) lds[wave * NV + k] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < NV) {
-        double acc = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) acc += lds[w * NV + threadIdx.x];
-        slot[threadIdx.x] += acc;
-    }
-}
-
-template <int LAT, int TX, int TY, int TZ>
-__device__ __forceinline__ void tile_origin(const Geom& g, int& x0, int& y0, int& z0) {
-    const uint32_t b = xcd_remap(blockIdx.x, g.nblocks);
-    const uint32_t bx = b % (uint32_t)g.nbx;
-    const uint32_t r = b / (uint32_t)g.nbx;
-    const uint32_t by = r % (uint32_t)g.nby;
-    const uint32_t bz = r / (uint32_t)g.nby;
-    x0 = (int)bx * TX;
-    y0 = (int)by * TY;
-    z0 = (int)bz * TZ;
-}
-
-__device__ __forceinline__ int wrap_any(int v, int n) {
-    while (v < 0) v += n;
-    while (v >= n) v -= n;
-    return v;
-}
-
-// ------------------------------------------------------------------ force tile
-
-// Chemical potential mu = psi'(rho) - kappa lap_h rho on the tile plus a
-// one-site halo, from the density on the tile plus a two-site halo, both in
-// LDS; then F = -rho grad_h mu + eta grad_h(cs2 rho) at a site of the tile.
-template <int LAT, typename Real, int TX, int TY, int TZ>
-struct ForceTile {
-    using L = Lattice<LAT>;
-    static constexpr int D = L::D;
-    static constexpr int HZ = (LAT == 0) ? 0 : 1;
-    static constexpr int RX = TX + 4, RY = TY + 4, RZ = TZ + 4 * HZ;
-    static constexpr int MX = TX + 2, MY = TY + 2, MZ = TZ + 2 * HZ;
-    static constexpr int NR = RX * RY * RZ, NM = MX * MY * MZ;
-    static constexpr int NT = TX * TY * TZ;
-
-    static __device__ __forceinline__ void stage(const Real* __restrict__ drho, const Geom& g,
-                                                 const ForceParams<Real>& fp, int x0, int y0,
-                                                 int z0, Real* rs, Real* ms) {
-        const int tid = threadIdx.x;
-        for (int l = tid; l < NR; l += NT) {
-            const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
-            const int gx = wrap_any(x0 + lx - 2, g.nx);
-            const int gy = wrap_any(y0 + ly - 2, g.ny);
-            const int gz = wrap_any(z0 + lz - 2 * HZ, g.nz);
-            rs[l] = drho[(uint32_t)((gz * g.ny + gy) * g.nx + gx)];
-        }
-        __syncthreads();
-        for (int l = tid; l < NM; l += NT) {
-            const int mx = l % MX, my = (l / MX) % MY, mz = l / (MX * MY);
-            const int c = ((mz + HZ) * RY + (my + 1)) * RX + (mx + 1);
-            const Real rc = rs[c];
-            Real lap = Real(0);
-#pragma unroll
-            for (int i = 1; i < L::Q; ++i) {
-                const int n = c + (L::cz[i] * RY + L::cy[i]) * RX + L::cx[i];
-                lap += Real(L::w[i]) * (rs[n] - rc);
-            }
-            lap *= Real(6);   // 2 / cs2
-            const Real d = rc + fp.shift;
-            ms[l] = Real(2) * fp.a * d + Real(4) * fp.b * d * d * d - fp.kappa * lap;
-        }
-        __syncthreads();
-    }
-
-    // Force at tile-local site (lx, ly, lz); also returns delta rho there.
-    static __device__ __forceinline__ void force(const Real* rs, const Real* ms,
-                                                 const ForceParams<Real>& fp, Real rho0, int lx,
-                                                 int ly, int lz, Real (&F)[D]) {
-        const int cm = ((lz + HZ) * MY + (ly + 1)) * MX + (lx + 1);
-        const int cr = ((lz + 2 * HZ) * RY + (ly + 2)) * RX + (lx + 2);
-        Real gm[D], gr[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) gm[a] = gr[a] = Real(0);
-#pragma unroll
-        for (int i = 1; i < L::Q; ++i) {
-            const Real mu = ms[cm + (L::cz[i] * MY + L::cy[i]) * MX + L::cx[i]];
-            const Real rn = rs[cr + (L::cz[i] * RY + L::cy[i]) * RX + L::cx[i]];
-            const int c3[3] = {L::cx[i], L::cy[i], L::cz[i]};
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                if (c3[a] == 0) continue;
-                const Real wc = Real(L::w[i] * c3[a]);
-                gm[a] += wc * mu;
-                gr[a] += wc * rn;
-            }
-        }
-        const Real rho = rho0 + rs[cr];
-#pragma unroll
-        for (int a = 0; a < D; ++a) F[a] = -rho * Real(3) * gm[a] + fp.eta * gr[a];
-    }
-};
 
 // ------------------------------------------------------------------ kernels
 
