@@ -158,6 +158,63 @@ def extras(args, stream):
     s.close()
     del s
     torch.cuda.empty_cache()
+
+    # 64 replicas of uneven size, one persistent launch per step, captured graph
+    from paper_1012_3632_amd import Batch
+    wl = W.WORKLOADS["d3q19_batch64"]
+    edges = W.batch_edges(wl["replicas"], wl["edges"], wl["size_seed"])
+    pb = Params.from_dict(dict(lattice="D3Q19", precision="fp32", rho0=1.0, kT=wl["kT"],
+                               rate_bulk=wl["rate_bulk"], rate_shear=wl["rate_shear"],
+                               rate_ghost=wl["rate_ghost"]))
+    b = Batch(pb, [(e, e, e) for e in edges], seeds=list(range(wl["replicas"])))
+    best, _ = b.autotune(repeats=3)
+    gsteps = 100
+    b.graph_capture(gsteps, stats_stride=1, stream=stream)
+    b.graph_launch(stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    b.graph_launch(stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / gsteps
+    Vt = sum(e ** 3 for e in edges)
+    res["d3q19_batch64"] = {"ms_per_step": round(ms, 4), "MLUPS": round(Vt / (ms * 1e-3) / 1e6, 1),
+                            "sites": Vt, "grid_config": best,
+                            "hbm_frac": round(152 * Vt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "graph_steps": gsteps, "statistics": "every step"}
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+
+    # differentiable run: adjoint / forward time
+    from paper_1012_3632_amd.autograd import FLBRun
+    wl = W.WORKLOADS["d2q9_256_adjoint"]
+    pa = Params.from_dict(dict(W.params_of("d2q9_256_adjoint"), precision="fp32"))
+    drho = W.initial_drho(pa.shape, 1234, wl["init_noise"])
+    w = torch.tensor([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, dtype=torch.float64).view(-1, 1, 1, 1)
+    df0 = (w * torch.as_tensor(drho)).to("cuda", torch.float32)
+    target = torch.ones(pa.shape, dtype=torch.float64, device="cuda")
+    times = []
+    for rep in range(3):
+        x = df0.clone().requires_grad_(True)
+        rs = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+        kT = torch.tensor(pa.kT, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rho = FLBRun.apply(x, rs, kT, pa, wl["steps"], wl["checkpoint_every"])
+        L = ((rho - target) ** 2).mean()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append((t1 - t0, t2 - t1))
+    fwd, bwd = min(t[0] for t in times), min(t[1] for t in times)
+    res["d2q9_256_adjoint"] = {"forward_ms": round(fwd * 1e3, 3), "backward_ms": round(bwd * 1e3, 3),
+                               "adjoint_forward_ratio": round(bwd / fwd, 3), "steps": wl["steps"],
+                               "checkpoint_every": wl["checkpoint_every"]}
     return res
 
 

@@ -122,6 +122,10 @@ flb_status flb_step(flb_handle* h, int64_t nsteps, int32_t stats_stride, void* s
  * second buffer, *step the index n of the next step.  Host only. */
 flb_status flb_state(const flb_handle* h, void** cur, void** other, uint64_t* step);
 
+/* Set the index of the next step (e.g. after loading a checkpointed state
+ * into the current buffer).  Asynchronous. */
+flb_status flb_seek(flb_handle* h, uint64_t step, void* stream);
+
 /* Finalize the statistics in a fixed order and copy them to the host:
  * mode_sum[Q], mode_sumsq[Q] (either may be NULL), *nsamples the number of
  * sampled steps.  Synchronizes the stream.  Returns FLB_ERR_NONFINITE if a

@@ -51,6 +51,7 @@ PROTOS = {
     "flb_init": [P(flb_params), vp, vp, vp, vp, vp, vp, P(vp)],
     "flb_step": [vp, C.c_int64, C.c_int32, vp],
     "flb_state": [vp, P(vp), P(vp), P(C.c_uint64)],
+    "flb_seek": [vp, C.c_uint64, vp],
     "flb_moments": [vp, P(C.c_double), P(C.c_double), P(C.c_int64), vp],
     "flb_reset_stats": [vp, vp],
     "flb_fields": [vp, vp, vp],

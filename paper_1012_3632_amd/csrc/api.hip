@@ -101,6 +101,7 @@ StepSpec spec_of(const flb_params& p) {
     s.ny = p.ny;
     s.nz = p.nz;
     s.rho0 = p.rho0;
+    s.kT = p.kT;
     s.lam_bulk = p.rate_bulk;
     s.lam_shear = p.rate_shear;
     s.lam_ghost = p.rate_ghost;
@@ -130,6 +131,8 @@ uint32_t max_slots(const StepSpec& s) {
 bool aligned(const void* p) { return p && ((uintptr_t)p % ALIGN) == 0; }
 
 }  // namespace
+
+void flb::set_last_error(const char* msg) { g_last_error = msg; }
 
 struct flb_handle {
     flb_params p;
@@ -318,6 +321,13 @@ flb_status flb_step(flb_handle* h, int64_t nsteps, int32_t stats_stride, void* s
     h->step += (uint64_t)nsteps;
     h->nsamples += ns;
     // keep the device step counter in step with the host (graph replays read it)
+    HIP_TRY(launch_set_u64(h->step_dev, h->step, (hipStream_t)stream));
+    return FLB_OK;
+}
+
+flb_status flb_seek(flb_handle* h, uint64_t step, void* stream) {
+    if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
+    h->step = step;
     HIP_TRY(launch_set_u64(h->step_dev, h->step, (hipStream_t)stream));
     return FLB_OK;
 }

@@ -1,32 +1,525 @@
-// Batched replicas (placeholder until the persistent batched kernel lands).
+// Batched replicas: many independent ideal-gas lattices of uneven size
+// advanced by one persistent launch per step.
+//
+// Every replica's sites are cut into chunks of BT = 256 consecutive sites
+// (x fastest); the chunks of all replicas form one flat tile table.  A grid of
+// (compute units x blocks per CU) workgroups walks the table with a grid
+// stride, so uneven replica sizes cost nothing beyond the last partial wave.
+// Replica r has its own box, Philox key seeds[r] and counter word 3 = r, and
+// its populations start at element Q * sum_{s<r} V_s of each buffer.
+// Statistics: one FP64 slot per tile (fixed tile->slot map), reduced per
+// replica in tile order by k_batch_finalize.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
 #include "../../include/flb.h"
+#include "device.h"
+#include "internal.h"
+
+namespace flb {
+
+constexpr int BT = 256;   // sites per tile (one per thread)
+
+struct RepInfo {
+    int32_t nx, ny, nz;
+    uint32_t V;
+    uint64_t off;          // element offset of the replica in a population buffer
+    uint32_t key0, key1;
+    uint32_t tile0, ntiles;
+    uint32_t inv_nx, inv_ny;   // ceil(2^32 / n): exact division for n < 256, s < 2^24
+};
+
+__device__ __forceinline__ uint32_t div_small(uint32_t s, uint32_t inv) { return __umulhi(s, inv); }
+
+template <int LAT, typename Real, bool STATS>
+__global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
+                                                   Real* __restrict__ fout,
+                                                   const RepInfo* __restrict__ reps,
+                                                   const uint32_t* __restrict__ tile_rep,
+                                                   uint32_t ntiles, CollideParams<Real> P,
+                                                   StepIndex st, double* __restrict__ partial) {
+    using L = Lattice<LAT>;
+    using M = Moments<LAT, Real>;
+    constexpr int Q = L::Q, D = L::D;
+    __shared__ double lds_stats[STATS ? (BT / 64) * 2 * Q : 1];
+    const uint32_t step = st.get();
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t r = tile_rep[t];
+        const RepInfo R = reps[r];
+        Geom g;
+        g.nx = R.nx;
+        g.ny = R.ny;
+        g.nz = R.nz;
+        g.V = R.V;
+        const uint32_t s = (t - R.tile0) * BT + threadIdx.x;
+        double v[2 * Q];
+        if (s < R.V) {
+            const uint32_t yz = div_small(s, R.inv_nx);
+            const int x = (int)(s - yz * (uint32_t)R.nx);
+            const uint32_t z = div_small(yz, R.inv_ny);
+            const int y = (int)(yz - z * (uint32_t)R.ny);
+            Real f[Q], m[Q];
+            pull<LAT, Real>(fin + R.off, x, y, (int)z, g, f);
+            M::forward(f, m);
+            if constexpr (STATS) {
+#pragma unroll
+                for (int a = 0; a < Q; ++a) {
+                    const double ma = (double)m[a];
+                    v[a] = ma;
+                    v[Q + a] = ma * ma;
+                }
+            }
+            Real zn[4 * L::NBLK];
+            if (P.noise_on) site_normals<L::NBLK, Real>(s, step, 0u, r, R.key0, R.key1, zn);
+            const Real F[D] = {};
+            collide_moments<LAT, Real, false>(m, F, zn, P);
+            M::inverse(m, f);
+            Real* out = fout + R.off;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) out[(size_t)i * R.V + s] = f[i];
+        } else if constexpr (STATS) {
+#pragma unroll
+            for (int k = 0; k < 2 * Q; ++k) v[k] = 0.0;
+        }
+        if constexpr (STATS) {
+            block_accumulate<2 * Q, BT>(v, partial + (size_t)t * 2 * Q, lds_stats);
+            __syncthreads();   // lds_stats is reused by the next tile
+        }
+    }
+}
+
+// out[r][k] = sum over replica r's tiles (in order) of partial[tile][k].
+__global__ void k_batch_finalize(const double* __restrict__ partial,
+                                 const RepInfo* __restrict__ reps, int nvals,
+                                 double* __restrict__ out) {
+    __shared__ double red[256];
+    const int k = blockIdx.x, r = blockIdx.y;
+    const RepInfo R = reps[r];
+    double acc = 0.0;
+    for (uint32_t t = threadIdx.x; t < R.ntiles; t += 256)
+        acc += partial[(size_t)(R.tile0 + t) * nvals + k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(size_t)r * nvals + k] = red[0];
+}
+
+template <int LAT, typename Real>
+__global__ void k_batch_init(Real* __restrict__ f, const RepInfo* __restrict__ reps,
+                             const uint32_t* __restrict__ tile_rep, uint32_t ntiles) {
+    using L = Lattice<LAT>;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const RepInfo R = reps[tile_rep[t]];
+        const uint32_t s = (t - R.tile0) * BT + threadIdx.x;
+        if (s < R.V) {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) f[R.off + (size_t)i * R.V + s] = Real(0);
+        }
+    }
+}
+
+}  // namespace flb
+
+using namespace flb;
+
+namespace {
+
+flb_status bfail(flb_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    set_last_error(buf);
+    return s;
+}
+
+#define BHIP(expr)                                                                        \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return bfail(FLB_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+constexpr double CS2 = 1.0 / 3.0;
+
+struct Layout {
+    std::vector<RepInfo> reps;
+    std::vector<uint32_t> tile_rep;
+    size_t elems;          // reals per population buffer
+    size_t reps_off, tiles_off, ctr_off, scratch_bytes, stats_bytes;
+};
+
+flb_status batch_layout(const flb_params* p, int32_t nrep, const int32_t* dims,
+                        const uint64_t* seeds, Layout* L) {
+    if (!p || !dims) return bfail(FLB_ERR_INVALID_ARG, "NULL argument");
+    if (nrep < 1 || nrep > 4096) return bfail(FLB_ERR_INVALID_ARG, "nrep = %d", nrep);
+    if (p->force_model != FLB_IDEAL)
+        return bfail(FLB_ERR_UNSUPPORTED, "batched replicas are ideal-gas only");
+    flb_params q = *p;
+    const int Q = p->lattice == FLB_D2Q9 ? 9 : 19;
+    L->reps.clear();
+    L->tile_rep.clear();
+    size_t off = 0;
+    uint32_t tile = 0;
+    for (int r = 0; r < nrep; ++r) {
+        q.nx = dims[3 * r];
+        q.ny = dims[3 * r + 1];
+        q.nz = dims[3 * r + 2];
+        size_t a, b, c;
+        flb_status st = flb_query_sizes(&q, &a, &b, &c);
+        if (st != FLB_OK) {
+            const std::string why = flb_last_error();
+            return bfail(st, "replica %d: %s", r, why.c_str());
+        }
+        if (q.nx >= 256 || q.ny >= 256 || q.nz >= 65536)
+            return bfail(FLB_ERR_INVALID_ARG, "replica %d: batched boxes need nx, ny < 256", r);
+        RepInfo R{};
+        R.nx = q.nx;
+        R.ny = q.ny;
+        R.nz = q.nz;
+        R.V = (uint32_t)q.nx * q.ny * q.nz;
+        if (R.V >= (1u << 24)) return bfail(FLB_ERR_INVALID_ARG, "replica %d too large", r);
+        R.off = off;
+        const uint64_t seed = seeds ? seeds[r] : (uint64_t)r;
+        R.key0 = (uint32_t)(seed & 0xffffffffu);
+        R.key1 = (uint32_t)(seed >> 32);
+        R.tile0 = tile;
+        R.ntiles = (R.V + BT - 1) / BT;
+        R.inv_nx = (uint32_t)(((1ull << 32) + R.nx - 1) / R.nx);
+        R.inv_ny = (uint32_t)(((1ull << 32) + R.ny - 1) / R.ny);
+        for (uint32_t t = 0; t < R.ntiles; ++t) L->tile_rep.push_back((uint32_t)r);
+        tile += R.ntiles;
+        off += (size_t)Q * R.V;
+        L->reps.push_back(R);
+    }
+    L->elems = off;
+    size_t s = 0;
+    L->ctr_off = s;
+    s += ALIGN;
+    L->reps_off = s;
+    s += align_up(L->reps.size() * sizeof(RepInfo));
+    L->tiles_off = s;
+    s += align_up(L->tile_rep.size() * sizeof(uint32_t));
+    L->scratch_bytes = s;
+    L->stats_bytes = align_up(((size_t)tile * 2 * Q + (size_t)nrep * 2 * Q) * sizeof(double));
+    return FLB_OK;
+}
+
+}  // namespace
+
+struct flb_batch {
+    flb_params p;
+    int q, nrep;
+    size_t rb;
+    Layout L;
+    void* fa;
+    void* fb;
+    bool cur_a;
+    char* scratch;
+    double* stats;
+    RepInfo* reps_dev;
+    uint32_t* tiles_dev;
+    unsigned long long* ctr_dev;
+    uint32_t ntiles;
+    uint64_t step;
+    int64_t nsamples;
+    int grid_cfg;
+    int ncu;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+    int64_t graph_steps, graph_samples;
+    void* cur() const { return cur_a ? fa : fb; }
+    void* other() const { return cur_a ? fb : fa; }
+};
+
+namespace {
+
+constexpr int N_GRID_CFG = 4;
+constexpr int GRID_PER_CU[N_GRID_CFG] = {8, 4, 16, 2};
+
+template <int LAT, typename Real>
+void batch_launch(flb_batch* b, int cfg, const void* fin, void* fout,
+                  const unsigned long long* step_dev, unsigned long long step_host,
+                  double* partial, hipStream_t st) {
+    CollideParams<Real> P;
+    const flb_params& p = b->p;
+    P.rho0 = (Real)p.rho0;
+    P.lam_bulk = (Real)p.rate_bulk;
+    P.lam_shear = (Real)p.rate_shear;
+    P.lam_ghost = (Real)p.rate_ghost;
+    using LL = Lattice<LAT>;
+    int k = 0;
+    for (int a = LL::D + 1; a < LL::Q; ++a, ++k) {
+        const double lam = LL::cls[a] == CLS_BULK ? p.rate_bulk
+                           : LL::cls[a] == CLS_SHEAR ? p.rate_shear
+                                                     : p.rate_ghost;
+        P.amp[k] = (Real)std::sqrt(p.kT * LL::N[a] * lam * (2.0 - lam) / CS2);
+    }
+    for (; k < KMAX; ++k) P.amp[k] = Real(0);
+    P.noise_on = p.kT > 0.0;
+    P.noise_local = p.noise_rho_local ? 1 : 0;
+    P.key0 = P.key1 = 0;   // per replica
+    P.replica = 0;
+    StepIndex si{step_dev, step_host};
+    const uint32_t grid = std::min<uint32_t>(b->ntiles, (uint32_t)(b->ncu * GRID_PER_CU[cfg]));
+    if (partial)
+        hipLaunchKernelGGL((k_batch_step<LAT, Real, true>), dim3(grid), dim3(BT), 0, st,
+                           (const Real*)fin, (Real*)fout, b->reps_dev, b->tiles_dev, b->ntiles, P,
+                           si, partial);
+    else
+        hipLaunchKernelGGL((k_batch_step<LAT, Real, false>), dim3(grid), dim3(BT), 0, st,
+                           (const Real*)fin, (Real*)fout, b->reps_dev, b->tiles_dev, b->ntiles, P,
+                           si, partial);
+}
+
+hipError_t batch_one(flb_batch* b, int cfg, const void* fin, void* fout,
+                     const unsigned long long* step_dev, unsigned long long step_host,
+                     double* partial, hipStream_t st) {
+    const int lat = b->p.lattice, prec = b->p.precision;
+    if (lat == 0 && prec == 0) batch_launch<0, float>(b, cfg, fin, fout, step_dev, step_host, partial, st);
+    else if (lat == 0) batch_launch<0, double>(b, cfg, fin, fout, step_dev, step_host, partial, st);
+    else if (prec == 0) batch_launch<1, float>(b, cfg, fin, fout, step_dev, step_host, partial, st);
+    else batch_launch<1, double>(b, cfg, fin, fout, step_dev, step_host, partial, st);
+    return hipGetLastError();
+}
+
+flb_status batch_run(flb_batch* b, int64_t nsteps, int32_t stride, bool graph_mode,
+                     hipStream_t st, int64_t* samples) {
+    int64_t ns = 0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const bool sample = stride > 0 && ((k + 1) % stride) == 0;
+        BHIP(batch_one(b, b->grid_cfg, b->cur(), b->other(), graph_mode ? b->ctr_dev : nullptr,
+                       graph_mode ? (unsigned long long)k : (unsigned long long)(b->step + k),
+                       sample ? b->stats : nullptr, st));
+        b->cur_a = !b->cur_a;
+        ns += sample;
+    }
+    if (graph_mode) BHIP(launch_add_u64(b->ctr_dev, (unsigned long long)nsteps, st));
+    *samples = ns;
+    return FLB_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
-flb_status flb_batch_query_sizes(const flb_params*, int32_t, const int32_t*, size_t*, size_t*,
-                                 size_t*) {
-    return FLB_ERR_UNSUPPORTED;
+flb_status flb_batch_query_sizes(const flb_params* base, int32_t nrep, const int32_t* dims,
+                                 size_t* pop_bytes, size_t* scratch_bytes, size_t* stats_bytes) {
+    Layout L;
+    flb_status s = batch_layout(base, nrep, dims, nullptr, &L);
+    if (s != FLB_OK) return s;
+    const size_t rb = base->precision == FLB_FP64 ? 8 : 4;
+    if (pop_bytes) *pop_bytes = align_up(L.elems * rb);
+    if (scratch_bytes) *scratch_bytes = L.scratch_bytes;
+    if (stats_bytes) *stats_bytes = L.stats_bytes;
+    return FLB_OK;
 }
-flb_status flb_batch_init(const flb_params*, int32_t, const int32_t*, const uint64_t*, void*,
-                          void*, void*, void*, void*, flb_batch**) {
-    return FLB_ERR_UNSUPPORTED;
+
+flb_status flb_batch_init(const flb_params* base, int32_t nrep, const int32_t* dims,
+                          const uint64_t* seeds, void* f_a, void* f_b, void* scratch,
+                          void* stats, void* stream, flb_batch** out) {
+    if (!out) return bfail(FLB_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    auto al = [](const void* q) { return q && ((uintptr_t)q % ALIGN) == 0; };
+    if (!al(f_a) || !al(f_b) || !al(scratch) || !al(stats) || f_a == f_b)
+        return bfail(FLB_ERR_INVALID_ARG, "buffers must be distinct, non-NULL, 256-byte aligned");
+    flb_batch* b = new (std::nothrow) flb_batch();
+    if (!b) return bfail(FLB_ERR_INVALID_ARG, "out of host memory");
+    flb_status s = batch_layout(base, nrep, dims, seeds, &b->L);
+    if (s != FLB_OK) {
+        delete b;
+        return s;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    b->p = *base;
+    b->q = base->lattice == FLB_D2Q9 ? 9 : 19;
+    b->nrep = nrep;
+    b->rb = base->precision == FLB_FP64 ? 8 : 4;
+    b->fa = f_a;
+    b->fb = f_b;
+    b->cur_a = true;
+    b->scratch = (char*)scratch;
+    b->stats = (double*)stats;
+    b->reps_dev = (RepInfo*)(b->scratch + b->L.reps_off);
+    b->tiles_dev = (uint32_t*)(b->scratch + b->L.tiles_off);
+    b->ctr_dev = (unsigned long long*)(b->scratch + b->L.ctr_off);
+    b->ntiles = (uint32_t)b->L.tile_rep.size();
+    b->step = base->step0;
+    b->nsamples = 0;
+    b->grid_cfg = 0;
+    b->graph = nullptr;
+    b->gexec = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->reps_dev, b->L.reps.data(), b->L.reps.size() * sizeof(RepInfo),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->tiles_dev, b->L.tile_rep.data(), b->ntiles * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_set_u64(b->ctr_dev, b->step, st);
+    if (e == hipSuccess) e = launch_fill_zero(stats, b->L.stats_bytes, st);
+    if (e == hipSuccess) {
+        const uint32_t grid = std::min<uint32_t>(b->ntiles, 2048);
+        if (b->p.lattice == 0 && b->p.precision == 0)
+            hipLaunchKernelGGL((k_batch_init<0, float>), dim3(grid), dim3(BT), 0, st, (float*)f_a, b->reps_dev, b->tiles_dev, b->ntiles);
+        else if (b->p.lattice == 0)
+            hipLaunchKernelGGL((k_batch_init<0, double>), dim3(grid), dim3(BT), 0, st, (double*)f_a, b->reps_dev, b->tiles_dev, b->ntiles);
+        else if (b->p.precision == 0)
+            hipLaunchKernelGGL((k_batch_init<1, float>), dim3(grid), dim3(BT), 0, st, (float*)f_a, b->reps_dev, b->tiles_dev, b->ntiles);
+        else
+            hipLaunchKernelGGL((k_batch_init<1, double>), dim3(grid), dim3(BT), 0, st, (double*)f_a, b->reps_dev, b->tiles_dev, b->ntiles);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete b;
+        return bfail(FLB_ERR_HIP, "flb_batch_init: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return FLB_OK;
 }
-flb_status flb_batch_step(flb_batch*, int64_t, int32_t, void*) { return FLB_ERR_UNSUPPORTED; }
-flb_status flb_batch_moments(flb_batch*, double*, double*, int64_t*, void*) {
-    return FLB_ERR_UNSUPPORTED;
+
+flb_status flb_batch_step(flb_batch* b, int64_t nsteps, int32_t stats_stride, void* stream) {
+    if (!b) return bfail(FLB_ERR_INVALID_ARG, "batch is NULL");
+    if (nsteps < 0 || stats_stride < 0) return bfail(FLB_ERR_INVALID_ARG, "bad step count");
+    int64_t ns = 0;
+    flb_status s = batch_run(b, nsteps, stats_stride, false, (hipStream_t)stream, &ns);
+    if (s != FLB_OK) return s;
+    b->step += (uint64_t)nsteps;
+    b->nsamples += ns;
+    BHIP(launch_set_u64(b->ctr_dev, b->step, (hipStream_t)stream));
+    return FLB_OK;
 }
-flb_status flb_batch_state(const flb_batch*, void**, void**, uint64_t*) {
-    return FLB_ERR_UNSUPPORTED;
+
+flb_status flb_batch_moments(flb_batch* b, double* mode_sum, double* mode_sumsq,
+                             int64_t* nsamples, void* stream) {
+    if (!b) return bfail(FLB_ERR_INVALID_ARG, "batch is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const int nv = 2 * b->q;
+    double* out = b->stats + (size_t)b->ntiles * nv;
+    hipLaunchKernelGGL(k_batch_finalize, dim3(nv, b->nrep), dim3(256), 0, st, b->stats,
+                       b->reps_dev, nv, out);
+    BHIP(hipGetLastError());
+    std::vector<double> host((size_t)b->nrep * nv);
+    BHIP(hipMemcpyAsync(host.data(), out, host.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    BHIP(hipStreamSynchronize(st));
+    for (int r = 0; r < b->nrep; ++r)
+        for (int a = 0; a < b->q; ++a) {
+            if (mode_sum) mode_sum[r * b->q + a] = host[(size_t)r * nv + a];
+            if (mode_sumsq) mode_sumsq[r * b->q + a] = host[(size_t)r * nv + b->q + a];
+        }
+    if (nsamples) *nsamples = b->nsamples;
+    for (double v : host)
+        if (!std::isfinite(v)) return bfail(FLB_ERR_NONFINITE, "statistics are not finite");
+    return FLB_OK;
 }
-flb_status flb_batch_graph_capture(flb_batch*, int64_t, int32_t, void*) {
-    return FLB_ERR_UNSUPPORTED;
+
+flb_status flb_batch_state(const flb_batch* b, void** cur, void** other, uint64_t* step) {
+    if (!b) return bfail(FLB_ERR_INVALID_ARG, "batch is NULL");
+    if (cur) *cur = b->cur();
+    if (other) *other = b->other();
+    if (step) *step = b->step;
+    return FLB_OK;
 }
-flb_status flb_batch_graph_launch(flb_batch*, void*) { return FLB_ERR_UNSUPPORTED; }
-flb_status flb_batch_destroy(flb_batch*) { return FLB_ERR_UNSUPPORTED; }
-flb_status flb_batch_autotune(flb_batch*, int32_t, int32_t*, double*, void*) {
-    return FLB_ERR_UNSUPPORTED;
+
+flb_status flb_batch_graph_capture(flb_batch* b, int64_t nsteps, int32_t stats_stride,
+                                   void* stream) {
+    if (!b) return bfail(FLB_ERR_INVALID_ARG, "batch is NULL");
+    if (nsteps <= 0 || nsteps % 2 != 0 || stats_stride < 0)
+        return bfail(FLB_ERR_INVALID_ARG, "graph step count must be positive and even");
+    hipStream_t st = (hipStream_t)stream;
+    if (!st) return bfail(FLB_ERR_INVALID_ARG, "graph capture needs a non-null stream");
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    const bool cur_a = b->cur_a;
+    BHIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int64_t ns = 0;
+    flb_status r = batch_run(b, nsteps, stats_stride, true, st, &ns);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    b->cur_a = cur_a;
+    if (r != FLB_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return bfail(FLB_ERR_HIP, "capture: %s", hipGetErrorString(e));
+    b->graph = g;
+    BHIP(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+    b->graph_steps = nsteps;
+    b->graph_samples = ns;
+    return FLB_OK;
+}
+
+flb_status flb_batch_graph_launch(flb_batch* b, void* stream) {
+    if (!b) return bfail(FLB_ERR_INVALID_ARG, "batch is NULL");
+    if (!b->gexec) return bfail(FLB_ERR_STATE, "no graph captured");
+    BHIP(hipGraphLaunch(b->gexec, (hipStream_t)stream));
+    b->step += (uint64_t)b->graph_steps;
+    b->nsamples += b->graph_samples;
+    return FLB_OK;
+}
+
+flb_status flb_batch_autotune(flb_batch* b, int32_t repeats, int32_t* best, double* best_ms,
+                              void* stream) {
+    if (!b) return bfail(FLB_ERR_INVALID_ARG, "batch is NULL");
+    if (repeats < 1) repeats = 1;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    BHIP(hipEventCreate(&e0));
+    BHIP(hipEventCreate(&e1));
+    int bi = b->grid_cfg;
+    float bt = 1e30f;
+    for (int c = 0; c < N_GRID_CFG; ++c) {
+        BHIP(batch_one(b, c, b->cur(), b->other(), nullptr, b->step, nullptr, st));
+        BHIP(hipEventRecord(e0, st));
+        for (int r = 0; r < repeats; ++r)
+            BHIP(batch_one(b, c, b->cur(), b->other(), nullptr, b->step, nullptr, st));
+        BHIP(hipEventRecord(e1, st));
+        BHIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        BHIP(hipEventElapsedTime(&ms, e0, e1));
+        ms /= repeats;
+        if (ms < bt) {
+            bt = ms;
+            bi = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->grid_cfg = bi;
+    if (best) *best = bi;
+    if (best_ms) *best_ms = bt;
+    return FLB_OK;
+}
+
+flb_status flb_batch_destroy(flb_batch* b) {
+    if (!b) return FLB_OK;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    delete b;
+    return FLB_OK;
 }
 
 }  // extern "C"

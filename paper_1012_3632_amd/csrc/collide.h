@@ -56,8 +56,6 @@ struct Moments {
             if (!L::odd[a] && L::T[a][0] != 0) acc = Real(L::T[a][0]) * f[0];
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                constexpr int dummy = 0;
-                (void)dummy;
                 const int t = L::T[a][L::pair[p][0]];
                 if (t == 0) continue;
                 const Real v = L::odd[a] ? d[p] : s[p];
@@ -108,6 +106,38 @@ struct Moments {
             f[j] = Real(L::w[i]) * (E - O);
         }
     }
+
+    // g_i = sum_a T_ai h_a (transpose of the forward transform), pairwise.
+    static __device__ __forceinline__ void transpose(const Real (&h)[Q], Real (&g)[Q]) {
+        {
+            Real acc = Real(0);
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                const int t = L::T[a][0];
+                if (t == 0) continue;
+                if (t == 1) acc += h[a];
+                else if (t == -1) acc -= h[a];
+                else acc += Real(t) * h[a];
+            }
+            g[0] = acc;
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int i = L::pair[p][0], j = L::pair[p][1];
+            Real E = Real(0), O = Real(0);
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                const int t = L::T[a][i];
+                if (t == 0) continue;
+                Real& acc = L::odd[a] ? O : E;
+                if (t == 1) acc += h[a];
+                else if (t == -1) acc -= h[a];
+                else acc += Real(t) * h[a];
+            }
+            g[i] = E + O;
+            g[j] = E - O;
+        }
+    }
 };
 
 // Equilibrium (m^eq) and forcing (m^F) moments of the stress modes.
@@ -150,6 +180,58 @@ template <typename Real> struct Stress<1, Real> {
         mF[3] = u[0] * F[1] + u[1] * F[0];
         mF[4] = u[1] * F[2] + u[2] * F[1];
         mF[5] = u[2] * F[0] + u[0] * F[2];
+    }
+};
+
+// Reverse mode of Stress::eval.  Every stress row has m^eq_k = rho u.G_k u and
+// m^F_k = 2 u.G_k F for a symmetric 3x3 (2x2) matrix G_k, so given the adjoints
+// meq_b, mF_b this adds d/d rho, d/d u and d/d F.
+template <int LAT, typename Real> struct StressAdj;
+
+template <typename Real> struct StressAdj<0, Real> {
+    static __device__ __forceinline__ void apply(Real rho, const Real (&u)[2], const Real (&F)[2],
+                                                 const Real (&meq)[3], const Real (&meq_b)[3],
+                                                 const Real (&mF_b)[3], Real& rho_b,
+                                                 Real (&u_b)[2], Real (&F_b)[2]) {
+        // G_0 = 3 I, G_1 = diag(1, -1), G_2 = offdiag(1/2)
+        const Real Gu[3][2] = {{Real(3) * u[0], Real(3) * u[1]}, {u[0], -u[1]},
+                               {Real(0.5) * u[1], Real(0.5) * u[0]}};
+        const Real GF[3][2] = {{Real(3) * F[0], Real(3) * F[1]}, {F[0], -F[1]},
+                               {Real(0.5) * F[1], Real(0.5) * F[0]}};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            rho_b += meq_b[k] * meq[k] / rho;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                u_b[a] += Real(2) * (rho * meq_b[k] * Gu[k][a] + mF_b[k] * GF[k][a]);
+                F_b[a] += Real(2) * mF_b[k] * Gu[k][a];
+            }
+        }
+    }
+};
+
+template <typename Real> struct StressAdj<1, Real> {
+    static __device__ __forceinline__ void apply(Real rho, const Real (&u)[3], const Real (&F)[3],
+                                                 const Real (&meq)[6], const Real (&meq_b)[6],
+                                                 const Real (&mF_b)[6], Real& rho_b,
+                                                 Real (&u_b)[3], Real (&F_b)[3]) {
+        // G_0 = I, G_1 = diag(2,-1,-1), G_2 = diag(0,1,-1), G_3..5 = offdiag(1/2) xy, yz, zx
+        const Real h = Real(0.5);
+        const Real Gu[6][3] = {{u[0], u[1], u[2]},          {Real(2) * u[0], -u[1], -u[2]},
+                               {Real(0), u[1], -u[2]},      {h * u[1], h * u[0], Real(0)},
+                               {Real(0), h * u[2], h * u[1]}, {h * u[2], Real(0), h * u[0]}};
+        const Real GF[6][3] = {{F[0], F[1], F[2]},          {Real(2) * F[0], -F[1], -F[2]},
+                               {Real(0), F[1], -F[2]},      {h * F[1], h * F[0], Real(0)},
+                               {Real(0), h * F[2], h * F[1]}, {h * F[2], Real(0), h * F[0]}};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            rho_b += meq_b[k] * meq[k] / rho;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                u_b[a] += Real(2) * (rho * meq_b[k] * Gu[k][a] + mF_b[k] * GF[k][a]);
+                F_b[a] += Real(2) * mF_b[k] * Gu[k][a];
+            }
+        }
     }
 };
 

@@ -24,12 +24,15 @@ struct StepSpec {
     int prec;          // 0 FP32, 1 FP64
     int force;         // 0 ideal, 1 Landau
     int nx, ny, nz;
-    double rho0, lam_bulk, lam_shear, lam_ghost;
+    double rho0, kT, lam_bulk, lam_shear, lam_ghost;
     double amp[15];
     int noise_on, noise_local;
     uint32_t key0, key1, replica;
     double a, b, rho_c, kappa, eta;
 };
+
+// Record the text returned by flb_last_error() (api.hip).
+void set_last_error(const char* msg);
 
 int n_configs(int lat, int force);
 TileShape config_shape(int lat, int force, int cfg);

@@ -163,6 +163,10 @@ class Simulation:
     def step(self, nsteps, stats_stride=0, stream=None):
         call("flb_step", self.handle, int(nsteps), int(stats_stride), _stream(stream))
 
+    def seek(self, step, stream=None):
+        """Set the index of the next step (noise counter) without touching the state."""
+        call("flb_seek", self.handle, int(step), _stream(stream))
+
     @property
     def step_index(self):
         s = C.c_uint64()
@@ -258,6 +262,76 @@ class Simulation:
     def close(self):
         if self._h is not None:
             lib.flb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent ideal-gas replicas of uneven size advanced together
+    (one persistent launch per step over a flat tile table)."""
+
+    def __init__(self, params, dims, seeds=None, device="cuda", stream=None):
+        self.params = params
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        self.nrep = len(self.dims)
+        self.device = torch.device(device)
+        d = (C.c_int32 * (3 * self.nrep))(*[v for dd in self.dims for v in dd])
+        self._dims_c = d
+        pop, scr, sta = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        call("flb_batch_query_sizes", C.byref(params.to_c()), self.nrep, d, C.byref(pop),
+             C.byref(scr), C.byref(sta))
+        mk = lambda n: torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
+        self.fa, self.fb = mk(pop.value), mk(pop.value)
+        self.scratch, self.stats = mk(scr.value), mk(sta.value)
+        seeds = list(range(self.nrep)) if seeds is None else [int(s) for s in seeds]
+        sd = (C.c_uint64 * self.nrep)(*seeds)
+        h = C.c_void_p()
+        call("flb_batch_init", C.byref(params.to_c()), self.nrep, d, sd, _ptr(self.fa),
+             _ptr(self.fb), _ptr(self.scratch), _ptr(self.stats), _stream(stream), C.byref(h))
+        self._h = h
+        self._bufs = {self.fa.data_ptr(): self.fa, self.fb.data_ptr(): self.fb}
+        self.sites = [a * b * c for (a, b, c) in self.dims]
+
+    def step(self, nsteps, stats_stride=0, stream=None):
+        call("flb_batch_step", self._h, int(nsteps), int(stats_stride), _stream(stream))
+
+    def graph_capture(self, nsteps, stats_stride=0, stream=None):
+        call("flb_batch_graph_capture", self._h, int(nsteps), int(stats_stride), _stream(stream))
+
+    def graph_launch(self, stream=None):
+        call("flb_batch_graph_launch", self._h, _stream(stream))
+
+    def autotune(self, repeats=3, stream=None):
+        best, ms = C.c_int32(), C.c_double()
+        call("flb_batch_autotune", self._h, int(repeats), C.byref(best), C.byref(ms), _stream(stream))
+        return best.value, ms.value
+
+    def moments(self, stream=None):
+        q = self.params.q
+        s = (C.c_double * (q * self.nrep))()
+        s2 = (C.c_double * (q * self.nrep))()
+        n = C.c_int64()
+        call("flb_batch_moments", self._h, s, s2, C.byref(n), _stream(stream))
+        return (np.array(s[:]).reshape(self.nrep, q), np.array(s2[:]).reshape(self.nrep, q), n.value)
+
+    def replica_state(self, r):
+        """View of replica r's shifted populations, shape (q, nz, ny, nx)."""
+        cur = C.c_void_p()
+        call("flb_batch_state", self._h, C.byref(cur), None, None)
+        buf = self._bufs[cur.value].view(self.params.dtype)
+        q = self.params.q
+        off = q * sum(self.sites[:r])
+        nx, ny, nz = self.dims[r]
+        return buf[off: off + q * self.sites[r]].view(q, nz, ny, nx)
+
+    def close(self):
+        if self._h is not None:
+            lib.flb_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

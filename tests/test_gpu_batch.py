@@ -1,0 +1,106 @@
+"""Batched replicas: each replica of the persistent batched launch equals a
+single-lattice run with its seed and replica index, and against the oracle;
+per-replica statistics; graph replay; the 64-replica workload's FDT check."""
+
+import numpy as np
+import pytest
+import torch
+
+import flb_workloads as W
+from helpers import gpu_params, oracle_params, rel_err
+
+pytestmark = pytest.mark.gpu
+
+C2 = dict(lattice="D3Q19", rho0=1.0, kT=1e-5, rate_bulk=1.2, rate_shear=1.6, rate_ghost=1.0)
+DIMS = [(16, 16, 16), (24, 8, 12), (9, 7, 5), (33, 3, 2), (1, 1, 1), (40, 20, 10)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("lattice", ["D3Q19", "D2Q9"])
+def test_batch_replicas_match_single_runs_and_oracle(precision, lattice):
+    from oracle import flb
+    from paper_1012_3632_amd import Batch, Simulation
+    dims = DIMS if lattice == "D3Q19" else [(nx, ny, 1) for (nx, ny, _) in DIMS]
+    seeds = [11 + 3 * r for r in range(len(dims))]
+    kw = dict(C2, lattice=lattice, precision=precision)
+    b = Batch(gpu_params(**kw), dims, seeds)
+    for cfg in range(1):
+        b.step(12, stats_stride=3)
+    s_b, q_b, n_b = b.moments()
+    assert n_b == 4
+    for r, (nx, ny, nz) in enumerate(dims):
+        single = Simulation(gpu_params(**kw, nx=nx, ny=ny, nz=nz, seed=seeds[r], replica=r))
+        single.step(12, stats_stride=3)
+        got = b.replica_state(r)
+        ref = single.state()
+        assert torch.equal(got, ref), r
+        s1, q1, n1 = single.moments()
+        np.testing.assert_allclose(q_b[r], q1, rtol=1e-12)
+        if r < 3:
+            po = oracle_params(**kw, nx=nx, ny=ny, nz=nz, seed=seeds[r], replica=r)
+            S, _ = flb.run(flb.initial_state(po), po, 12)
+            w = single.populations().numpy()
+            assert rel_err(w, S.numpy()) < (1e-12 if precision == "fp64" else 1e-5)
+
+
+def test_batch_graph_replay_matches_eager():
+    from paper_1012_3632_amd import Batch
+    kw = dict(C2, precision="fp32")
+    a = Batch(gpu_params(**kw), DIMS)
+    c = Batch(gpu_params(**kw), DIMS)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        c.graph_capture(8, stats_stride=1)
+        for k in range(3):
+            a.step(8, stats_stride=1)
+            c.graph_launch()
+            torch.cuda.synchronize()
+            for r in range(len(DIMS)):
+                assert torch.equal(a.replica_state(r), c.replica_state(r)), (k, r)
+    _, qa, na = a.moments()
+    _, qc, nc = c.moments()
+    assert na == nc == 24
+    np.testing.assert_array_equal(qa, qc)
+
+
+def test_batch_autotune_keeps_state():
+    from paper_1012_3632_amd import Batch
+    b = Batch(gpu_params(**C2, precision="fp32"), DIMS)
+    b.step(2)
+    before = [b.replica_state(r).clone() for r in range(len(DIMS))]
+    best, ms = b.autotune(repeats=2)
+    assert ms > 0
+    for r in range(len(DIMS)):
+        assert torch.equal(before[r], b.replica_state(r))
+
+
+def test_batch64_workload_fdt():
+    """The 64-replica workload (edges drawn from {32,...,96}, seeds 0..63,
+    FP32): per-replica mode variances equal rho0 kT N_a / cs2 after burn-in,
+    advanced by captured graphs."""
+    from paper_1012_3632_amd import Batch, lattice_tables
+    wl = W.WORKLOADS["d3q19_batch64"]
+    edges = W.batch_edges(wl["replicas"], wl["edges"], wl["size_seed"])
+    dims = [(e, e, e) for e in edges]
+    kw = dict(C2, precision="fp32", kT=wl["kT"])
+    b = Batch(gpu_params(**kw), dims, seeds=list(range(wl["replicas"])))
+    b.autotune(repeats=2)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b.graph_capture(100, stats_stride=0)
+        for _ in range(3):
+            b.graph_launch()
+        b.graph_capture(100, stats_stride=1)
+        b.graph_launch()
+        b.graph_launch()
+    torch.cuda.synchronize()
+    s, q, n = b.moments()
+    assert n == 200
+    # the statistics were accumulated only during the last two replays
+    N = lattice_tables("D3Q19")["N"]
+    G = kw["kT"] * N * 3
+    for r, e in enumerate(edges):
+        V = e ** 3
+        var = q[r] / (n * V) - (s[r] / (n * V)) ** 2
+        tol = 0.02 if e >= 48 else 0.03
+        np.testing.assert_allclose(var[4:] / G[4:], 1.0, atol=tol, err_msg=f"replica {r} edge {e}")
