@@ -72,8 +72,8 @@ flb_status validate(const flb_params* p) {
         return fail(FLB_ERR_INVALID_ARG, "D2Q9 needs nz = 1 (got %d)", p->nz);
     const double V = (double)p->nx * p->ny * p->nz;
     if (V >= 2147483648.0) return fail(FLB_ERR_INVALID_ARG, "too many sites (%.0f)", V);
-    if ((double)lattice_q(p->lattice) * V * (p->precision ? 8.0 : 4.0) >= 1.0e15)
-        return fail(FLB_ERR_INVALID_ARG, "population buffer too large");
+    if (V * (p->precision ? 8.0 : 4.0) >= 4294967296.0)
+        return fail(FLB_ERR_INVALID_ARG, "a population plane must stay below 4 GiB");
     if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0))
         return fail(FLB_ERR_INVALID_ARG, "rho0 = %g must be positive", p->rho0);
     if (!(p->kT >= 0.0) || !(p->kT < p->rho0 * CS2))

@@ -17,6 +17,18 @@ __device__ __forceinline__ uint32_t site_index(int x, int y, int z, const Geom& 
     return (uint32_t)((z * g.ny + y) * g.nx + x);
 }
 
+// Element idx of a population plane: 32-bit byte offset from the plane base
+// (the plane base is uniform, so the access uses the SGPR-base + 32-bit
+// VGPR-offset global addressing; a plane is below 4 GiB by construction).
+template <typename Real>
+__device__ __forceinline__ Real plane_ld(const Real* __restrict__ base, uint32_t idx) {
+    return *(const Real*)((const char*)base + idx * (uint32_t)sizeof(Real));
+}
+template <typename Real>
+__device__ __forceinline__ void plane_st(Real* __restrict__ base, uint32_t idx, Real v) {
+    *(Real*)((char*)base + idx * (uint32_t)sizeof(Real)) = v;
+}
+
 // f_i(x) = S_i(x - c_i), periodic.
 template <int LAT, typename Real>
 __device__ __forceinline__ void pull(const Real* __restrict__ fin, int x, int y, int z,
@@ -30,7 +42,7 @@ __device__ __forceinline__ void pull(const Real* __restrict__ fin, int x, int y,
         const int sx = L::cx[i] == 0 ? x : (L::cx[i] > 0 ? xm : xp);
         const int sy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? ym : yp);
         const int sz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zm : zp);
-        f[i] = fin[(size_t)i * g.V + (uint32_t)((sz * g.ny + sy) * g.nx + sx)];
+        f[i] = plane_ld(fin + (size_t)i * g.V, (uint32_t)((sz * g.ny + sy) * g.nx + sx));
     }
 }
 

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
         collide_moments<LAT, Real, FORCE>(m, F, zn, P);
         M::inverse(m, f);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) fout[(size_t)i * g.V + site] = f[i];
+        for (int i = 0; i < Q; ++i) plane_st(fout + (size_t)i * g.V, site, f[i]);
     } else if constexpr (STATS) {
 #pragma unroll
         for (int k = 0; k < 2 * Q; ++k) v[k] = 0.0;

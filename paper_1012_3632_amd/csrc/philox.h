@@ -46,13 +46,15 @@ __device__ __forceinline__ double u01d(uint32_t r) {
 }
 
 // Box-Muller on two words: (sqrt(-2 ln u0) cos 2 pi u1, sqrt(-2 ln u0) sin 2 pi u1).
+// FP32 uses the hardware transcendentals directly: v_log_f32 (log2),
+// v_sqrt_f32, and v_sin_f32 / v_cos_f32, which take their argument in
+// revolutions (sin(2 pi x)), so u1 needs no range reduction.
 __device__ __forceinline__ void box_muller(uint32_t r0, uint32_t r1, float& z0, float& z1) {
     const float u0 = u01f(r0), u1 = u01f(r1);
-    const float rad = sqrtf(-2.0f * logf(u0));
-    float s, c;
-    sincospif(2.0f * u1, &s, &c);
-    z0 = rad * c;
-    z1 = rad * s;
+    constexpr float MINUS_2_LN2 = -1.3862943611198906f;   // -2 ln 2
+    const float rad = __builtin_amdgcn_sqrtf(MINUS_2_LN2 * __builtin_amdgcn_logf(u0));
+    z0 = rad * __builtin_amdgcn_cosf(u1);
+    z1 = rad * __builtin_amdgcn_sinf(u1);
 }
 __device__ __forceinline__ void box_muller(uint32_t r0, uint32_t r1, double& z0, double& z1) {
     const double u0 = u01d(r0), u1 = u01d(r1);
