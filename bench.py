@@ -71,7 +71,8 @@ def bench_main(args):
     import flb_workloads as W
     from paper_1012_3632_amd import Params, Simulation
 
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()   # non-null stream: graph capture needs one
+    torch.cuda.set_stream(stream)
     kw = W.params_of("d3q19_128")
     p = Params.from_dict(dict(kw, precision="fp32"))
     V = p.nx * p.ny * p.nz

@@ -29,7 +29,7 @@
  * standard normal z_k from Philox4x32-10 (Salmon et al., SC'11) with counter
  * (site, step, k/4 | tag << 16, replica) and key (seed mod 2^32, seed >> 32),
  * site = x + nx (y + ny z), tag = 0; words r of one block give uniforms
- * ((r >> 8) + 1) 2^-24 (FP32) or (r + 1) 2^-32 (FP64), and Box-Muller pairs
+ * u = (r + 1) 2^-32 (evaluated in the run's precision), and Box-Muller pairs
  * (r0, r1) -> z_{4k}, z_{4k+1} = sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1),
  * (r2, r3) -> z_{4k+2}, z_{4k+3}.
  *

@@ -23,23 +23,27 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
     constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(M0, c0), lo0 = M0 * c0;
-        const uint32_t hi1 = __umulhi(M1, c2), lo1 = M1 * c2;
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        // one 32x32->64 multiply (v_mad_u64_u32) gives both halves of a product
+        const uint64_t p0 = (uint64_t)M0 * c0;
+        const uint64_t p1 = (uint64_t)M1 * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = lo1;
+        c1 = (uint32_t)p1;
         c2 = n2;
-        c3 = lo0;
+        c3 = (uint32_t)p0;
         k0 += W0;
         k1 += W1;
     }
     return Philox4{c0, c1, c2, c3};
 }
 
-// Uniforms in (0, 1]: FP32 from the top 24 bits, FP64 from all 32 bits.
+// Uniforms u = (r + 1) 2^-32 in (0, 1].  FP32 evaluates it as
+// fma(float(r), 2^-32, 2^-32): exact for r < 2^24, so the small-u tail that sets
+// the large Box-Muller radii keeps full 32-bit resolution; larger r round to 24
+// significant bits (r = 2^32 - 1 gives exactly 1).
 __device__ __forceinline__ float u01f(uint32_t r) {
-    return (float)((r >> 8) + 1u) * 0x1.0p-24f;
+    return __builtin_fmaf((float)r, 0x1.0p-32f, 0x1.0p-32f);
 }
 __device__ __forceinline__ double u01d(uint32_t r) {
     return ((double)r + 1.0) * 0x1.0p-32;
