@@ -60,7 +60,7 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
         g.nz = R.nz;
         g.V = R.V;
         const uint32_t s = (t - R.tile0) * BT + threadIdx.x;
-        double v[2 * Q];
+        Real v[2 * Q];
         if (s < R.V) {
             const uint32_t yz = div_small(s, R.inv_nx);
             const int x = (int)(s - yz * (uint32_t)R.nx);
@@ -72,9 +72,8 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
             if constexpr (STATS) {
 #pragma unroll
                 for (int a = 0; a < Q; ++a) {
-                    const double ma = (double)m[a];
-                    v[a] = ma;
-                    v[Q + a] = ma * ma;
+                    v[a] = m[a];
+                    v[Q + a] = m[a] * m[a];
                 }
             }
             Real zn[4 * L::NBLK];
@@ -87,7 +86,7 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
             for (int i = 0; i < Q; ++i) out[(size_t)i * R.V + s] = f[i];
         } else if constexpr (STATS) {
 #pragma unroll
-            for (int k = 0; k < 2 * Q; ++k) v[k] = 0.0;
+            for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
         }
         if constexpr (STATS) {
             block_accumulate<2 * Q, BT>(v, partial + (size_t)t * 2 * Q, lds_stats);

@@ -46,23 +46,52 @@ __device__ __forceinline__ void pull(const Real* __restrict__ fin, int x, int y,
     }
 }
 
-template <typename Real>
-__device__ __forceinline__ Real wave_sum(Real v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+// Wavefront sum with DPP lane shifts (no LDS traffic): four row_shr steps
+// leave each 16-lane row's sum in its lane 15, two row_bcast steps carry the
+// row sums up so that lane 63 holds the total of all 64 lanes.  Disabled or
+// out-of-row source lanes read 0 (old operand 0).  Fixed order, deterministic.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_shift(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_shift(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
-// Reduce NV doubles over the block in a fixed order and add them to slot[0..NV).
-template <int NV, int NT>
-__device__ __forceinline__ void block_accumulate(double (&v)[NV], double* __restrict__ slot,
+// Stage-outer over NV independent values, so consecutive DPP reads never
+// depend on the instruction just before them (no hazard wait states).
+template <int NV, typename Acc>
+__device__ __forceinline__ void wave_sums_to_lane63(Acc (&v)[NV]) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x111, 0xf>(v[k]);   // row_shr:1
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x112, 0xf>(v[k]);   // row_shr:2
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x114, 0xf>(v[k]);   // row_shr:4
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x118, 0xf>(v[k]);   // row_shr:8 (row sums in lane 15)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x142, 0xa>(v[k]);   // row_bcast:15 into rows 1, 3
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x143, 0xc>(v[k]);   // row_bcast:31 into rows 2, 3
+}
+
+// Reduce NV values over the block in a fixed order and add them, in FP64, to
+// slot[0..NV).  Acc is the type of the per-thread values (the wavefront sums
+// are formed in Acc, the cross-wavefront and long-run sums in FP64).
+template <int NV, int NT, typename Acc>
+__device__ __forceinline__ void block_accumulate(Acc (&v)[NV], double* __restrict__ slot,
                                                  double* lds) {
     constexpr int NW = (NT + 63) / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    wave_sums_to_lane63<NV, Acc>(v);
+    if (lane == 63) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const double s = wave_sum(v[k]);
-        if (lane == 0) lds[wave * NV + k] = s;
+        for (int k = 0; k < NV; ++k) lds[wave * NV + k] = (double)v[k];
     }
     __syncthreads();
     if (threadIdx.x < NV) {

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
         if (inside) FT::force(lds_force, lds_force + FT::NR, fp, P.rho0, tx, ty, tz, F);
     }
 
-    double v[2 * Q];
+    Real v[2 * Q];
     if (inside) {
         Real f[Q], m[Q];
         pull<LAT, Real>(fin, x, y, z, g, f);
@@ -84,9 +84,8 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
         if constexpr (STATS) {
 #pragma unroll
             for (int a = 0; a < Q; ++a) {
-                const double ma = (double)m[a];
-                v[a] = ma;
-                v[Q + a] = ma * ma;
+                v[a] = m[a];
+                v[Q + a] = m[a] * m[a];
             }
         }
         const uint32_t site = site_index<LAT>(x, y, z, g);
@@ -99,7 +98,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
         for (int i = 0; i < Q; ++i) plane_st(fout + (size_t)i * g.V, site, f[i]);
     } else if constexpr (STATS) {
 #pragma unroll
-        for (int k = 0; k < 2 * Q; ++k) v[k] = 0.0;
+        for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
     }
     if constexpr (STATS) {
         const uint32_t b = xcd_remap(blockIdx.x, g.nblocks);
