@@ -276,17 +276,21 @@ def copy_probe():
 
 
 def profile_step(args):
+    """Every launch shape of the d3q19_128 step, with and without statistics,
+    a few steps each (for per-kernel hardware counters)."""
     import torch
 
     import flb_workloads as W
     from paper_1012_3632_amd import Params, Simulation
     p = Params.from_dict(dict(W.params_of("d3q19_128"), precision=args.profile_step))
     sim = Simulation(p)
-    best, _ = sim.autotune(repeats=2)
-    sim.step(args.warmup + args.steps, stats_stride=1)
+    n, _ = sim.launch_configs()
+    for cfg in range(n):
+        sim.set_launch(cfg)
+        sim.step(args.steps, stats_stride=1)
+        sim.step(args.steps, stats_stride=0)
     torch.cuda.synchronize()
-    print(json.dumps({"profile_step": args.profile_step, "steps": args.warmup + args.steps,
-                      "launch_config": best}))
+    print(json.dumps({"profile_step": args.profile_step, "configs": n, "steps_each": args.steps}))
 
 
 if __name__ == "__main__":

@@ -178,6 +178,19 @@ flb_status flb_graph_launch(flb_handle* h, void* stream);
 flb_status flb_adjoint_step(flb_handle* h, const void* s_n, const void* abar_np1, void* abar_n,
                             double* grad, uint64_t n, void* stream);
 
+/* Reverse pass over one checkpoint segment [k0, k1) in a single call: the
+ * states S_{k0+1} .. S_{k1-1} are recomputed from s_k0 (device, the state the
+ * step with index k0 starts from) with the forward kernels and kept in `work`
+ * (device, flb_adjoint_segment_bytes(h, k1 - k0) bytes, 256-byte aligned),
+ * together with their densities for the force model; then the adjoint step is
+ * applied for n = k1 - 1 down to k0.  abar (device, Q V reals) holds
+ * dL/dS_{k1} on entry and dL/dS_{k0} on return.  Parameter derivatives are
+ * accumulated as in flb_adjoint_step; grad (host, nullable) behaves the same.
+ * Does not touch the handle's state buffers or step counter. */
+flb_status flb_adjoint_segment(flb_handle* h, const void* s_k0, void* abar, void* work,
+                               uint64_t k0, uint64_t k1, double* grad, void* stream);
+flb_status flb_adjoint_segment_bytes(const flb_handle* h, int64_t nsteps, size_t* bytes);
+
 /* Adjoint seed of the loss of the final density: given S_N (device) and
  * rhobar[V] = dL/drho_N (device, handle precision), where
  * rho_N(x) = rho0 + sum_i delta S_{N,i}(x - c_i), writes abar_N = dL/dS_N

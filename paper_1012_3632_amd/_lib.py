@@ -63,6 +63,8 @@ PROTOS = {
     "flb_graph_launch": [vp, vp],
     "flb_adjoint_step": [vp, vp, vp, vp, P(C.c_double), C.c_uint64, vp],
     "flb_adjoint_density_seed": [vp, vp, vp, vp],
+    "flb_adjoint_segment": [vp, vp, vp, vp, C.c_uint64, C.c_uint64, P(C.c_double), vp],
+    "flb_adjoint_segment_bytes": [vp, C.c_int64, P(C.c_size_t)],
     "flb_density": [vp, vp, vp, vp],
     "flb_destroy": [vp],
     "flb_batch_query_sizes": [P(flb_params), C.c_int32, P(C.c_int32), P(C.c_size_t),

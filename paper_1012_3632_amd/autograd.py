@@ -46,24 +46,15 @@ class FLBRun(torch.autograd.Function):
     def backward(ctx, grad_rho):
         sim, ck, N = ctx.sim, ctx.ck, ctx.nsteps
         abar = sim.adjoint_seed(grad_rho.to(sim.params.dtype).contiguous())
-        spare = torch.empty_like(abar)
         g = np.zeros(4)
+        work = None
         nseg = len(ctx.ckpts)
         for seg in range(nseg - 1, -1, -1):
             k0 = seg * ck
             k1 = min(k0 + ck, N)
-            sim.load_state(ctx.ckpts[seg])
-            sim.seek(k0)
-            states = [ctx.ckpts[seg]]
-            for _ in range(k0, k1 - 1):
-                sim.step(1)
-                states.append(sim.state().clone())
-            for n in range(k1 - 1, k0 - 1, -1):
-                last = (seg == 0 and n == k0)
-                out = sim.adjoint_step(states[n - k0], abar, n, out=spare,
-                                       grad=g if last else None)
-                abar, spare = out, abar
-            del states
+            # one library call per segment: recompute on the GPU, then the reverse sweep
+            work = sim.adjoint_segment(ctx.ckpts[seg], abar, k0, k1, work=work,
+                                       grad=g if seg == 0 else None)
         FLBRun.last_grads = dict(rate_shear=g[0], kT=g[1], rate_bulk=g[2], rate_ghost=g[3])
         dev = grad_rho.device
         return (abar.to(ctx.dtype), torch.tensor(g[0], dtype=torch.float64, device=dev),

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_adj_collide(
     constexpr int Q = L::Q, D = L::D, NT = TX * TY * TZ;
     constexpr int LDS_F = FORCE ? (FT::NR + FT::NM) : 1;
     __shared__ Real lds_force[LDS_F];
-    __shared__ double lds_red[((NT + 63) / 64) * 4];
+    __shared__ double lds_red[4 * ((NT + 63) / 64) * 4];
 
     int x0, y0, z0;
     tile_origin<LAT, TX, TY, TZ>(g, x0, y0, z0);

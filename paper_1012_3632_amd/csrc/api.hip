@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -513,6 +514,63 @@ flb_status flb_adjoint_step(flb_handle* h, const void* s_n, const void* abar_np1
         HIP_TRY(hipMemcpyAsync(host, out, sizeof host, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         for (int k = 0; k < 4; ++k) grad[k] += host[k];
+        HIP_TRY(launch_fill_zero(h->gpartial, (size_t)h->gslots * 4 * sizeof(double), st));
+    }
+    return FLB_OK;
+}
+
+flb_status flb_adjoint_segment_bytes(const flb_handle* h, int64_t nsteps, size_t* bytes) {
+    if (!h || !bytes || nsteps < 1) return fail(FLB_ERR_INVALID_ARG, "bad argument");
+    const size_t plane = align_up((size_t)h->q * h->V * h->real_bytes);
+    const size_t dens = align_up(h->V * h->real_bytes);
+    // nsteps - 1 recomputed states, one spare adjoint buffer, nsteps densities
+    *bytes = (size_t)nsteps * plane + (h->spec.force ? (size_t)nsteps * dens : 0);
+    return FLB_OK;
+}
+
+flb_status flb_adjoint_segment(flb_handle* h, const void* s_k0, void* abar, void* work,
+                               uint64_t k0, uint64_t k1, double* grad, void* stream) {
+    if (!h || !s_k0 || !abar || !work) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    if (k1 <= k0) return fail(FLB_ERR_INVALID_ARG, "empty segment [%llu, %llu)",
+                              (unsigned long long)k0, (unsigned long long)k1);
+    if (!aligned(work)) return fail(FLB_ERR_INVALID_ARG, "work must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t k = (size_t)(k1 - k0);
+    const size_t plane = align_up((size_t)h->q * h->V * h->real_bytes);
+    const size_t dens = align_up(h->V * h->real_bytes);
+    char* w = (char*)work;
+    auto state = [&](size_t j) -> const void* {
+        return j == 0 ? s_k0 : (const void*)(w + (j - 1) * plane);
+    };
+    char* spare = w + (k - 1) * plane;
+    char* dbase = w + k * plane;
+    auto density = [&](size_t j) -> void* { return h->spec.force ? dbase + j * dens : nullptr; };
+    // recompute S_{k0+1} .. S_{k1-1}, keeping each state's density after streaming
+    if (h->spec.force) HIP_TRY(launch_density(h->spec, state(0), density(0), st));
+    for (size_t j = 1; j < k; ++j) {
+        HIP_TRY(launch_step(h->spec, h->cfg, state(j - 1), (void*)state(j), density(j - 1), nullptr,
+                            (unsigned long long)(k0 + j - 1), nullptr, st));
+        if (h->spec.force) HIP_TRY(launch_density(h->spec, state(j), density(j), st));
+    }
+    // reverse sweep: abar and spare alternate
+    void* cur = abar;
+    void* nxt = spare;
+    uint32_t ns = 0;
+    for (size_t j = k; j-- > 0;) {
+        HIP_TRY(launch_adjoint_step(h->spec, state(j), density(j), cur, nxt, h->adj_work,
+                                    (unsigned long long)(k0 + j), h->gpartial, &ns, st));
+        std::swap(cur, nxt);
+    }
+    if (cur != abar)
+        HIP_TRY(hipMemcpyAsync(abar, cur, (size_t)h->q * h->V * h->real_bytes,
+                               hipMemcpyDeviceToDevice, st));
+    if (grad) {
+        double* out = h->gpartial + (size_t)h->gslots * 4;
+        HIP_TRY(launch_stats_finalize(h->gpartial, h->gslots, 4, out, st));
+        double host[4];
+        HIP_TRY(hipMemcpyAsync(host, out, sizeof host, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int q = 0; q < 4; ++q) grad[q] += host[q];
         HIP_TRY(launch_fill_zero(h->gpartial, (size_t)h->gslots * 4 * sizeof(double), st));
     }
     return FLB_OK;

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
     using L = Lattice<LAT>;
     using M = Moments<LAT, Real>;
     constexpr int Q = L::Q, D = L::D;
-    __shared__ double lds_stats[STATS ? (BT / 64) * 2 * Q : 1];
+    __shared__ double lds_stats[STATS ? 4 * (BT / 64) * 2 * Q : 1];
     const uint32_t step = st.get();
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const uint32_t r = tile_rep[t];

@@ -46,58 +46,74 @@ __device__ __forceinline__ void pull(const Real* __restrict__ fin, int x, int y,
     }
 }
 
-// Wavefront sum with DPP lane shifts (no LDS traffic): four row_shr steps
-// leave each 16-lane row's sum in its lane 15, two row_bcast steps carry the
-// row sums up so that lane 63 holds the total of all 64 lanes.  Disabled or
-// out-of-row source lanes read 0 (old operand 0).  Fixed order, deterministic.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_shift(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+// Pull for a wavefront whose lanes share one (y, z) row (y, z uniform, e.g.
+// from readfirstlane): the row offset goes into the uniform plane base
+// (scalar arithmetic) and each lane only adds its x, x - 1 or x + 1.
+template <int LAT, typename Real>
+__device__ __forceinline__ void pull_rows(const Real* __restrict__ fin, int x, int y, int z,
+                                          const Geom& g, Real (&f)[Lattice<LAT>::Q]) {
+    using L = Lattice<LAT>;
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int sx = L::cx[i] == 0 ? x : (L::cx[i] > 0 ? xm : xp);
+        const int sy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? ym : yp);
+        const int sz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zm : zp);
+        const Real* row = fin + ((size_t)i * g.V + (size_t)(uint32_t)((sz * g.ny + sy) * g.nx));
+        f[i] = plane_ld(row, (uint32_t)sx);
+    }
 }
-template <int CTRL, int ROW_MASK>
+
+// Row sums with DPP lane shifts (no LDS traffic): four row_shr steps leave the
+// sum of each 16-lane row in its lane 15.  Out-of-row source lanes read 0 (old
+// operand 0).  Stage-outer over NV independent values, so consecutive DPP reads
+// never depend on the instruction just before them.  Fixed order.
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
 __device__ __forceinline__ double dpp_shift(double v) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
     return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
-// Stage-outer over NV independent values, so consecutive DPP reads never
-// depend on the instruction just before them (no hazard wait states).
 template <int NV, typename Acc>
-__device__ __forceinline__ void wave_sums_to_lane63(Acc (&v)[NV]) {
+__device__ __forceinline__ void row_sums_to_lane15(Acc (&v)[NV]) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x111, 0xf>(v[k]);   // row_shr:1
+    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x111>(v[k]);   // row_shr:1
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x112, 0xf>(v[k]);   // row_shr:2
+    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x112>(v[k]);   // row_shr:2
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x114, 0xf>(v[k]);   // row_shr:4
+    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x114>(v[k]);   // row_shr:4
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x118, 0xf>(v[k]);   // row_shr:8 (row sums in lane 15)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x142, 0xa>(v[k]);   // row_bcast:15 into rows 1, 3
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x143, 0xc>(v[k]);   // row_bcast:31 into rows 2, 3
+    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x118>(v[k]);   // row_shr:8
 }
 
 // Reduce NV values over the block in a fixed order and add them, in FP64, to
-// slot[0..NV).  Acc is the type of the per-thread values (the wavefront sums
-// are formed in Acc, the cross-wavefront and long-run sums in FP64).
+// slot[0..NV).  Acc is the type of the per-thread values (16-lane row sums are
+// formed in Acc; the sums over rows, wavefronts and steps in FP64).  lds must
+// hold 4 * NW * NV doubles (NW wavefronts).  All lanes must be active.
 template <int NV, int NT, typename Acc>
 __device__ __forceinline__ void block_accumulate(Acc (&v)[NV], double* __restrict__ slot,
                                                  double* lds) {
-    constexpr int NW = (NT + 63) / 64;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    wave_sums_to_lane63<NV, Acc>(v);
-    if (lane == 63) {
+    constexpr int NR = 4 * ((NT + 63) / 64);   // 16-lane rows in the block
+    const int lane = threadIdx.x & 63;
+    const int row = threadIdx.x >> 4;
+    row_sums_to_lane15<NV, Acc>(v);
+    if ((lane & 15) == 15) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) lds[wave * NV + k] = (double)v[k];
+        for (int k = 0; k < NV; ++k) lds[row * NV + k] = (double)v[k];
     }
     __syncthreads();
     if (threadIdx.x < NV) {
         double acc = 0.0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) acc += lds[w * NV + threadIdx.x];
+        for (int r = 0; r < NR; ++r) acc += lds[r * NV + threadIdx.x];
         slot[threadIdx.x] += acc;
     }
 }

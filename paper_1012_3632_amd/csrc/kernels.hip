@@ -49,7 +49,7 @@ __global__ void k_density(const Real* __restrict__ fin, Real* __restrict__ out, 
     out[s] = acc;
 }
 
-template <int LAT, typename Real, bool FORCE, bool STATS, int TX, int TY, int TZ>
+template <int LAT, typename Real, bool FORCE, bool STATS, int TX, int TY, int TZ, int SPT>
 __global__ __launch_bounds__(TX* TY* TZ) void k_step(
     const Real* __restrict__ fin, Real* __restrict__ fout, const Real* __restrict__ drho, Geom g,
     CollideParams<Real> P, ForceParams<Real> fp, StepIndex st, double* __restrict__ partial) {
@@ -58,34 +58,51 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
     using FT = ForceTile<LAT, Real, TX, TY, TZ>;
     constexpr int Q = L::Q, D = L::D, NT = TX * TY * TZ;
     constexpr int LDS_F = FORCE ? (FT::NR + FT::NM) : 1;
-    constexpr int LDS_S = STATS ? ((NT + 63) / 64) * 2 * Q : 1;
+    constexpr int LDS_S = STATS ? 4 * ((NT + 63) / 64) * 2 * Q : 1;
     __shared__ Real lds_force[LDS_F];
     __shared__ double lds_stats[LDS_S];
 
+    static_assert(!FORCE || SPT == 1, "the force tile covers one site per thread");
+    // with TX a multiple of 64 every wavefront lies in one (y, z) row
+    constexpr bool ROWS = (TX % 64) == 0;
     int x0, y0, z0;
-    tile_origin<LAT, TX, TY, TZ>(g, x0, y0, z0);
-    const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
-    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
-    const bool inside = x < g.nx && y < g.ny && z < g.nz;
+    tile_origin<LAT, TX, TY * SPT, TZ>(g, x0, y0, z0);
+    const int tx = threadIdx.x % TX;
+    int ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
+    if constexpr (ROWS) {
+        ty = __builtin_amdgcn_readfirstlane(ty);
+        tz = __builtin_amdgcn_readfirstlane(tz);
+    }
+    const int x = x0 + tx, z = z0 + tz;
 
     Real F[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) F[a] = Real(0);
     if constexpr (FORCE) {
         FT::stage(drho, g, fp, x0, y0, z0, lds_force, lds_force + FT::NR);
-        if (inside) FT::force(lds_force, lds_force + FT::NR, fp, P.rho0, tx, ty, tz, F);
+        if (x < g.nx && y0 + ty < g.ny && z < g.nz)
+            FT::force(lds_force, lds_force + FT::NR, fp, P.rho0, tx, ty, tz, F);
     }
 
     Real v[2 * Q];
+    if constexpr (STATS) {
+#pragma unroll
+        for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
+    }
+#pragma unroll
+    for (int sp = 0; sp < SPT; ++sp) {
+    const int y = y0 + ty + sp * TY;
+    const bool inside = x < g.nx && y < g.ny && z < g.nz;
     if (inside) {
         Real f[Q], m[Q];
-        pull<LAT, Real>(fin, x, y, z, g, f);
+        if constexpr (ROWS) pull_rows<LAT, Real>(fin, x, y, z, g, f);
+        else pull<LAT, Real>(fin, x, y, z, g, f);
         M::forward(f, m);
         if constexpr (STATS) {
 #pragma unroll
             for (int a = 0; a < Q; ++a) {
-                v[a] = m[a];
-                v[Q + a] = m[a] * m[a];
+                v[a] += m[a];
+                v[Q + a] += m[a] * m[a];
             }
         }
         const uint32_t site = site_index<LAT>(x, y, z, g);
@@ -94,11 +111,15 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
             site_normals<L::NBLK, Real>(site, st.get(), 0u, P.replica, P.key0, P.key1, zn);
         collide_moments<LAT, Real, FORCE>(m, F, zn, P);
         M::inverse(m, f);
+        if constexpr (ROWS) {
+            const size_t row = (size_t)(uint32_t)((z * g.ny + y) * g.nx);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) plane_st(fout + (size_t)i * g.V, site, f[i]);
-    } else if constexpr (STATS) {
+            for (int i = 0; i < Q; ++i) plane_st(fout + ((size_t)i * g.V + row), (uint32_t)x, f[i]);
+        } else {
 #pragma unroll
-        for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
+            for (int i = 0; i < Q; ++i) plane_st(fout + (size_t)i * g.V, site, f[i]);
+        }
+    }
     }
     if constexpr (STATS) {
         const uint32_t b = xcd_remap(blockIdx.x, g.nblocks);
@@ -209,8 +230,9 @@ static Geom make_geom(const StepSpec& s, TileShape t) {
     g.nx = s.nx;
     g.ny = s.ny;
     g.nz = s.nz;
+    const int ty = t.ty * (t.spt > 1 ? t.spt : 1);
     g.nbx = (s.nx + t.tx - 1) / t.tx;
-    g.nby = (s.ny + t.ty - 1) / t.ty;
+    g.nby = (s.ny + ty - 1) / ty;
     g.nbz = (s.nz + t.tz - 1) / t.tz;
     g.nblocks = (uint32_t)g.nbx * g.nby * g.nbz;
     g.V = (uint32_t)s.nx * s.ny * s.nz;
@@ -259,7 +281,7 @@ hipError_t launch_init(const StepSpec& s, void* f, const double* drho, hipStream
 }
 
 hipError_t launch_density(const StepSpec& s, const void* fin, void* out, hipStream_t st) {
-    const Geom g = make_geom(s, TileShape{1, 1, 1});
+    const Geom g = make_geom(s, TileShape{1, 1, 1, 1});
     const dim3 grid((g.V + 255) / 256), block(256);
     if (s.lat == 0 && s.prec == 0) hipLaunchKernelGGL((k_density<0, float>), grid, block, 0, st, (const float*)fin, (float*)out, g);
     else if (s.lat == 0) hipLaunchKernelGGL((k_density<0, double>), grid, block, 0, st, (const double*)fin, (double*)out, g);
@@ -268,18 +290,18 @@ hipError_t launch_density(const StepSpec& s, const void* fin, void* out, hipStre
     return hipGetLastError();
 }
 
-template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ>
+template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ, int SPT = 1>
 static void step_tile(const StepSpec& s, const void* fin, void* fout, const void* drho,
                       StepIndex si, double* partial, hipStream_t st) {
-    const Geom g = make_geom(s, TileShape{TX, TY, TZ});
+    const Geom g = make_geom(s, TileShape{TX, TY, TZ, SPT});
     const dim3 grid(g.nblocks), block(TX * TY * TZ);
     const CollideParams<Real> P = collide_params<Real>(s);
     const ForceParams<Real> fp = force_params<Real>(s);
     if (partial)
-        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, true, TX, TY, TZ>), grid, block, 0, st,
+        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, true, TX, TY, TZ, SPT>), grid, block, 0, st,
                            (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
     else
-        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, false, TX, TY, TZ>), grid, block, 0, st,
+        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, false, TX, TY, TZ, SPT>), grid, block, 0, st,
                            (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
 }
 
@@ -288,10 +310,14 @@ static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fou
                           const void* drho, StepIndex si, double* partial, hipStream_t st) {
     if (!s.force) {
         switch (cfg) {
-            case 0: step_tile<LAT, Real, false, 64, 4, 1>(s, fin, fout, drho, si, partial, st); break;
-            case 1: step_tile<LAT, Real, false, 128, 2, 1>(s, fin, fout, drho, si, partial, st); break;
-            case 2: step_tile<LAT, Real, false, 256, 1, 1>(s, fin, fout, drho, si, partial, st); break;
-            default: step_tile<LAT, Real, false, 32, 8, 1>(s, fin, fout, drho, si, partial, st); break;
+            case 0: step_tile<LAT, Real, false, 64, 4, 1, 1>(s, fin, fout, drho, si, partial, st); break;
+            case 1: step_tile<LAT, Real, false, 128, 2, 1, 1>(s, fin, fout, drho, si, partial, st); break;
+            case 2: step_tile<LAT, Real, false, 256, 1, 1, 1>(s, fin, fout, drho, si, partial, st); break;
+            case 3: step_tile<LAT, Real, false, 32, 8, 1, 1>(s, fin, fout, drho, si, partial, st); break;
+            case 4: step_tile<LAT, Real, false, 128, 2, 1, 2>(s, fin, fout, drho, si, partial, st); break;
+            case 5: step_tile<LAT, Real, false, 64, 4, 1, 2>(s, fin, fout, drho, si, partial, st); break;
+            case 6: step_tile<LAT, Real, false, 128, 2, 1, 4>(s, fin, fout, drho, si, partial, st); break;
+            default: step_tile<LAT, Real, false, 256, 1, 1, 2>(s, fin, fout, drho, si, partial, st); break;
         }
     } else if constexpr (LAT == 1) {
         switch (cfg) {
@@ -323,7 +349,7 @@ template <int LAT, typename Real, bool FORCE>
 static void fields_launch(const StepSpec& s, const void* fin, const void* drho, void* out,
                           hipStream_t st) {
     constexpr int TX = (LAT == 1) ? 32 : 64, TY = 4, TZ = (LAT == 1) ? 2 : 1;
-    const Geom g = make_geom(s, TileShape{TX, TY, TZ});
+    const Geom g = make_geom(s, TileShape{TX, TY, TZ, 1});
     hipLaunchKernelGGL((k_fields<LAT, Real, FORCE, TX, TY, TZ>), dim3(g.nblocks),
                        dim3(TX * TY * TZ), 0, st, (const Real*)fin, (const Real*)drho, (Real*)out,
                        g, (Real)s.rho0, force_params<Real>(s));

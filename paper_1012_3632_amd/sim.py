@@ -259,6 +259,25 @@ class Simulation:
             grad[:] = np.array(g[:])
         return out
 
+    def adjoint_segment(self, s_k0, abar, k0, k1, work=None, grad=None, stream=None):
+        """In place: abar = dL/dS_{k1} -> dL/dS_{k0}, recomputing the segment's
+        states from s_k0 on the GPU.  ``work`` may be a preallocated uint8
+        device tensor of at least adjoint_segment_bytes(k1 - k0) bytes."""
+        need = self.adjoint_segment_bytes(k1 - k0)
+        if work is None or work.numel() < need:
+            work = torch.empty(need, dtype=torch.uint8, device=self.device)
+        g = (C.c_double * 4)(*grad) if grad is not None else None
+        call("flb_adjoint_segment", self.handle, _ptr(s_k0.contiguous()), _ptr(abar), _ptr(work),
+             int(k0), int(k1), g, _stream(stream))
+        if grad is not None:
+            grad[:] = np.array(g[:])
+        return work
+
+    def adjoint_segment_bytes(self, nsteps):
+        n = C.c_size_t()
+        call("flb_adjoint_segment_bytes", self.handle, int(nsteps), C.byref(n))
+        return n.value
+
     def close(self):
         if self._h is not None:
             lib.flb_destroy(self._h)

@@ -35,7 +35,8 @@ def test_batch_replicas_match_single_runs_and_oracle(precision, lattice):
         ref = single.state()
         assert torch.equal(got, ref), r
         s1, q1, n1 = single.moments()
-        np.testing.assert_allclose(q_b[r], q1, rtol=1e-12)
+        # FP32 runs form wavefront sums in FP32 over differently shaped tiles
+        np.testing.assert_allclose(q_b[r], q1, rtol=1e-12 if precision == "fp64" else 1e-6)
         if r < 3:
             po = oracle_params(**kw, nx=nx, ny=ny, nz=nz, seed=seeds[r], replica=r)
             S, _ = flb.run(flb.initial_state(po), po, 12)
