@@ -31,25 +31,28 @@ HBM_PEAK_GBS = 8000.0
 
 def src_hash():
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1012_3632_amd", "csrc", "*"))):
+    # the step kernel's device sources: kernels.hip and the headers it includes
+    csrc = os.path.join(ROOT, "paper_1012_3632_amd", "csrc")
+    for p in [os.path.join(csrc, "kernels.hip")] + sorted(glob.glob(os.path.join(csrc, "*.h"))):
         h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 
 
 def traffic_from_profiles(kernel_key):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel sources."""
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy)
+    from the committed rocprofv3 counter summary, or None if the counters were
+    taken on other kernel sources than the ones built now."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
-        e = d.get(kernel_key)
-        if e and e.get("src_hash") == src_hash():
-            return e["bytes_per_launch"]
+        if d.get("src_hash") != src_hash():
+            return None
+        v = d["bytes_per_launch"].get(kernel_key)
+        return None if v is None else round(v)
     except Exception:
         return None
-    return None
 
 
 def time_steps(sim, steps, stride, stream):
@@ -101,10 +104,12 @@ def bench_main(args):
         "data": "synthetic",
         "config": {"workload": "d3q19_128 ideal-gas FLB, 128^3 periodic, FP32 shifted storage, "
                                "rates 1.2/1.6/1.0, kT 1e-5, seed 7, FP64 statistics every step",
-                   "lattice": "D3Q19", "sites": V, "launch_config": best_cfg},
+                   "lattice": "D3Q19", "sites": V, "launch_config": best_cfg,
+                   "launch_shape": list(sim.launch_shape(best_cfg))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profiles("k_step_d3q19_fp32_stats"),
+                     "traffic": traffic_from_profiles(
+                         "k_step_d3q19_fp32_stats_%dx%dx%dx%d" % sim.launch_shape(best_cfg)),
                      "kernel": "k_step<D3Q19,float,ideal,stats>",
                      "bytes_per_site": bytes_site},
         "wall_timed_s": round(wall, 3),

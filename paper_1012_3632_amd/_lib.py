@@ -80,6 +80,7 @@ PROTOS = {
     "flb_autotune": [vp, C.c_int32, P(C.c_int32), P(C.c_double), vp],
     "flb_set_launch": [vp, C.c_int32],
     "flb_launch_configs": [vp, P(C.c_int32), P(C.c_int32)],
+    "flb_launch_shape": [vp, C.c_int32, P(C.c_int32)],
     "flb_batch_autotune": [vp, C.c_int32, P(C.c_int32), P(C.c_double), vp],
 }
 

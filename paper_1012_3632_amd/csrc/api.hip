@@ -490,6 +490,18 @@ flb_status flb_launch_configs(const flb_handle* h, int32_t* count, int32_t* curr
     return FLB_OK;
 }
 
+flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape) {
+    if (!h || !shape) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    if (config < 0 || config >= n_configs(h->spec.lat, h->spec.force))
+        return fail(FLB_ERR_INVALID_ARG, "launch config %d out of range", config);
+    const TileShape t = config_shape(h->spec.lat, h->spec.force, config);
+    shape[0] = t.tx;
+    shape[1] = t.ty;
+    shape[2] = t.tz;
+    shape[3] = t.spt;
+    return FLB_OK;
+}
+
 flb_status flb_adjoint_density_seed(flb_handle* h, const void* rhobar, void* abar_N,
                                     void* stream) {
     if (!h || !rhobar || !abar_N) return fail(FLB_ERR_INVALID_ARG, "NULL argument");

@@ -238,6 +238,12 @@ class Simulation:
         call("flb_launch_configs", self.handle, C.byref(n), C.byref(cur))
         return n.value, cur.value
 
+    def launch_shape(self, config):
+        """(tx, ty, tz, sites_per_thread) of a launch configuration."""
+        sh = (C.c_int32 * 4)()
+        call("flb_launch_shape", self.handle, int(config), sh)
+        return tuple(sh[:])
+
     def adjoint_seed(self, rhobar, stream=None):
         p = self.params
         out = torch.empty((p.q,) + p.shape, dtype=p.dtype, device=self.device)
