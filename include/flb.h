@@ -27,11 +27,13 @@
  *
  * Noise: every non-conserved mode a (in basis order, k = a - d - 1) draws a
  * standard normal z_k from Philox4x32-10 (Salmon et al., SC'11) with counter
- * (site, step, k/4 | tag << 16, replica) and key (seed mod 2^32, seed >> 32),
- * site = x + nx (y + ny z), tag = 0; words r of one block give uniforms
- * u = (r + 1) 2^-32 (evaluated in the run's precision), and Box-Muller pairs
- * (r0, r1) -> z_{4k}, z_{4k+1} = sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1),
- * (r2, r3) -> z_{4k+2}, z_{4k+3}.
+ * (site, step, block | tag << 16, replica) and key (seed mod 2^32, seed >> 32),
+ * site = x + nx (y + ny z), tag = 0.  The words w_0, w_1, ... of blocks 0, 1, ...
+ * feed P = ceil(K/2) Box-Muller pairs: pair p has radius
+ * sqrt(-2 ln u), u = (w_p + 1) 2^-32 (in the run's precision), and angle
+ * 2 pi (h + 1) 2^-16 with h the high (p even) or low (p odd) half of
+ * w_{P + p/2}; z_{2p}, z_{2p+1} = radius (cos, sin) of the angle.  D3Q19 uses
+ * 3 blocks per site-step, D2Q9 2.
  *
  * Storage: populations are stored shifted, delta f_i = f_i - w_i rho0, in
  * structure-of-arrays order f[i * V + site] (V = nx ny nz sites, x fastest),

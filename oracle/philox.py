@@ -14,11 +14,15 @@ not fix one.  This build fixes the draw as follows, on both sides:
   (0x9E3779B9, 0xBB67AE85) between rounds; 10 rounds.
 * counter (site, step, block | tag << 16, replica), key (seed mod 2^32,
   seed >> 32), site = x + nx*(y + ny*z).
-* uniform u = (r + 1) * 2^-32 in (0, 1] (FP64 convention).
-* Box-Muller: words (r0, r1, r2, r3) of one block give
-  z0, z1 = sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1),
-  z2, z3 = sqrt(-2 ln u2) (cos 2 pi u3, sin 2 pi u3).
-  Normal number 4*block + k drives the k-th non-conserved mode in basis order.
+* Box-Muller pairs: pair p takes a full 32-bit word r for its radius,
+  R = sqrt(-2 ln u), u = (r + 1) 2^-32 in (0, 1], and 16 bits h for its angle,
+  theta = 2 pi v, v = (h + 1) 2^-16; (z_2p, z_2p+1) = R (cos theta, sin theta).
+  With P = ceil(K/2) pairs for K normals, the words w_0, w_1, ... are the
+  outputs of blocks 0, 1, ... in order; pair p uses w_p for its radius and
+  w_{P + p//2} for its angle (high half for even p, low half for odd p).  A
+  D3Q19 site (K = 15) thus needs 12 words (3 blocks), a D2Q9 site (K = 6) 5
+  words (2 blocks).  Normal number k drives the k-th non-conserved mode in
+  basis order.
 
 Pinned by: an independent library implementation of the same bijection
 (rocRAND's host-callable ``ten_rounds``) compared word for word in the tests,
@@ -79,22 +83,25 @@ def uniform(r):
     return (np.asarray(r, dtype=np.float64) + 1.0) * 2.0 ** -32
 
 
-def box_muller(words):
-    """Map one block of words (4, n) to four normals (4, n), FP64."""
-    u0, u1, u2, u3 = (uniform(words[k]) for k in range(4))
-    r01 = np.sqrt(-2.0 * np.log(u0))
-    r23 = np.sqrt(-2.0 * np.log(u2))
-    t1 = 2.0 * np.pi * u1
-    t3 = 2.0 * np.pi * u3
-    return np.stack([r01 * np.cos(t1), r01 * np.sin(t1), r23 * np.cos(t3), r23 * np.sin(t3)])
+def pair_normals(r, h):
+    """Box-Muller on a radius word r (uint32 array) and 16-bit angles h:
+    returns (R cos theta, R sin theta), FP64."""
+    R = np.sqrt(-2.0 * np.log(uniform(r)))
+    theta = 2.0 * np.pi * ((np.asarray(h, dtype=np.float64) + 1.0) * 2.0 ** -16)
+    return R * np.cos(theta), R * np.sin(theta)
 
 
 def normals(nsites, step, count, seed, tag=0, replica=0):
-    """``count`` standard normals per site for sites 0..nsites-1: shape (count, nsites).
-
-    Normal k comes from block k // 4, position k % 4.
-    """
+    """``count`` standard normals per site for sites 0..nsites-1: shape (count, nsites)."""
     sites = np.arange(nsites, dtype=np.uint64)
-    nblk = (count + 3) // 4
-    out = [box_muller(block_words(sites, step, b, seed, tag, replica)) for b in range(nblk)]
-    return np.concatenate(out, axis=0)[:count]
+    npair = (count + 1) // 2
+    nword = npair + (npair + 1) // 2
+    nblk = (nword + 3) // 4
+    words = np.concatenate([block_words(sites, step, b, seed, tag, replica) for b in range(nblk)])
+    out = []
+    for p in range(npair):
+        a = words[npair + p // 2]
+        h = (a >> np.uint32(16)) if p % 2 == 0 else (a & np.uint32(0xFFFF))
+        c, s = pair_normals(words[p], h)
+        out += [c, s]
+    return np.stack(out)[:count]

@@ -133,8 +133,8 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_adj_collide(
         pull<LAT, Real>(s_n, x, y, z, g, f);
         M::forward(f, m);
         const uint32_t site = (uint32_t)((z * g.ny + y) * g.nx + x);
-        Real zn[4 * L::NBLK];
-        if (P.noise_on) site_normals<L::NBLK, Real>(site, step, 0u, P.replica, P.key0, P.key1, zn);
+        Real zn[2 * L::NPAIR];
+        if (P.noise_on) site_normals<L::NPAIR, Real>(site, step, 0u, P.replica, P.key0, P.key1, zn);
         Real ab[Q], mbs[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) ab[i] = Real(L::w[i]) * abar[(size_t)i * g.V + site];

@@ -76,8 +76,8 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
                     v[Q + a] = m[a] * m[a];
                 }
             }
-            Real zn[4 * L::NBLK];
-            if (P.noise_on) site_normals<L::NBLK, Real>(s, step, 0u, r, R.key0, R.key1, zn);
+            Real zn[2 * L::NPAIR];
+            if (P.noise_on) site_normals<L::NPAIR, Real>(s, step, 0u, r, R.key0, R.key1, zn);
             const Real F[D] = {};
             collide_moments<LAT, Real, false>(m, F, zn, P);
             M::inverse(m, f);

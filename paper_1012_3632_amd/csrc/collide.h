@@ -43,7 +43,11 @@ struct Moments {
     static constexpr int NP = L::NP;
 
     // m_a = sum_i T_ai f_i via opposite-pair sums and differences.
-    static __device__ __forceinline__ void forward(const Real (&f)[Q], Real (&m)[Q]) {
+    static __host__ __device__ __forceinline__ void forward(const Real (&f)[Q], Real (&m)[Q]) {
+        if constexpr (LAT == 1) {
+            forward19(f, m);
+            return;
+        }
         Real s[NP], d[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
@@ -68,7 +72,11 @@ struct Moments {
     }
 
     // f_i = w_i sum_a T_ai m_a / N_a, pairwise: f_i = w (E + O), f_ibar = w (E - O).
-    static __device__ __forceinline__ void inverse(const Real (&m)[Q], Real (&f)[Q]) {
+    static __host__ __device__ __forceinline__ void inverse(const Real (&m)[Q], Real (&f)[Q]) {
+        if constexpr (LAT == 1) {
+            inverse19(m, f);
+            return;
+        }
         Real mt[Q];
 #pragma unroll
         for (int a = 0; a < Q; ++a) mt[a] = m[a] * Real(1.0 / L::N[a]);
@@ -107,8 +115,117 @@ struct Moments {
         }
     }
 
+    // D3Q19 forward transform with the sub-sums shared between the rows of
+    // the basis (same result as the table, fewer additions).  Pair sums s and
+    // differences d: axes A*/a*, plane edges P (++ with --), M (+- with -+).
+    static __host__ __device__ __forceinline__ void forward19(const Real (&f)[Q], Real (&m)[Q]) {
+        const Real Ax = f[1] + f[2], ax = f[1] - f[2];
+        const Real Ay = f[3] + f[4], ay = f[3] - f[4];
+        const Real Az = f[5] + f[6], az = f[5] - f[6];
+        const Real Pxy = f[7] + f[10], dPxy = f[7] - f[10];
+        const Real Mxy = f[8] + f[9], dMxy = f[8] - f[9];
+        const Real Pxz = f[11] + f[14], dPxz = f[11] - f[14];
+        const Real Mxz = f[12] + f[13], dMxz = f[12] - f[13];
+        const Real Pyz = f[15] + f[18], dPyz = f[15] - f[18];
+        const Real Myz = f[16] + f[17], dMyz = f[16] - f[17];
+        // even rows
+        const Real Exy = Pxy + Mxy, Exz = Pxz + Mxz, Eyz = Pyz + Myz;
+        const Real A = Ax + (Ay + Az);
+        const Real E = Exy + Exz + Eyz;
+        m[0] = f[0] + A + E;                               // 1
+        m[4] = E - f[0];                                   // c^2 - 1
+        m[16] = f[0] + E - Real(2) * A;                    // 3c^4 - 6c^2 + 1
+        const Real a5 = Real(2) * Ax - (Ay + Az);
+        const Real a6 = Ay - Az;
+        const Real B = (Exy + Exz) - Real(2) * Eyz;
+        const Real Cc = Exy - Exz;
+        m[5] = B + a5;                                     // 3cx^2 - c^2
+        m[17] = B - a5;                                    // (2c^2 - 3)(3cx^2 - c^2)
+        m[6] = Cc + a6;                                    // cy^2 - cz^2
+        m[18] = Cc - a6;                                   // (2c^2 - 3)(cy^2 - cz^2)
+        m[7] = Pxy - Mxy;                                  // cx cy
+        m[8] = Pyz - Myz;                                  // cy cz
+        m[9] = Pxz - Mxz;                                  // cz cx
+        // odd rows
+        const Real X1 = dPxy + dMxy, X2 = dPxz + dMxz;     // cx-odd edge parts
+        const Real Y1 = dPxy - dMxy, Y2 = dPyz + dMyz;     // cy-odd edge parts
+        const Real Z1 = dPxz - dMxz, Z2 = dPyz - dMyz;     // cz-odd edge parts
+        const Real SX = X1 + X2, SY = Y1 + Y2, SZ = Z1 + Z2;
+        m[1] = ax + SX;                                    // cx
+        m[2] = ay + SY;
+        m[3] = az + SZ;
+        m[10] = SX - Real(2) * ax;                         // (3c^2 - 5) cx
+        m[11] = SY - Real(2) * ay;
+        m[12] = SZ - Real(2) * az;
+        m[13] = X1 - X2;                                   // (cy^2 - cz^2) cx
+        m[14] = Y2 - Y1;                                   // (cz^2 - cx^2) cy
+        m[15] = Z1 - Z2;                                   // (cx^2 - cy^2) cz
+    }
+
+    // D3Q19 inverse f_i = w_i sum_a T_ai m_a / N_a with shared sub-sums: for
+    // every opposite pair the even-row part E and odd-row part O, then
+    // f_i = w (E + O), f_ibar = w (E - O).
+    static __host__ __device__ __forceinline__ void inverse19(const Real (&m)[Q], Real (&f)[Q]) {
+        Real t[Q];
+#pragma unroll
+        for (int a = 0; a < Q; ++a) t[a] = m[a] * Real(1.0 / L::N[a]);
+        const Real G = t[0] - Real(2) * t[16];
+        const Real H = t[17] - t[5];
+        const Real K = t[6] - t[18];
+        f[0] = Real(L::w[0]) * (t[0] - t[4] + t[16]);
+        const Real Ex = G - Real(2) * H;
+        const Real Ey = G + H + K;
+        const Real Ez = G + H - K;
+        const Real Ox = t[1] - Real(2) * t[10];
+        const Real Oy = t[2] - Real(2) * t[11];
+        const Real Oz = t[3] - Real(2) * t[12];
+        const Real wa = Real(L::w[1]);
+        f[1] = wa * (Ex + Ox);
+        f[2] = wa * (Ex - Ox);
+        f[3] = wa * (Ey + Oy);
+        f[4] = wa * (Ey - Oy);
+        f[5] = wa * (Ez + Oz);
+        f[6] = wa * (Ez - Oz);
+        const Real Ec = t[0] + t[4] + t[16];
+        const Real U = t[5] + t[17], W = t[6] + t[18];
+        const Real EcU = Ec + U;
+        const Real Bxy = EcU + W, Bxz = EcU - W, Byz = Ec - Real(2) * U;
+        const Real Sx = t[1] + t[10], Sy = t[2] + t[11], Sz = t[3] + t[12];
+        const Real we = Real(L::w[7]);
+        // xy plane: 7 (+,+) / 10 (-,-), 8 (+,-) / 9 (-,+)
+        {
+            const Real E7 = Bxy + t[7], E8 = Bxy - t[7];
+            const Real O7 = (Sx + Sy) + (t[13] - t[14]);
+            const Real O8 = (Sx - Sy) + (t[13] + t[14]);
+            f[7] = we * (E7 + O7);
+            f[10] = we * (E7 - O7);
+            f[8] = we * (E8 + O8);
+            f[9] = we * (E8 - O8);
+        }
+        // xz plane: 11 (+,+) / 14, 12 (+,-) / 13
+        {
+            const Real E11 = Bxz + t[9], E12 = Bxz - t[9];
+            const Real O11 = (Sx + Sz) + (t[15] - t[13]);
+            const Real O12 = (Sx - Sz) - (t[13] + t[15]);
+            f[11] = we * (E11 + O11);
+            f[14] = we * (E11 - O11);
+            f[12] = we * (E12 + O12);
+            f[13] = we * (E12 - O12);
+        }
+        // yz plane: 15 (+,+) / 18, 16 (+,-) / 17
+        {
+            const Real E15 = Byz + t[8], E16 = Byz - t[8];
+            const Real O15 = (Sy + Sz) + (t[14] - t[15]);
+            const Real O16 = (Sy - Sz) + (t[14] + t[15]);
+            f[15] = we * (E15 + O15);
+            f[18] = we * (E15 - O15);
+            f[16] = we * (E16 + O16);
+            f[17] = we * (E16 - O16);
+        }
+    }
+
     // g_i = sum_a T_ai h_a (transpose of the forward transform), pairwise.
-    static __device__ __forceinline__ void transpose(const Real (&h)[Q], Real (&g)[Q]) {
+    static __host__ __device__ __forceinline__ void transpose(const Real (&h)[Q], Real (&g)[Q]) {
         {
             Real acc = Real(0);
 #pragma unroll

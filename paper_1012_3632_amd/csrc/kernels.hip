@@ -106,9 +106,9 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
             }
         }
         const uint32_t site = site_index<LAT>(x, y, z, g);
-        Real zn[4 * L::NBLK];
+        Real zn[2 * L::NPAIR];
         if (P.noise_on)
-            site_normals<L::NBLK, Real>(site, st.get(), 0u, P.replica, P.key0, P.key1, zn);
+            site_normals<L::NPAIR, Real>(site, st.get(), 0u, P.replica, P.key0, P.key1, zn);
         collide_moments<LAT, Real, FORCE>(m, F, zn, P);
         M::inverse(m, f);
         if constexpr (ROWS) {

@@ -31,7 +31,7 @@ template <> struct Lattice<0> {
     static constexpr int D = 2;
     static constexpr int NP = 4;          // opposite pairs
     static constexpr int K = 6;           // non-conserved modes
-    static constexpr int NBLK = 2;        // Philox blocks per site-step
+    static constexpr int NPAIR = 3;       // Box-Muller pairs per site-step (K normals)
     static constexpr int cx[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     static constexpr int cy[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
     static constexpr int cz[Q] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -62,7 +62,7 @@ template <> struct Lattice<1> {
     static constexpr int D = 3;
     static constexpr int NP = 9;
     static constexpr int K = 15;
-    static constexpr int NBLK = 4;
+    static constexpr int NPAIR = 8;
     static constexpr int cx[Q] = {0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0};
     static constexpr int cy[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1};
     static constexpr int cz[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};

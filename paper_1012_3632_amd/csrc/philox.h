@@ -6,7 +6,9 @@
 // and the key is bumped by the Weyl constants between rounds.  The noise of
 // the step uses counter (site, step, block | tag << 16, replica) and key
 // (seed mod 2^32, seed >> 32); the key and all counter words but the site are
-// uniform across a launch.
+// uniform across a launch.  Each Box-Muller pair takes a full 32-bit word for
+// its radius and 16 bits for its angle, so a D3Q19 site (15 normals) needs
+// three Philox blocks.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -50,36 +52,61 @@ __device__ __forceinline__ double u01d(uint32_t r) {
     return ((double)r + 1.0) * 0x1.0p-32;
 }
 
-// Box-Muller on two words: (sqrt(-2 ln u0) cos 2 pi u1, sqrt(-2 ln u0) sin 2 pi u1).
+// Box-Muller with a 32-bit radius word r and a 16-bit angle h:
+// R = sqrt(-2 ln u), u = (r + 1) 2^-32;  theta = 2 pi v, v = (h + 1) 2^-16;
+// (z0, z1) = R (cos theta, sin theta).
 // FP32 uses the hardware transcendentals directly: v_log_f32 (log2),
 // v_sqrt_f32, and v_sin_f32 / v_cos_f32, which take their argument in
-// revolutions (sin(2 pi x)), so u1 needs no range reduction.
-__device__ __forceinline__ void box_muller(uint32_t r0, uint32_t r1, float& z0, float& z1) {
-    const float u0 = u01f(r0), u1 = u01f(r1);
+// revolutions (sin(2 pi x)), so v needs no range reduction.
+__device__ __forceinline__ void box_muller(uint32_t r, uint32_t h, float& z0, float& z1) {
+    const float u = u01f(r);
+    const float v = (float)(h + 1u) * 0x1.0p-16f;
     constexpr float MINUS_2_LN2 = -1.3862943611198906f;   // -2 ln 2
-    const float rad = __builtin_amdgcn_sqrtf(MINUS_2_LN2 * __builtin_amdgcn_logf(u0));
-    z0 = rad * __builtin_amdgcn_cosf(u1);
-    z1 = rad * __builtin_amdgcn_sinf(u1);
+    const float rad = __builtin_amdgcn_sqrtf(MINUS_2_LN2 * __builtin_amdgcn_logf(u));
+    z0 = rad * __builtin_amdgcn_cosf(v);
+    z1 = rad * __builtin_amdgcn_sinf(v);
 }
-__device__ __forceinline__ void box_muller(uint32_t r0, uint32_t r1, double& z0, double& z1) {
-    const double u0 = u01d(r0), u1 = u01d(r1);
-    const double rad = sqrt(-2.0 * log(u0));
+__device__ __forceinline__ void box_muller(uint32_t r, uint32_t h, double& z0, double& z1) {
+    const double u = u01d(r);
+    const double v = (double)(h + 1u) * 0x1.0p-16;
+    const double rad = sqrt(-2.0 * log(u));
     double s, c;
-    sincos(2.0 * 3.141592653589793 * u1, &s, &c);
+    sincos(2.0 * 3.141592653589793 * v, &s, &c);
     z0 = rad * c;
     z1 = rad * s;
 }
 
-// The NBLK * 4 normals of one site-step: z[4 b + k] from block b, word pair k/2.
-template <int NBLK, typename Real>
+// The 2 NPAIR normals of one site-step.  Words w[0 ..) are the Philox outputs
+// of blocks 0, 1, ... (counter word 2 = block | tag << 16) in order x, y, z, w.
+// Pair p takes its radius from word w[p] and its angle from word
+// w[NPAIR + p/2] (high 16 bits for even p, low 16 bits for odd p);
+// z[2p], z[2p+1] = R (cos, sin).  D3Q19: 8 pairs from 12 words (3 blocks);
+// D2Q9: 3 pairs from 5 words (2 blocks).
+template <int NPAIR>
+struct NoiseLayout {
+    static constexpr int NWORD = NPAIR + (NPAIR + 1) / 2;
+    static constexpr int NBLK = (NWORD + 3) / 4;
+};
+
+template <int NPAIR, typename Real>
 __device__ __forceinline__ void site_normals(uint32_t site, uint32_t step, uint32_t tag,
                                              uint32_t replica, uint32_t k0, uint32_t k1,
-                                             Real (&z)[4 * NBLK]) {
+                                             Real (&z)[2 * NPAIR]) {
+    constexpr int NBLK = NoiseLayout<NPAIR>::NBLK;
+    uint32_t w[4 * NBLK];
 #pragma unroll
     for (int b = 0; b < NBLK; ++b) {
         const Philox4 r = philox4x32_10(site, step, (uint32_t)b | (tag << 16), replica, k0, k1);
-        box_muller(r.x, r.y, z[4 * b + 0], z[4 * b + 1]);
-        box_muller(r.z, r.w, z[4 * b + 2], z[4 * b + 3]);
+        w[4 * b + 0] = r.x;
+        w[4 * b + 1] = r.y;
+        w[4 * b + 2] = r.z;
+        w[4 * b + 3] = r.w;
+    }
+#pragma unroll
+    for (int p = 0; p < NPAIR; ++p) {
+        const uint32_t a = w[NPAIR + p / 2];
+        const uint32_t h = (p % 2 == 0) ? (a >> 16) : (a & 0xffffu);
+        box_muller(w[p], h, z[2 * p], z[2 * p + 1]);
     }
 }
 
