@@ -109,11 +109,26 @@ def bench_main(args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_from_profiles(
-                         "k_step_d3q19_fp32_stats_%dx%dx%dx%d" % sim.launch_shape(best_cfg)),
+                         "k_step_d3q19_fp32_stats_%dx%dx%dx%d%s" % (sim.launch_shape(best_cfg)[:4] + ("_nt" if sim.launch_shape(best_cfg)[4] else "",))),
                      "kernel": "k_step<D3Q19,float,ideal,stats>",
                      "bytes_per_site": bytes_site},
         "wall_timed_s": round(wall, 3),
     }
+    # context: what a plain device copy reaches on this GPU (read + write bytes)
+    a = torch.empty(1 << 27, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(20):
+        b.copy_(a)
+    e1.record(stream)
+    e1.synchronize()
+    copy_gbs = 2 * a.numel() * 4 * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    out["roofline"]["measured_copy_GBps"] = round(copy_gbs, 1)
+    out["roofline"]["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
+    del a, b
     # the same step without statistics
     ms_ns = time_steps(sim, args.steps, 0, stream)
     out["fp32_nostats"] = {"ms_per_step": round(ms_ns, 5),

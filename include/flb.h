@@ -247,7 +247,8 @@ flb_status flb_autotune(flb_handle* h, int32_t repeats, int32_t* best, double* b
                         void* stream);
 flb_status flb_set_launch(flb_handle* h, int32_t config);
 flb_status flb_launch_configs(const flb_handle* h, int32_t* count, int32_t* current);
-/* shape[4] = threads per block in x, y, z and sites per thread (stacked in y). */
+/* shape[5] = threads per block in x, y, z, sites per thread (stacked in y),
+ * and 1 if populations are stored with non-temporal hints. */
 flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape);
 flb_status flb_batch_autotune(flb_batch* b, int32_t repeats, int32_t* best, double* best_ms,
                               void* stream);

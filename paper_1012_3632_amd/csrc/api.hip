@@ -499,6 +499,7 @@ flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape)
     shape[1] = t.ty;
     shape[2] = t.tz;
     shape[3] = t.spt;
+    shape[4] = t.nt;
     return FLB_OK;
 }
 

@@ -28,6 +28,11 @@ template <typename Real>
 __device__ __forceinline__ void plane_st(Real* __restrict__ base, uint32_t idx, Real v) {
     *(Real*)((char*)base + idx * (uint32_t)sizeof(Real)) = v;
 }
+// Same with a non-temporal hint (the next read of this value is a step away).
+template <typename Real>
+__device__ __forceinline__ void plane_st_nt(Real* __restrict__ base, uint32_t idx, Real v) {
+    __builtin_nontemporal_store(v, (Real*)((char*)base + idx * (uint32_t)sizeof(Real)));
+}
 
 // f_i(x) = S_i(x - c_i), periodic.
 template <int LAT, typename Real>

@@ -49,7 +49,8 @@ __global__ void k_density(const Real* __restrict__ fin, Real* __restrict__ out, 
     out[s] = acc;
 }
 
-template <int LAT, typename Real, bool FORCE, bool STATS, int TX, int TY, int TZ, int SPT>
+template <int LAT, typename Real, bool FORCE, bool STATS, int TX, int TY, int TZ, int SPT,
+          bool NTS>
 __global__ __launch_bounds__(TX* TY* TZ) void k_step(
     const Real* __restrict__ fin, Real* __restrict__ fout, const Real* __restrict__ drho, Geom g,
     CollideParams<Real> P, ForceParams<Real> fp, StepIndex st, double* __restrict__ partial) {
@@ -114,7 +115,10 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
         if constexpr (ROWS) {
             const size_t row = (size_t)(uint32_t)((z * g.ny + y) * g.nx);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) plane_st(fout + ((size_t)i * g.V + row), (uint32_t)x, f[i]);
+            for (int i = 0; i < Q; ++i) {
+                if constexpr (NTS) plane_st_nt(fout + ((size_t)i * g.V + row), (uint32_t)x, f[i]);
+                else plane_st(fout + ((size_t)i * g.V + row), (uint32_t)x, f[i]);
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < Q; ++i) plane_st(fout + (size_t)i * g.V, site, f[i]);
@@ -281,7 +285,7 @@ hipError_t launch_init(const StepSpec& s, void* f, const double* drho, hipStream
 }
 
 hipError_t launch_density(const StepSpec& s, const void* fin, void* out, hipStream_t st) {
-    const Geom g = make_geom(s, TileShape{1, 1, 1, 1});
+    const Geom g = make_geom(s, TileShape{1, 1, 1, 1, 0});
     const dim3 grid((g.V + 255) / 256), block(256);
     if (s.lat == 0 && s.prec == 0) hipLaunchKernelGGL((k_density<0, float>), grid, block, 0, st, (const float*)fin, (float*)out, g);
     else if (s.lat == 0) hipLaunchKernelGGL((k_density<0, double>), grid, block, 0, st, (const double*)fin, (double*)out, g);
@@ -290,18 +294,18 @@ hipError_t launch_density(const StepSpec& s, const void* fin, void* out, hipStre
     return hipGetLastError();
 }
 
-template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ, int SPT = 1>
+template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ, int SPT = 1, bool NTS = false>
 static void step_tile(const StepSpec& s, const void* fin, void* fout, const void* drho,
                       StepIndex si, double* partial, hipStream_t st) {
-    const Geom g = make_geom(s, TileShape{TX, TY, TZ, SPT});
+    const Geom g = make_geom(s, TileShape{TX, TY, TZ, SPT, NTS});
     const dim3 grid(g.nblocks), block(TX * TY * TZ);
     const CollideParams<Real> P = collide_params<Real>(s);
     const ForceParams<Real> fp = force_params<Real>(s);
     if (partial)
-        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, true, TX, TY, TZ, SPT>), grid, block, 0, st,
+        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, true, TX, TY, TZ, SPT, NTS>), grid, block, 0, st,
                            (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
     else
-        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, false, TX, TY, TZ, SPT>), grid, block, 0, st,
+        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, false, TX, TY, TZ, SPT, NTS>), grid, block, 0, st,
                            (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
 }
 
@@ -317,7 +321,9 @@ static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fou
             case 4: step_tile<LAT, Real, false, 128, 2, 1, 2>(s, fin, fout, drho, si, partial, st); break;
             case 5: step_tile<LAT, Real, false, 64, 4, 1, 2>(s, fin, fout, drho, si, partial, st); break;
             case 6: step_tile<LAT, Real, false, 128, 2, 1, 4>(s, fin, fout, drho, si, partial, st); break;
-            default: step_tile<LAT, Real, false, 256, 1, 1, 2>(s, fin, fout, drho, si, partial, st); break;
+            case 7: step_tile<LAT, Real, false, 256, 1, 1, 2>(s, fin, fout, drho, si, partial, st); break;
+            case 8: step_tile<LAT, Real, false, 128, 2, 1, 1, true>(s, fin, fout, drho, si, partial, st); break;
+            default: step_tile<LAT, Real, false, 256, 1, 1, 1, true>(s, fin, fout, drho, si, partial, st); break;
         }
     } else if constexpr (LAT == 1) {
         switch (cfg) {
@@ -349,7 +355,7 @@ template <int LAT, typename Real, bool FORCE>
 static void fields_launch(const StepSpec& s, const void* fin, const void* drho, void* out,
                           hipStream_t st) {
     constexpr int TX = (LAT == 1) ? 32 : 64, TY = 4, TZ = (LAT == 1) ? 2 : 1;
-    const Geom g = make_geom(s, TileShape{TX, TY, TZ, 1});
+    const Geom g = make_geom(s, TileShape{TX, TY, TZ, 1, 0});
     hipLaunchKernelGGL((k_fields<LAT, Real, FORCE, TX, TY, TZ>), dim3(g.nblocks),
                        dim3(TX * TY * TZ), 0, st, (const Real*)fin, (const Real*)drho, (Real*)out,
                        g, (Real)s.rho0, force_params<Real>(s));

@@ -239,8 +239,8 @@ class Simulation:
         return n.value, cur.value
 
     def launch_shape(self, config):
-        """(tx, ty, tz, sites_per_thread) of a launch configuration."""
-        sh = (C.c_int32 * 4)()
+        """(tx, ty, tz, sites_per_thread, nontemporal) of a launch configuration."""
+        sh = (C.c_int32 * 5)()
         call("flb_launch_shape", self.handle, int(config), sh)
         return tuple(sh[:])
 
