@@ -67,6 +67,12 @@ def time_steps(sim, steps, stride, stream):
     return e0.elapsed_time(e1) / steps   # ms per step
 
 
+def profile_key(shape):
+    """Name of a stats-on D3Q19 FP32 step launch in the committed counter table."""
+    tx, ty, tz, spt, nt = shape
+    return "k_step_d3q19_fp32_stats_%dx%dx%dx%d%s" % (tx, ty, tz, spt, "_nt" if nt else "")
+
+
 def bench_main(args):
     import numpy as np
     import torch
@@ -80,7 +86,7 @@ def bench_main(args):
     p = Params.from_dict(dict(kw, precision="fp32"))
     V = p.nx * p.ny * p.nz
     sim = Simulation(p)
-    best_cfg, _ = sim.autotune(repeats=5)
+    (plain_cfg, best_cfg), _ = sim.autotune(repeats=5)
     sim.step(args.warmup, stats_stride=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -108,8 +114,7 @@ def bench_main(args):
                    "launch_shape": list(sim.launch_shape(best_cfg))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profiles(
-                         "k_step_d3q19_fp32_stats_%dx%dx%dx%d%s" % (sim.launch_shape(best_cfg)[:4] + ("_nt" if sim.launch_shape(best_cfg)[4] else "",))),
+                     "traffic": traffic_from_profiles(profile_key(sim.launch_shape(best_cfg))),
                      "kernel": "k_step<D3Q19,float,ideal,stats>",
                      "bytes_per_site": bytes_site},
         "wall_timed_s": round(wall, 3),
@@ -133,7 +138,9 @@ def bench_main(args):
     ms_ns = time_steps(sim, args.steps, 0, stream)
     out["fp32_nostats"] = {"ms_per_step": round(ms_ns, 5),
                            "MLUPS": round(V / (ms_ns * 1e-3) / 1e6, 1),
-                           "hbm_frac": round(bytes_site * V / (ms_ns * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                           "hbm_frac": round(bytes_site * V / (ms_ns * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "launch_config": plain_cfg,
+                           "launch_shape": list(sim.launch_shape(plain_cfg))}
     sim.close()
     del sim
     # FP64 step beside it

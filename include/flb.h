@@ -238,11 +238,17 @@ flb_status flb_batch_graph_capture(flb_batch* b, int64_t nsteps, int32_t stats_s
 flb_status flb_batch_graph_launch(flb_batch* b, void* stream);
 flb_status flb_batch_destroy(flb_batch* b);
 
-/* Launch shape in use and autotuning.  flb_autotune times every candidate
- * launch shape of the handle's step kernel (block size, sites per thread;
- * tile shape for the force kernel) on its own buffers without changing the
- * state, keeps the fastest and returns its index and time per step (ms).
- * Synchronizes the stream. */
+/* Launch shapes in use and autotuning.  A handle keeps two launch shapes:
+ * one for steps without statistics and one for steps that accumulate them.
+ * flb_autotune times every candidate launch shape of the handle's step kernel
+ * (block size, sites per thread, store hints; tile shape for the force
+ * kernel) in both modes on its own buffers, without changing the state or the
+ * accumulated statistics, keeps the fastest of each and writes best[2] (shape
+ * indices) and best_ms[2] (ms per step), entry 0 for plain steps and entry 1
+ * for steps with statistics (either pointer may be NULL).  It allocates and
+ * frees a temporary statistics buffer and synchronizes the stream.
+ * flb_set_launch sets both shapes; flb_launch_configs writes the number of
+ * shapes and current[2] (plain, with statistics). */
 flb_status flb_autotune(flb_handle* h, int32_t repeats, int32_t* best, double* best_ms,
                         void* stream);
 flb_status flb_set_launch(flb_handle* h, int32_t config);

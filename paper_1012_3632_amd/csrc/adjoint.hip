@@ -17,7 +17,9 @@
 //   mubar = -grad_h^T (rho Fbar),  rhobar = -Fbar.grad_h mu + eta cs2 grad_h^T Fbar
 //                                            + psi''(rho) mubar - kappa lap_h mubar
 // (grad_h^T phi(y) = 3 sum_i w_i c_i phi(y - c_i); lap_h is self-adjoint), added
-// to every population of the site: abar_n,i(y) += rhobar(y + c_i).
+// to every population of the site: abar_n,i(y) += rhobar(y + c_i).  In a
+// reverse sweep that last spread is deferred: the next (earlier) step's
+// collision adjoint adds rhobar(y + c_i) as it reads abar, which saves a pass.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -104,9 +106,10 @@ __device__ __forceinline__ void collide_adjoint(const Real (&m)[Lattice<LAT>::Q]
 // Collision adjoint + transposed transforms + push (P1).
 template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX* TY* TZ) void k_adj_collide(
-    const Real* __restrict__ s_n, const Real* __restrict__ abar, Real* __restrict__ abar_out,
-    const Real* __restrict__ drho, Real* __restrict__ Fbar, Geom g, CollideParams<Real> P,
-    ForceParams<Real> fp, Real inv2kT, uint32_t step, double* __restrict__ gpartial) {
+    const Real* __restrict__ s_n, const Real* __restrict__ abar, const Real* __restrict__ rb_prev,
+    Real* __restrict__ abar_out, const Real* __restrict__ drho, Real* __restrict__ Fbar, Geom g,
+    CollideParams<Real> P, ForceParams<Real> fp, Real inv2kT, uint32_t step,
+    double* __restrict__ gpartial) {
     using L = Lattice<LAT>;
     using M = Moments<LAT, Real>;
     using FT = ForceTile<LAT, Real, TX, TY, TZ>;
@@ -120,6 +123,28 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_adj_collide(
     const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
     const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
     const bool inside = x < g.nx && y < g.ny && z < g.nz;
+    const uint32_t site = (uint32_t)((z * g.ny + y) * g.nx + x);
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+    // global loads first, so that their latency overlaps the force tile's
+    Real f[Q], ab[Q];
+    if (inside) {
+        pull<LAT, Real>(s_n, x, y, z, g, f);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) ab[i] = abar[(size_t)i * g.V + site];
+        if (FORCE && rb_prev) {
+            // the density adjoint of the later step not yet spread over the
+            // populations: abar_i(y) += rhobar(y + c_i)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int sx = L::cx[i] == 0 ? x : (L::cx[i] > 0 ? xp : xm);
+                const int sy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? yp : ym);
+                const int sz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zp : zm);
+                ab[i] += rb_prev[(uint32_t)((sz * g.ny + sy) * g.nx + sx)];
+            }
+        }
+    }
     Real F[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) F[a] = Real(0);
@@ -129,15 +154,13 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_adj_collide(
     }
     double pg[4] = {0.0, 0.0, 0.0, 0.0};
     if (inside) {
-        Real f[Q], m[Q];
-        pull<LAT, Real>(s_n, x, y, z, g, f);
+        Real m[Q];
         M::forward(f, m);
-        const uint32_t site = (uint32_t)((z * g.ny + y) * g.nx + x);
         Real zn[2 * L::NPAIR];
         if (P.noise_on) site_normals<L::NPAIR, Real>(site, step, 0u, P.replica, P.key0, P.key1, zn);
-        Real ab[Q], mbs[Q];
+        Real mbs[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) ab[i] = Real(L::w[i]) * abar[(size_t)i * g.V + site];
+        for (int i = 0; i < Q; ++i) ab[i] *= Real(L::w[i]);
         M::forward(ab, mbs);
 #pragma unroll
         for (int a = 0; a < Q; ++a) mbs[a] *= Real(1.0 / L::N[a]);
@@ -145,9 +168,6 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_adj_collide(
         collide_adjoint<LAT, Real, FORCE>(m, F, zn, P, inv2kT, mbs, mb, Fb, pg);
         Real fb[Q];
         M::transpose(mb, fb);
-        const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
-        const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
-        const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int dx = L::cx[i] == 0 ? x : (L::cx[i] > 0 ? xm : xp);
@@ -313,11 +333,13 @@ static ForceParams<Real> adj_force_params(const StepSpec& s) {
     return f;
 }
 
+// Force adjoint work space: D planes of Fbar, then two rhobar planes (a step
+// of a reverse sweep reads the later step's rhobar while writing its own).
 size_t adjoint_work_bytes(const StepSpec& s) {
     if (!s.force) return 0;
     const size_t rb = s.prec ? 8 : 4;
     const size_t D = s.lat == 1 ? 3 : 2;
-    return (D + 1) * (size_t)s.nx * s.ny * s.nz * rb;
+    return (D + 2) * (size_t)s.nx * s.ny * s.nz * rb;
 }
 
 uint32_t adjoint_slots(const StepSpec& s) {
@@ -327,48 +349,64 @@ uint32_t adjoint_slots(const StepSpec& s) {
 }
 
 template <int LAT, typename Real, bool FORCE>
-static void adj_launch(const StepSpec& s, const void* s_n, const void* drho, const void* abar_np1,
-                       void* abar_n, void* work, unsigned long long step, double* gpartial,
-                       hipStream_t st) {
+static void adj_launch(const StepSpec& s, const AdjointStepArgs& a, hipStream_t st) {
     using T = AdjTile<LAT, FORCE>;
     constexpr int D = Lattice<LAT>::D;
     const Geom g = adj_geom(s, T::X, T::Y, T::Z);
     const CollideParams<Real> P = adj_collide_params<Real>(s);
     const ForceParams<Real> fp = adj_force_params<Real>(s);
     const Real inv2kT = s.kT > 0.0 ? (Real)(0.5 / s.kT) : Real(0);
-    Real* Fbar = (Real*)work;
-    Real* rbar = FORCE ? Fbar + (size_t)D * g.V : nullptr;
+    Real* Fbar = (Real*)a.work;
+    Real* rb_in = (FORCE && a.rb_in >= 0) ? Fbar + (size_t)(D + a.rb_in) * g.V : nullptr;
+    Real* rb_out = FORCE ? Fbar + (size_t)(D + a.rb_out) * g.V : nullptr;
     hipLaunchKernelGGL((k_adj_collide<LAT, Real, FORCE, T::X, T::Y, T::Z>), dim3(g.nblocks),
-                       dim3(T::X * T::Y * T::Z), 0, st, (const Real*)s_n, (const Real*)abar_np1,
-                       (Real*)abar_n, (const Real*)drho, Fbar, g, P, fp, inv2kT, (uint32_t)step,
-                       gpartial);
+                       dim3(T::X * T::Y * T::Z), 0, st, (const Real*)a.s_n,
+                       (const Real*)a.abar_np1, (const Real*)rb_in, (Real*)a.abar_n,
+                       (const Real*)a.drho, Fbar, g, P, fp, inv2kT, (uint32_t)a.step, a.gpartial);
     if constexpr (FORCE) {
         hipLaunchKernelGGL((k_adj_force<LAT, Real, T::X, T::Y, T::Z>), dim3(g.nblocks),
-                           dim3(T::X * T::Y * T::Z), 0, st, (const Real*)drho, (const Real*)Fbar,
-                           rbar, g, (Real)s.rho0, fp);
-        hipLaunchKernelGGL((k_adj_spread<LAT, Real, true>), dim3((g.V + 255) / 256), dim3(256),
-                           0, st, (const Real*)rbar, (Real*)abar_n, g);
+                           dim3(T::X * T::Y * T::Z), 0, st, (const Real*)a.drho, (const Real*)Fbar,
+                           rb_out, g, (Real)s.rho0, fp);
+        if (a.spread)
+            hipLaunchKernelGGL((k_adj_spread<LAT, Real, true>), dim3((g.V + 255) / 256),
+                               dim3(256), 0, st, (const Real*)rb_out, (Real*)a.abar_n, g);
     }
 }
 
-hipError_t launch_adjoint_step(const StepSpec& s, const void* s_n, const void* drho,
-                               const void* abar_np1, void* abar_n, void* work,
-                               unsigned long long step, double* gpartial, uint32_t* nslots_out,
-                               hipStream_t st) {
+hipError_t launch_adjoint_step(const StepSpec& s, const AdjointStepArgs& a, hipStream_t st) {
+    if (s.force && (a.rb_out < 0 || a.rb_out > 1 || a.rb_in > 1 || a.rb_in == a.rb_out))
+        return hipErrorInvalidValue;
     if (s.lat == 0 && s.prec == 0) {
-        if (s.force) adj_launch<0, float, true>(s, s_n, drho, abar_np1, abar_n, work, step, gpartial, st);
-        else adj_launch<0, float, false>(s, s_n, drho, abar_np1, abar_n, work, step, gpartial, st);
+        if (s.force) adj_launch<0, float, true>(s, a, st);
+        else adj_launch<0, float, false>(s, a, st);
     } else if (s.lat == 0) {
-        if (s.force) adj_launch<0, double, true>(s, s_n, drho, abar_np1, abar_n, work, step, gpartial, st);
-        else adj_launch<0, double, false>(s, s_n, drho, abar_np1, abar_n, work, step, gpartial, st);
+        if (s.force) adj_launch<0, double, true>(s, a, st);
+        else adj_launch<0, double, false>(s, a, st);
     } else if (s.prec == 0) {
-        if (s.force) adj_launch<1, float, true>(s, s_n, drho, abar_np1, abar_n, work, step, gpartial, st);
-        else adj_launch<1, float, false>(s, s_n, drho, abar_np1, abar_n, work, step, gpartial, st);
+        if (s.force) adj_launch<1, float, true>(s, a, st);
+        else adj_launch<1, float, false>(s, a, st);
     } else {
-        if (s.force) adj_launch<1, double, true>(s, s_n, drho, abar_np1, abar_n, work, step, gpartial, st);
-        else adj_launch<1, double, false>(s, s_n, drho, abar_np1, abar_n, work, step, gpartial, st);
+        if (s.force) adj_launch<1, double, true>(s, a, st);
+        else adj_launch<1, double, false>(s, a, st);
     }
-    if (nslots_out) *nslots_out = adjoint_slots(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_spread(const StepSpec& s, void* work, int rb, void* abar,
+                                 hipStream_t st) {
+    if (!s.force) return hipSuccess;
+    if (rb < 0 || rb > 1) return hipErrorInvalidValue;
+    const Geom g = adj_geom(s, 1, 1, 1);
+    const size_t off = (size_t)((s.lat == 1 ? 3 : 2) + rb) * g.V;
+    const dim3 grid((g.V + 255) / 256), blk(256);
+    if (s.lat == 0 && s.prec == 0)
+        hipLaunchKernelGGL((k_adj_spread<0, float, true>), grid, blk, 0, st, (const float*)work + off, (float*)abar, g);
+    else if (s.lat == 0)
+        hipLaunchKernelGGL((k_adj_spread<0, double, true>), grid, blk, 0, st, (const double*)work + off, (double*)abar, g);
+    else if (s.prec == 0)
+        hipLaunchKernelGGL((k_adj_spread<1, float, true>), grid, blk, 0, st, (const float*)work + off, (float*)abar, g);
+    else
+        hipLaunchKernelGGL((k_adj_spread<1, double, true>), grid, blk, 0, st, (const double*)work + off, (double*)abar, g);
     return hipGetLastError();
 }
 

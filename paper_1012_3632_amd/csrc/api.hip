@@ -148,7 +148,8 @@ struct flb_handle {
     uint32_t slots;
     uint64_t step;
     int64_t nsamples;
-    int cfg;
+    int cfg;                // launch shape of steps without statistics
+    int cfg_stats;          // launch shape of steps that accumulate statistics
     hipGraph_t graph;
     hipGraphExec_t gexec;
     int64_t graph_steps, graph_samples;
@@ -181,8 +182,8 @@ void scratch_layout(const StepSpec& s, size_t V, size_t rb, size_t* drho_off, si
 flb_status do_step(flb_handle* h, bool sample, const unsigned long long* step_dev,
                    unsigned long long step_host, hipStream_t st) {
     if (h->spec.force) HIP_TRY(launch_density(h->spec, h->cur(), h->drho, st));
-    HIP_TRY(launch_step(h->spec, h->cfg, h->cur(), h->other(), h->drho, step_dev, step_host,
-                        sample ? h->stats : nullptr, st));
+    HIP_TRY(launch_step(h->spec, sample ? h->cfg_stats : h->cfg, h->cur(), h->other(), h->drho,
+                        step_dev, step_host, sample ? h->stats : nullptr, st));
     h->cur_a = !h->cur_a;
     return FLB_OK;
 }
@@ -288,6 +289,7 @@ flb_status flb_init(const flb_params* p, void* f_a, void* f_b, void* scratch, vo
     h->step = p->step0;
     h->nsamples = 0;
     h->cfg = 0;
+    h->cfg_stats = 0;
     h->graph = nullptr;
     h->gexec = nullptr;
     size_t drho_off, adj_off, gp_off, total;
@@ -442,36 +444,49 @@ flb_status flb_autotune(flb_handle* h, int32_t repeats, int32_t* best, double* b
     if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
     if (repeats < 1) repeats = 1;
     hipStream_t st = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    // statistics of the trials go to a buffer of their own: the handle's sums stay
+    const size_t pbytes = ((size_t)h->slots + 1) * 2 * h->q * sizeof(double);
+    double* trial_stats = nullptr;
+    HIP_TRY(hipMalloc((void**)&trial_stats, pbytes));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch_fill_zero(trial_stats, pbytes, st);
     const int ncfg = n_configs(h->spec.lat, h->spec.force);
-    int bi = h->cfg;
-    float bt = 1e30f;
+    int bi[2] = {h->cfg, h->cfg_stats};
+    float bt[2] = {1e30f, 1e30f};
     // each trial writes cur -> other without swapping or counting: the state is unchanged
-    if (h->spec.force) HIP_TRY(launch_density(h->spec, h->cur(), h->drho, st));
-    for (int c = 0; c < ncfg; ++c) {
-        HIP_TRY(launch_step(h->spec, c, h->cur(), h->other(), h->drho, nullptr, h->step, nullptr,
-                            st));
-        HIP_TRY(hipEventRecord(e0, st));
-        for (int r = 0; r < repeats; ++r)
-            HIP_TRY(launch_step(h->spec, c, h->cur(), h->other(), h->drho, nullptr, h->step,
-                                nullptr, st));
-        HIP_TRY(hipEventRecord(e1, st));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        ms /= repeats;
-        if (ms < bt) {
-            bt = ms;
-            bi = c;
+    if (e == hipSuccess && h->spec.force) e = launch_density(h->spec, h->cur(), h->drho, st);
+    for (int mode = 0; mode < 2 && e == hipSuccess; ++mode) {
+        double* part = mode ? trial_stats : nullptr;
+        for (int c = 0; c < ncfg && e == hipSuccess; ++c) {
+            e = launch_step(h->spec, c, h->cur(), h->other(), h->drho, nullptr, h->step, part, st);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            for (int r = 0; r < repeats && e == hipSuccess; ++r)
+                e = launch_step(h->spec, c, h->cur(), h->other(), h->drho, nullptr, h->step, part,
+                                st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            ms /= repeats;
+            if (e == hipSuccess && ms < bt[mode]) {
+                bt[mode] = ms;
+                bi[mode] = c;
+            }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    h->cfg = bi;
-    if (best) *best = bi;
-    if (best_ms) *best_ms = bt;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    const hipError_t ef = hipFree(trial_stats);
+    if (e == hipSuccess) e = ef;
+    if (e != hipSuccess) return fail(FLB_ERR_HIP, "autotune: %s", hipGetErrorString(e));
+    h->cfg = bi[0];
+    h->cfg_stats = bi[1];
+    for (int m = 0; m < 2; ++m) {
+        if (best) best[m] = bi[m];
+        if (best_ms) best_ms[m] = bt[m];
+    }
     return FLB_OK;
 }
 
@@ -480,13 +495,17 @@ flb_status flb_set_launch(flb_handle* h, int32_t config) {
     if (config < 0 || config >= n_configs(h->spec.lat, h->spec.force))
         return fail(FLB_ERR_INVALID_ARG, "launch config %d out of range", config);
     h->cfg = config;
+    h->cfg_stats = config;
     return FLB_OK;
 }
 
 flb_status flb_launch_configs(const flb_handle* h, int32_t* count, int32_t* current) {
     if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
     if (count) *count = n_configs(h->spec.lat, h->spec.force);
-    if (current) *current = h->cfg;
+    if (current) {
+        current[0] = h->cfg;
+        current[1] = h->cfg_stats;
+    }
     return FLB_OK;
 }
 
@@ -517,9 +536,9 @@ flb_status flb_adjoint_step(flb_handle* h, const void* s_n, const void* abar_np1
         return fail(FLB_ERR_INVALID_ARG, "abar_n must not alias the inputs");
     hipStream_t st = (hipStream_t)stream;
     if (h->spec.force) HIP_TRY(launch_density(h->spec, s_n, h->drho, st));
-    uint32_t ns = 0;
-    HIP_TRY(launch_adjoint_step(h->spec, s_n, h->drho, abar_np1, abar_n, h->adj_work,
-                                (unsigned long long)n, h->gpartial, &ns, st));
+    AdjointStepArgs a{s_n, h->drho, abar_np1, abar_n, h->adj_work, -1, 0, true,
+                      (unsigned long long)n, h->gpartial};
+    HIP_TRY(launch_adjoint_step(h->spec, a, st));
     if (grad) {
         double* out = h->gpartial + (size_t)h->gslots * 4;
         HIP_TRY(launch_stats_finalize(h->gpartial, h->gslots, 4, out, st));
@@ -566,14 +585,20 @@ flb_status flb_adjoint_segment(flb_handle* h, const void* s_k0, void* abar, void
         if (h->spec.force) HIP_TRY(launch_density(h->spec, state(j), density(j), st));
     }
     // reverse sweep: abar and spare alternate
+    // abar and spare alternate; each step's density adjoint is spread into
+    // the populations by the next (earlier) step, the last one's at the end
     void* cur = abar;
     void* nxt = spare;
-    uint32_t ns = 0;
+    int rb_in = -1;
     for (size_t j = k; j-- > 0;) {
-        HIP_TRY(launch_adjoint_step(h->spec, state(j), density(j), cur, nxt, h->adj_work,
-                                    (unsigned long long)(k0 + j), h->gpartial, &ns, st));
+        const int rb_out = (int)(j & 1);
+        AdjointStepArgs a{state(j), density(j), cur, nxt, h->adj_work, rb_in, rb_out, false,
+                          (unsigned long long)(k0 + j), h->gpartial};
+        HIP_TRY(launch_adjoint_step(h->spec, a, st));
+        rb_in = rb_out;
         std::swap(cur, nxt);
     }
+    if (h->spec.force) HIP_TRY(launch_adjoint_spread(h->spec, h->adj_work, rb_in, cur, st));
     if (cur != abar)
         HIP_TRY(hipMemcpyAsync(abar, cur, (size_t)h->q * h->V * h->real_bytes,
                                hipMemcpyDeviceToDevice, st));

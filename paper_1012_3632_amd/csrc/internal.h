@@ -63,10 +63,22 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
 // Adjoint launchers (adjoint.hip).
 hipError_t launch_adjoint_seed(const StepSpec& s, const void* rhobar, void* abar, hipStream_t st);
-hipError_t launch_adjoint_step(const StepSpec& s, const void* s_n, const void* drho,
-                               const void* abar_np1, void* abar_n, void* work,
-                               unsigned long long step, double* gpartial, uint32_t* nslots_out,
-                               hipStream_t st);
+struct AdjointStepArgs {
+    const void* s_n;         // state S_n
+    const void* drho;        // density of S_n after streaming (force model)
+    const void* abar_np1;    // dL/dS_{n+1}, less the pending spread of rb_in
+    void* abar_n;            // out: dL/dS_n, less the spread of rb_out unless spread
+    void* work;              // adjoint_work_bytes: Fbar planes, two rhobar planes
+    int rb_in;               // rhobar plane (0/1) still to be spread into abar_np1, or -1
+    int rb_out;              // rhobar plane (0/1) this step writes
+    bool spread;             // spread rb_out into abar_n now
+    unsigned long long step;
+    double* gpartial;        // per-block parameter-derivative slots (added to)
+};
+hipError_t launch_adjoint_step(const StepSpec& s, const AdjointStepArgs& a, hipStream_t st);
+// abar_i(y) += rhobar(y + c_i) from rhobar plane rb of the work space.
+hipError_t launch_adjoint_spread(const StepSpec& s, void* work, int rb, void* abar,
+                                 hipStream_t st);
 size_t adjoint_work_bytes(const StepSpec& s);
 uint32_t adjoint_slots(const StepSpec& s);
 

@@ -76,13 +76,19 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
     }
     const int x = x0 + tx, z = z0 + tz;
 
-    Real F[D];
+    Real F[D], fpre[FORCE ? Q : 1];
 #pragma unroll
     for (int a = 0; a < D; ++a) F[a] = Real(0);
     if constexpr (FORCE) {
+        // the populations are pulled before the density tile is staged, so
+        // that the two sets of loads are in flight together
+        const bool in0 = x < g.nx && y0 + ty < g.ny && z < g.nz;
+        if (in0) {
+            if constexpr (ROWS) pull_rows<LAT, Real>(fin, x, y0 + ty, z, g, fpre);
+            else pull<LAT, Real>(fin, x, y0 + ty, z, g, fpre);
+        }
         FT::stage(drho, g, fp, x0, y0, z0, lds_force, lds_force + FT::NR);
-        if (x < g.nx && y0 + ty < g.ny && z < g.nz)
-            FT::force(lds_force, lds_force + FT::NR, fp, P.rho0, tx, ty, tz, F);
+        if (in0) FT::force(lds_force, lds_force + FT::NR, fp, P.rho0, tx, ty, tz, F);
     }
 
     Real v[2 * Q];
@@ -96,8 +102,14 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
     const bool inside = x < g.nx && y < g.ny && z < g.nz;
     if (inside) {
         Real f[Q], m[Q];
-        if constexpr (ROWS) pull_rows<LAT, Real>(fin, x, y, z, g, f);
-        else pull<LAT, Real>(fin, x, y, z, g, f);
+        if constexpr (FORCE) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) f[i] = fpre[i];
+        } else if constexpr (ROWS) {
+            pull_rows<LAT, Real>(fin, x, y, z, g, f);
+        } else {
+            pull<LAT, Real>(fin, x, y, z, g, f);
+        }
         M::forward(f, m);
         if constexpr (STATS) {
 #pragma unroll

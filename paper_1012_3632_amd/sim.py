@@ -226,17 +226,20 @@ class Simulation:
         call("flb_graph_launch", self.handle, _stream(stream))
 
     def autotune(self, repeats=5, stream=None):
-        best, ms = C.c_int32(), C.c_double()
-        call("flb_autotune", self.handle, int(repeats), C.byref(best), C.byref(ms), _stream(stream))
-        return best.value, ms.value
+        """Time every launch shape, for steps without and with statistics;
+        returns ((shape_plain, shape_stats), (ms_plain, ms_stats))."""
+        best, ms = (C.c_int32 * 2)(), (C.c_double * 2)()
+        call("flb_autotune", self.handle, int(repeats), best, ms, _stream(stream))
+        return tuple(best[:]), tuple(ms[:])
 
     def set_launch(self, config):
         call("flb_set_launch", self.handle, int(config))
 
     def launch_configs(self):
-        n, cur = C.c_int32(), C.c_int32()
-        call("flb_launch_configs", self.handle, C.byref(n), C.byref(cur))
-        return n.value, cur.value
+        """(number of launch shapes, (shape of plain steps, shape of steps with statistics))."""
+        n, cur = C.c_int32(), (C.c_int32 * 2)()
+        call("flb_launch_configs", self.handle, C.byref(n), cur)
+        return n.value, tuple(cur[:])
 
     def launch_shape(self, config):
         """(tx, ty, tz, sites_per_thread, nontemporal) of a launch configuration."""

@@ -45,9 +45,43 @@ def test_parity_d2q9_ideal_full_run(precision):
 def test_parity_d3q19_ideal(precision, shape):
     nz, ny, nx = shape
     kw = dict(C2, precision=precision, nx=nx, ny=ny, nz=nz)
-    for launch in range(10):
+    for launch in range(n_launch(kw)):
         sim, fg, fr, _ = run_pair(kw, 30, drho_amp=0.01, launch=launch)
         assert rel_err(fg, fr) < tol(kw), launch
+
+
+def n_launch(kw):
+    from paper_1012_3632_amd import Simulation
+    s = Simulation(gpu_params(**kw))
+    n, _ = s.launch_configs()
+    s.close()
+    return n
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_statistics_every_launch_d3q19(precision):
+    """The per-block statistics slots give the oracle's mode sums for every
+    launch shape, over a box ragged in x and y."""
+    kw = dict(C2, precision=precision, nx=130, ny=21, nz=12)
+    n = n_launch(kw)
+    assert n >= 10
+    ref = None
+    for launch in range(n):
+        sim, fg, fr, st = run_pair(kw, 12, drho_amp=0.01, launch=launch, stats_stride=2)
+        s, s2, ns = sim.moments()
+        assert ns == st["nsamples"] == 6
+        if precision == "fp64":
+            np.testing.assert_allclose(s2, st["sumsq"], rtol=1e-11, err_msg=str(launch))
+            np.testing.assert_allclose(s, st["sum"], rtol=1e-9, atol=1e-10, err_msg=str(launch))
+        else:
+            # FP32 moments are summed in FP32 per thread before the FP64 reduction
+            np.testing.assert_allclose(s2, st["sumsq"], rtol=5e-5, err_msg=str(launch))
+            if ref is None:
+                ref = (s, s2)
+            np.testing.assert_allclose(s2, ref[1], rtol=1e-6, err_msg=str(launch))
+            np.testing.assert_allclose(s, ref[0], rtol=1e-5, atol=1e-6 * np.abs(ref[0]).max(),
+                                       err_msg=str(launch))
+        sim.close()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -107,16 +141,17 @@ def test_fields_match_oracle(force):
 
 
 def test_full_size_step_parity_d3q19_128():
-    """d3q19_128 at full size in the default launch: the GPU state after 40
-    steps is advanced one step by the oracle and by the GPU; every site is
-    compared (FP32 bar)."""
+    """d3q19_128 at full size in the launch shape the autotuner picks (the one
+    the benchmark times): the GPU state after 40 steps is advanced one step by
+    the oracle and by the GPU; every site is compared (FP32 bar)."""
     from oracle import flb
     from paper_1012_3632_amd import Simulation
     kw = dict(W.params_of("d3q19_128"), precision="fp32")
     sim = Simulation(gpu_params(**kw))
-    sim.step(40)
+    sim.autotune(repeats=2)
+    sim.step(40, stats_stride=1)
     S40 = sim.populations()
-    sim.step(1)
+    sim.step(1, stats_stride=1)
     got = sim.populations().numpy()
     po = oracle_params(**kw)
     ref = flb.step(S40, 40, po).numpy()
@@ -164,7 +199,8 @@ def test_launch_configs_bitwise_identical_and_autotune_keeps_state():
     from paper_1012_3632_amd import Simulation
     kw = dict(C2, precision="fp32", nx=64, ny=32, nz=16)
     ref = None
-    for cfg in range(10):
+    n = n_launch(kw)
+    for cfg in range(n):
         s = Simulation(gpu_params(**kw))
         s.set_launch(cfg)
         s.step(6)
@@ -174,10 +210,16 @@ def test_launch_configs_bitwise_identical_and_autotune_keeps_state():
         assert torch.equal(st, ref), cfg
     s = Simulation(gpu_params(**kw))
     s.step(3)
+    s.step(2, stats_stride=1)
     before = s.state().clone()
+    m_before = s.moments()
     best, ms = s.autotune(repeats=2)
     assert torch.equal(s.state(), before)
-    assert ms > 0 and 0 <= best < 10
+    m_after = s.moments()
+    for x, y in zip(m_before, m_after):
+        np.testing.assert_array_equal(x, y)
+    assert s.launch_configs() == (n, best)
+    assert all(t > 0 for t in ms) and all(0 <= b < n for b in best)
 
 
 def test_conservation_gpu():
