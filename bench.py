@@ -69,7 +69,7 @@ def time_steps(sim, steps, stride, stream):
 
 def profile_key(shape):
     """Name of a stats-on D3Q19 FP32 step launch in the committed counter table."""
-    tx, ty, tz, spt, nt = shape
+    tx, ty, tz, spt, nt, _ = shape
     return "k_step_d3q19_fp32_stats_%dx%dx%dx%d%s" % (tx, ty, tz, spt, "_nt" if nt else "")
 
 
@@ -177,12 +177,16 @@ def extras(args, stream):
     drho = W.initial_drho(p.shape, 7, W.WORKLOADS["d3q19_256_landau"]["init_noise"])
     s = Simulation(p, drho_init=drho)
     del drho
-    s.autotune(repeats=3)
+    (_, cfg_stats), _ = s.autotune(repeats=3)
     s.step(5, stats_stride=1)
     n = max(args.steps // 4, 10)
     ms = time_steps(s, n, 1, stream)
+    # a step is the density pass (19 reads + 1 write) and the force step
+    # (19 reads + 19 writes + the density): 80 + 156 = 236 B per site
     res["d3q19_256_landau"] = {"ms_per_step": round(ms, 4), "MLUPS": round(V / (ms * 1e-3) / 1e6, 1),
-                               "hbm_frac_algorithmic_160B": round(160 * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                               "hbm_frac_algorithmic_236B": round(236 * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "launch_config": cfg_stats, "launch_shape": list(s.launch_shape(cfg_stats)),
+                               "statistics": "every step"}
     s.close()
     del s
     torch.cuda.empty_cache()

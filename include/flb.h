@@ -245,16 +245,18 @@ flb_status flb_batch_destroy(flb_batch* b);
  * kernel) in both modes on its own buffers, without changing the state or the
  * accumulated statistics, keeps the fastest of each and writes best[2] (shape
  * indices) and best_ms[2] (ms per step), entry 0 for plain steps and entry 1
- * for steps with statistics (either pointer may be NULL).  It allocates and
- * frees a temporary statistics buffer and synchronizes the stream.
+ * for steps with statistics (either pointer may be NULL).  The statistics
+ * trials run on the handle's own slots, saved to host memory before and
+ * restored after; the call synchronizes the stream.
  * flb_set_launch sets both shapes; flb_launch_configs writes the number of
  * shapes and current[2] (plain, with statistics). */
 flb_status flb_autotune(flb_handle* h, int32_t repeats, int32_t* best, double* best_ms,
                         void* stream);
 flb_status flb_set_launch(flb_handle* h, int32_t config);
 flb_status flb_launch_configs(const flb_handle* h, int32_t* count, int32_t* current);
-/* shape[5] = threads per block in x, y, z, sites per thread (stacked in y),
- * and 1 if populations are stored with non-temporal hints. */
+/* shape[6] = threads per block in x, y, z, sites per thread (stacked in y),
+ * 1 if populations are stored with non-temporal hints, and the number of z
+ * planes a block sweeps (z-marching force step; 0 otherwise). */
 flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape);
 flb_status flb_batch_autotune(flb_batch* b, int32_t repeats, int32_t* best, double* best_ms,
                               void* stream);

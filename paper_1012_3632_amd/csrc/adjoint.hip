@@ -294,7 +294,7 @@ template <> struct AdjTile<0, true> { static constexpr int X = 64, Y = 4, Z = 1;
 template <> struct AdjTile<1, true> { static constexpr int X = 16, Y = 4, Z = 2; };
 
 static Geom adj_geom(const StepSpec& s, int tx, int ty, int tz) {
-    Geom g;
+    Geom g{};
     g.nx = s.nx;
     g.ny = s.ny;
     g.nz = s.nz;

@@ -444,14 +444,16 @@ flb_status flb_autotune(flb_handle* h, int32_t repeats, int32_t* best, double* b
     if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
     if (repeats < 1) repeats = 1;
     hipStream_t st = (hipStream_t)stream;
-    // statistics of the trials go to a buffer of their own: the handle's sums stay
+    // the statistics trials accumulate into the handle's own slots: their
+    // contents are saved to host memory first and put back afterwards
     const size_t pbytes = ((size_t)h->slots + 1) * 2 * h->q * sizeof(double);
-    double* trial_stats = nullptr;
-    HIP_TRY(hipMalloc((void**)&trial_stats, pbytes));
+    std::vector<double> saved(pbytes / sizeof(double));
+    double* trial_stats = h->stats;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
+    hipError_t e = hipMemcpyAsync(saved.data(), h->stats, pbytes, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    if (e == hipSuccess) e = launch_fill_zero(trial_stats, pbytes, st);
     const int ncfg = n_configs(h->spec.lat, h->spec.force);
     int bi[2] = {h->cfg, h->cfg_stats};
     float bt[2] = {1e30f, 1e30f};
@@ -478,8 +480,10 @@ flb_status flb_autotune(flb_handle* h, int32_t repeats, int32_t* best, double* b
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    const hipError_t ef = hipFree(trial_stats);
-    if (e == hipSuccess) e = ef;
+    // restore the sums even after a failed trial
+    hipError_t er = hipMemcpyAsync(h->stats, saved.data(), pbytes, hipMemcpyHostToDevice, st);
+    if (er == hipSuccess) er = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = er;
     if (e != hipSuccess) return fail(FLB_ERR_HIP, "autotune: %s", hipGetErrorString(e));
     h->cfg = bi[0];
     h->cfg_stats = bi[1];
@@ -519,6 +523,7 @@ flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape)
     shape[2] = t.tz;
     shape[3] = t.spt;
     shape[4] = t.nt;
+    shape[5] = t.zc;
     return FLB_OK;
 }
 

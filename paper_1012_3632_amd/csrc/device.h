@@ -213,4 +213,105 @@ struct ForceTile {
     }
 };
 
+// ------------------------------------------------------------------ force march
+
+// The same density -> chemical potential -> force chain for a D3Q19 block
+// that sweeps a column of TX x TY sites through a run of z planes.  LDS holds
+// a ring of five density planes (TX + 4) x (TY + 4) and three chemical
+// potential planes (TX + 2) x (TY + 2): every step in z stages one new density
+// plane and evaluates one new mu plane, so the halo is only in x and y.
+// Ring slots are numbered relative to the first plane zb of the run.
+//
+// With a barrier after the density plane is written and one after the mu
+// plane, five density slots and three mu slots are enough: at plane z the
+// density of z + 2 overwrites that of z - 3, last read by the force at
+// z - 2, and mu(z + 1) overwrites mu(z - 2), last read by the force at z - 1;
+// both reads precede a barrier that every thread has passed.
+template <typename Real, int TX, int TY>
+struct ForceMarch {
+    using L = Lattice<1>;
+    static constexpr int RX = TX + 4, RY = TY + 4, MX = TX + 2, MY = TY + 2;
+    static constexpr int NRP = RX * RY, NMP = MX * MY, NT = TX * TY;
+    static constexpr int NLD = (NRP + NT - 1) / NT;   // density values staged per thread
+    static constexpr int LDS = 5 * NRP + 3 * NMP;
+
+    static __device__ __forceinline__ int rslot(int z, int zb) { return (z - zb + 5) % 5; }
+    static __device__ __forceinline__ int mslot(int z, int zb) { return (z - zb + 3) % 3; }
+
+    // in-plane offsets (gy nx + gx) of this thread's staged density values
+    static __device__ __forceinline__ void plane_offsets(const Geom& g, int x0, int y0,
+                                                         uint32_t (&off)[NLD]) {
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int l = (int)threadIdx.x + k * NT;
+            const int lx = l % RX, ly = l / RX;
+            const int gx = wrap_any(x0 + lx - 2, g.nx);
+            const int gy = wrap_any(y0 + ly - 2, g.ny);
+            off[k] = (uint32_t)(gy * g.nx + gx);
+        }
+    }
+    static __device__ __forceinline__ void load_plane(const Real* __restrict__ drho, const Geom& g,
+                                                      const uint32_t (&off)[NLD], int z,
+                                                      Real (&r)[NLD]) {
+        const uint32_t base = (uint32_t)(wrap_any(z, g.nz) * g.ny) * (uint32_t)g.nx;
+#pragma unroll
+        for (int k = 0; k < NLD; ++k)
+            if ((int)threadIdx.x + k * NT < NRP) r[k] = drho[base + off[k]];
+    }
+    static __device__ __forceinline__ void store_plane(const Real (&r)[NLD], Real* rs) {
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int l = (int)threadIdx.x + k * NT;
+            if (l < NRP) rs[l] = r[k];
+        }
+    }
+    // mu on plane z (tile plus a one-site halo in x and y) from density planes z-1, z, z+1
+    static __device__ __forceinline__ void mu_plane(const Real* lds_r, Real* lds_m, int z, int zb,
+                                                    const ForceParams<Real>& fp) {
+        const Real* rp[3] = {lds_r + rslot(z - 1, zb) * NRP, lds_r + rslot(z, zb) * NRP,
+                             lds_r + rslot(z + 1, zb) * NRP};
+        Real* mo = lds_m + mslot(z, zb) * NMP;
+        for (int l = threadIdx.x; l < NMP; l += NT) {
+            const int mx = l % MX, my = l / MX;
+            const int c = (my + 1) * RX + (mx + 1);
+            const Real rc = rp[1][c];
+            Real lap = Real(0);
+#pragma unroll
+            for (int i = 1; i < L::Q; ++i)
+                lap += Real(L::w[i]) * (rp[1 + L::cz[i]][c + L::cy[i] * RX + L::cx[i]] - rc);
+            lap *= Real(6);   // 2 / cs2
+            const Real d = rc + fp.shift;
+            mo[l] = Real(2) * fp.a * d + Real(4) * fp.b * d * d * d - fp.kappa * lap;
+        }
+    }
+    // force at the tile site (tx, ty) of plane z
+    static __device__ __forceinline__ void force(const Real* lds_r, const Real* lds_m, int z, int zb,
+                                                 const ForceParams<Real>& fp, Real rho0, int tx,
+                                                 int ty, Real (&F)[3]) {
+        const Real* rp[3] = {lds_r + rslot(z - 1, zb) * NRP, lds_r + rslot(z, zb) * NRP,
+                             lds_r + rslot(z + 1, zb) * NRP};
+        const Real* mp[3] = {lds_m + mslot(z - 1, zb) * NMP, lds_m + mslot(z, zb) * NMP,
+                             lds_m + mslot(z + 1, zb) * NMP};
+        const int cm = (ty + 1) * MX + (tx + 1);
+        const int cr = (ty + 2) * RX + (tx + 2);
+        Real gm[3] = {Real(0), Real(0), Real(0)}, gr[3] = {Real(0), Real(0), Real(0)};
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            const Real mu = mp[1 + L::cz[i]][cm + L::cy[i] * MX + L::cx[i]];
+            const Real rn = rp[1 + L::cz[i]][cr + L::cy[i] * RX + L::cx[i]];
+            const int c3[3] = {L::cx[i], L::cy[i], L::cz[i]};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (c3[a] == 0) continue;
+                const Real wc = Real(L::w[i] * c3[a]);
+                gm[a] += wc * mu;
+                gr[a] += wc * rn;
+            }
+        }
+        const Real rho = rho0 + rp[1][cr];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) F[a] = -rho * Real(3) * gm[a] + fp.eta * gr[a];
+    }
+};
+
 }  // namespace flb

@@ -10,6 +10,7 @@ struct TileShape {
     int tx, ty, tz;   // threads per block in x, y, z
     int spt;          // sites per thread, stacked in y: the site tile is tx x (ty spt) x tz
     int nt;           // 1: populations are stored with non-temporal hints
+    int zc;           // > 0: the block sweeps zc planes in z (D3Q19 force step), tz = 1
 };
 
 // Candidate tiles (the autotuner picks one per handle).
@@ -18,8 +19,10 @@ constexpr TileShape IDEAL_CFG[N_IDEAL_CFG] = {
     {64, 4, 1, 1, 0},  {128, 2, 1, 1, 0}, {256, 1, 1, 1, 0}, {32, 8, 1, 1, 0},
     {128, 2, 1, 2, 0}, {64, 4, 1, 2, 0},  {128, 2, 1, 4, 0}, {256, 1, 1, 2, 0},
     {128, 2, 1, 1, 1}, {256, 1, 1, 1, 1}};
-constexpr int N_FORCE3_CFG = 3;
-constexpr TileShape FORCE3_CFG[N_FORCE3_CFG] = {{32, 4, 2, 1, 0}, {16, 4, 4, 1, 0}, {64, 2, 2, 1, 0}};
+constexpr int N_FORCE3_CFG = 8;
+constexpr TileShape FORCE3_CFG[N_FORCE3_CFG] = {
+    {32, 4, 2, 1, 0}, {16, 4, 4, 1, 0}, {64, 2, 2, 1, 0}, {64, 4, 1, 1, 0, 16},
+    {64, 4, 1, 1, 0, 32}, {32, 8, 1, 1, 0, 16}, {64, 8, 1, 1, 0, 16}, {128, 2, 1, 1, 0, 16}};
 constexpr int N_FORCE2_CFG = 3;
 constexpr TileShape FORCE2_CFG[N_FORCE2_CFG] = {{64, 4, 1, 1, 0}, {32, 8, 1, 1, 0}, {128, 2, 1, 1, 0}};
 

@@ -143,6 +143,104 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
     }
 }
 
+// D3Q19 force step, z-marching form: block b owns the column tile (x0, y0)
+// of TX x TY sites and the planes [zb, zb + ZC) of it (ZC = g.zc).  The density
+// and chemical potential live in LDS ring buffers (ForceMarch); the density
+// plane two ahead is loaded into registers one plane early, and the
+// populations of the current plane are requested before the barriers, so
+// global loads overlap the LDS work.
+template <typename Real, bool STATS, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_step_march(
+    const Real* __restrict__ fin, Real* __restrict__ fout, const Real* __restrict__ drho, Geom g,
+    CollideParams<Real> P, ForceParams<Real> fp, StepIndex st, double* __restrict__ partial) {
+    using L = Lattice<1>;
+    using M = Moments<1, Real>;
+    using FM = ForceMarch<Real, TX, TY>;
+    constexpr int Q = L::Q, NT = TX * TY;
+    constexpr bool ROWS = (TX % 64) == 0;
+    constexpr int LDS_S = STATS ? 4 * ((NT + 63) / 64) * 2 * Q : 1;
+    __shared__ Real lds_r[5 * FM::NRP];
+    __shared__ Real lds_m[3 * FM::NMP];
+    __shared__ double lds_stats[LDS_S];
+
+    const uint32_t b = xcd_remap(blockIdx.x, g.nblocks);
+    const uint32_t ncol = (uint32_t)g.nbx * (uint32_t)g.nby;
+    const uint32_t col = b % ncol, chunk = b / ncol;
+    const int x0 = (int)(col % (uint32_t)g.nbx) * TX, y0 = (int)(col / (uint32_t)g.nbx) * TY;
+    const int zb = (int)chunk * g.zc;
+    const int ze = min(zb + g.zc, g.nz);
+    const int tx = threadIdx.x % TX;
+    int ty = threadIdx.x / TX;
+    if constexpr (ROWS) ty = __builtin_amdgcn_readfirstlane(ty);
+    const int x = x0 + tx, y = y0 + ty;
+    const bool inxy = x < g.nx && y < g.ny;
+
+    uint32_t off[FM::NLD];
+    FM::plane_offsets(g, x0, y0, off);
+    Real rreg[FM::NLD];
+#pragma unroll 1
+    for (int z = zb - 2; z <= zb + 1; ++z) {
+        FM::load_plane(drho, g, off, z, rreg);
+        FM::store_plane(rreg, lds_r + FM::rslot(z, zb) * FM::NRP);
+    }
+    __syncthreads();
+    FM::mu_plane(lds_r, lds_m, zb - 1, zb, fp);
+    FM::mu_plane(lds_r, lds_m, zb, zb, fp);
+    FM::load_plane(drho, g, off, zb + 2, rreg);
+
+    Real v[2 * Q];
+    if constexpr (STATS) {
+#pragma unroll
+        for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
+    }
+    const uint32_t step = st.get();
+#pragma unroll 1
+    for (int z = zb; z < ze; ++z) {
+        FM::store_plane(rreg, lds_r + FM::rslot(z + 2, zb) * FM::NRP);
+        if (z + 1 < ze) FM::load_plane(drho, g, off, z + 3, rreg);
+        // x is re-read each plane, so that per-plane lane addresses are not
+        // hoisted out of the loop (they would hold two VGPRs per plane)
+        int xl = x;
+        asm volatile("" : "+v"(xl));
+        Real f[Q];
+        if (inxy) {
+            if constexpr (ROWS) pull_rows<1, Real>(fin, xl, y, z, g, f);
+            else pull<1, Real>(fin, xl, y, z, g, f);
+        }
+        __syncthreads();
+        FM::mu_plane(lds_r, lds_m, z + 1, zb, fp);
+        __syncthreads();
+        if (inxy) {
+            Real F[3];
+            FM::force(lds_r, lds_m, z, zb, fp, P.rho0, tx, ty, F);
+            Real m[Q];
+            M::forward(f, m);
+            if constexpr (STATS) {
+#pragma unroll
+                for (int a = 0; a < Q; ++a) {
+                    v[a] += m[a];
+                    v[Q + a] += m[a] * m[a];
+                }
+            }
+            const uint32_t site = (uint32_t)((z * g.ny + y) * g.nx + xl);
+            Real zn[2 * L::NPAIR];
+            if (P.noise_on)
+                site_normals<L::NPAIR, Real>(site, step, 0u, P.replica, P.key0, P.key1, zn);
+            collide_moments<1, Real, true>(m, F, zn, P);
+            M::inverse(m, f);
+            if constexpr (ROWS) {
+                const size_t row = (size_t)(uint32_t)((z * g.ny + y) * g.nx);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) plane_st(fout + ((size_t)i * g.V + row), (uint32_t)xl, f[i]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) plane_st(fout + (size_t)i * g.V, site, f[i]);
+            }
+        }
+    }
+    if constexpr (STATS) block_accumulate<2 * Q, NT>(v, partial + (size_t)b * 2 * Q, lds_stats);
+}
+
 // rho and rho u = sum c f + F/2 after streaming of state fin.
 template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX* TY* TZ) void k_fields(const Real* __restrict__ fin,
@@ -242,14 +340,16 @@ TileShape config_shape(int lat, int force, int cfg) {
 }
 
 static Geom make_geom(const StepSpec& s, TileShape t) {
-    Geom g;
+    Geom g{};
     g.nx = s.nx;
     g.ny = s.ny;
     g.nz = s.nz;
     const int ty = t.ty * (t.spt > 1 ? t.spt : 1);
+    const int tz = t.zc > 0 ? t.zc : t.tz;
     g.nbx = (s.nx + t.tx - 1) / t.tx;
     g.nby = (s.ny + ty - 1) / ty;
-    g.nbz = (s.nz + t.tz - 1) / t.tz;
+    g.nbz = (s.nz + tz - 1) / tz;
+    g.zc = t.zc;
     g.nblocks = (uint32_t)g.nbx * g.nby * g.nbz;
     g.V = (uint32_t)s.nx * s.ny * s.nz;
     return g;
@@ -297,7 +397,7 @@ hipError_t launch_init(const StepSpec& s, void* f, const double* drho, hipStream
 }
 
 hipError_t launch_density(const StepSpec& s, const void* fin, void* out, hipStream_t st) {
-    const Geom g = make_geom(s, TileShape{1, 1, 1, 1, 0});
+    const Geom g = make_geom(s, TileShape{1, 1, 1, 1, 0, 0});
     const dim3 grid((g.V + 255) / 256), block(256);
     if (s.lat == 0 && s.prec == 0) hipLaunchKernelGGL((k_density<0, float>), grid, block, 0, st, (const float*)fin, (float*)out, g);
     else if (s.lat == 0) hipLaunchKernelGGL((k_density<0, double>), grid, block, 0, st, (const double*)fin, (double*)out, g);
@@ -309,7 +409,7 @@ hipError_t launch_density(const StepSpec& s, const void* fin, void* out, hipStre
 template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ, int SPT = 1, bool NTS = false>
 static void step_tile(const StepSpec& s, const void* fin, void* fout, const void* drho,
                       StepIndex si, double* partial, hipStream_t st) {
-    const Geom g = make_geom(s, TileShape{TX, TY, TZ, SPT, NTS});
+    const Geom g = make_geom(s, TileShape{TX, TY, TZ, SPT, NTS, 0});
     const dim3 grid(g.nblocks), block(TX * TY * TZ);
     const CollideParams<Real> P = collide_params<Real>(s);
     const ForceParams<Real> fp = force_params<Real>(s);
@@ -319,6 +419,21 @@ static void step_tile(const StepSpec& s, const void* fin, void* fout, const void
     else
         hipLaunchKernelGGL((k_step<LAT, Real, FORCE, false, TX, TY, TZ, SPT, NTS>), grid, block, 0, st,
                            (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
+}
+
+template <typename Real, int TX, int TY>
+static void step_march(const StepSpec& s, int zc, const void* fin, void* fout, const void* drho,
+                       StepIndex si, double* partial, hipStream_t st) {
+    const Geom g = make_geom(s, TileShape{TX, TY, 1, 1, 0, zc});
+    const dim3 grid(g.nblocks), block(TX * TY);
+    const CollideParams<Real> P = collide_params<Real>(s);
+    const ForceParams<Real> fp = force_params<Real>(s);
+    if (partial)
+        hipLaunchKernelGGL((k_step_march<Real, true, TX, TY>), grid, block, 0, st, (const Real*)fin,
+                           (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
+    else
+        hipLaunchKernelGGL((k_step_march<Real, false, TX, TY>), grid, block, 0, st, (const Real*)fin,
+                           (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
 }
 
 template <int LAT, typename Real>
@@ -341,7 +456,12 @@ static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fou
         switch (cfg) {
             case 0: step_tile<LAT, Real, true, 32, 4, 2>(s, fin, fout, drho, si, partial, st); break;
             case 1: step_tile<LAT, Real, true, 16, 4, 4>(s, fin, fout, drho, si, partial, st); break;
-            default: step_tile<LAT, Real, true, 64, 2, 2>(s, fin, fout, drho, si, partial, st); break;
+            case 2: step_tile<LAT, Real, true, 64, 2, 2>(s, fin, fout, drho, si, partial, st); break;
+            case 3: step_march<Real, 64, 4>(s, 16, fin, fout, drho, si, partial, st); break;
+            case 4: step_march<Real, 64, 4>(s, 32, fin, fout, drho, si, partial, st); break;
+            case 5: step_march<Real, 32, 8>(s, 16, fin, fout, drho, si, partial, st); break;
+            case 6: step_march<Real, 64, 8>(s, 16, fin, fout, drho, si, partial, st); break;
+            default: step_march<Real, 128, 2>(s, 16, fin, fout, drho, si, partial, st); break;
         }
     } else {
         switch (cfg) {
@@ -367,7 +487,7 @@ template <int LAT, typename Real, bool FORCE>
 static void fields_launch(const StepSpec& s, const void* fin, const void* drho, void* out,
                           hipStream_t st) {
     constexpr int TX = (LAT == 1) ? 32 : 64, TY = 4, TZ = (LAT == 1) ? 2 : 1;
-    const Geom g = make_geom(s, TileShape{TX, TY, TZ, 1, 0});
+    const Geom g = make_geom(s, TileShape{TX, TY, TZ, 1, 0, 0});
     hipLaunchKernelGGL((k_fields<LAT, Real, FORCE, TX, TY, TZ>), dim3(g.nblocks),
                        dim3(TX * TY * TZ), 0, st, (const Real*)fin, (const Real*)drho, (Real*)out,
                        g, (Real)s.rho0, force_params<Real>(s));

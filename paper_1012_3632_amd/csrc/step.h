@@ -16,6 +16,7 @@ struct Geom {
     int32_t nbx, nby, nbz;   // tiles per direction
     uint32_t nblocks;        // nbx * nby * nbz
     uint32_t V;              // sites
+    int32_t zc;              // z-marching launches: planes per block (else 0)
 };
 
 // Non-ideal force parameters (Landau psi and square-gradient kappa).

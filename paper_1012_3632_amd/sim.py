@@ -242,8 +242,9 @@ class Simulation:
         return n.value, tuple(cur[:])
 
     def launch_shape(self, config):
-        """(tx, ty, tz, sites_per_thread, nontemporal) of a launch configuration."""
-        sh = (C.c_int32 * 5)()
+        """(tx, ty, tz, sites_per_thread, nontemporal, z_planes_per_block) of a
+        launch configuration."""
+        sh = (C.c_int32 * 6)()
         call("flb_launch_shape", self.handle, int(config), sh)
         return tuple(sh[:])
 

@@ -96,11 +96,26 @@ def test_parity_d2q9_landau(precision, eta):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("eta", [0, 1])
-def test_parity_d3q19_landau(precision, eta):
-    kw = dict(W.params_of("d3q19_256_landau", nx=35, ny=13, nz=11), precision=precision, eta=eta)
-    for launch in range(3):
-        sim, fg, fr, _ = run_pair(kw, 25, drho_amp=0.01, launch=launch)
+@pytest.mark.parametrize("shape", [(11, 13, 35), (37, 9, 67)])
+def test_parity_d3q19_landau(precision, eta, shape):
+    """Every launch shape of the force step (3-D tiles and z-marching columns;
+    nz = 37 gives z-marching runs of 16 and 32 planes with a ragged last run)."""
+    nz, ny, nx = shape
+    kw = dict(W.params_of("d3q19_256_landau", nx=nx, ny=ny, nz=nz), precision=precision, eta=eta)
+    for launch in range(n_launch(kw)):
+        sim, fg, fr, _ = run_pair(kw, 12, drho_amp=0.01, launch=launch)
         assert rel_err(fg, fr) < tol(kw), launch
+
+
+def test_landau_statistics_every_launch_d3q19():
+    kw = dict(W.params_of("d3q19_256_landau", nx=67, ny=9, nz=37), precision="fp64", kT=1e-5)
+    for launch in range(n_launch(kw)):
+        sim, fg, fr, st = run_pair(kw, 6, drho_amp=0.01, launch=launch, stats_stride=2)
+        s, s2, ns = sim.moments()
+        assert ns == st["nsamples"] == 3
+        np.testing.assert_allclose(s2, st["sumsq"], rtol=1e-11, err_msg=str(launch))
+        np.testing.assert_allclose(s, st["sum"], rtol=1e-9, atol=1e-10, err_msg=str(launch))
+        sim.close()
 
 
 @pytest.mark.parametrize("lattice,shape", [("D2Q9", (1, 1, 1)), ("D2Q9", (1, 3, 1)),
