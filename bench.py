@@ -199,7 +199,7 @@ def extras(args, stream):
                                rate_bulk=wl["rate_bulk"], rate_shear=wl["rate_shear"],
                                rate_ghost=wl["rate_ghost"]))
     b = Batch(pb, [(e, e, e) for e in edges], seeds=list(range(wl["replicas"])))
-    best, _ = b.autotune(repeats=3)
+    (_, best), _ = b.autotune(repeats=3)
     gsteps = 100
     b.graph_capture(gsteps, stats_stride=1, stream=stream)
     b.graph_launch(stream=stream)

@@ -214,6 +214,10 @@ flb_status flb_destroy(flb_handle* h);
  * Philox key seeds[r] and counter word 3 = r; its populations occupy
  * Q V_r consecutive reals starting at element offset Q * sum_{s<r} V_s of
  * each population buffer (replica-major, then SoA within the replica).
+ * Statistics buffer: a table of per-chunk sums (2Q x chunks FP64, a chunk
+ * being up to 2048 consecutive sites of one replica; rewritten by each
+ * sampled step) followed by the per-replica FP64 accumulators (R x 2Q), to
+ * which each sampled step adds its sums over the replica's chunks.
  * -------------------------------------------------------------------------*/
 typedef struct flb_batch flb_batch;
 
@@ -258,6 +262,10 @@ flb_status flb_launch_configs(const flb_handle* h, int32_t* count, int32_t* curr
  * 1 if populations are stored with non-temporal hints, and the number of z
  * planes a block sweeps (z-marching force step; 0 otherwise). */
 flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape);
+/* The same for a batch: the candidates are persistent grids of 8, 4, 16 or 2
+ * blocks per compute unit; best[2] / best_ms[2] as for flb_autotune.  The
+ * statistics trials write only the per-chunk table that every sampled step
+ * overwrites, so the accumulated statistics are unchanged.  Synchronizes. */
 flb_status flb_batch_autotune(flb_batch* b, int32_t repeats, int32_t* best, double* best_ms,
                               void* stream);
 

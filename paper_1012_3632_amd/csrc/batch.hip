@@ -1,14 +1,20 @@
 // Batched replicas: many independent ideal-gas lattices of uneven size
 // advanced by one persistent launch per step.
 //
-// Every replica's sites are cut into chunks of BT = 256 consecutive sites
-// (x fastest); the chunks of all replicas form one flat tile table.  A grid of
-// (compute units x blocks per CU) workgroups walks the table with a grid
-// stride, so uneven replica sizes cost nothing beyond the last partial wave.
-// Replica r has its own box, Philox key seeds[r] and counter word 3 = r, and
-// its populations start at element Q * sum_{s<r} V_s of each buffer.
-// Statistics: one FP64 slot per tile (fixed tile->slot map), reduced per
-// replica in tile order by k_batch_finalize.
+// Every replica's sites are cut into tiles of BT = 256 consecutive sites
+// (x fastest), and its n tiles are dealt to c = ceil(n / CH) chunks (CH = 8):
+// chunk j holds tiles j, j + c, j + 2c, ... (at most CH, all of one
+// replica).  The chunks of all replicas form one flat table.  Blocks working
+// on neighbouring chunks at the same time therefore touch neighbouring tiles.  A grid of (compute units x blocks per CU) workgroups walks the
+// table with a grid stride, one chunk at a time, so uneven replica sizes cost
+// nothing beyond the last partial wave.  Replica r has its own box, Philox
+// key seeds[r] and counter word 3 = r, and its populations start at element
+// Q * sum_{s<r} V_s of each buffer.
+// Statistics: a thread sums the moments of its CH sites in registers; a
+// sampled step stores each chunk's 2Q FP64 block sums in a value-major table
+// partial[k][chunk] (plain stores, one block reduction per chunk), and
+// k_batch_accumulate then adds, per replica and value, the sum over the
+// replica's chunks (fixed order) to an FP64 accumulator.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,13 +33,14 @@
 namespace flb {
 
 constexpr int BT = 256;   // sites per tile (one per thread)
+constexpr int CH = 8;     // tiles per chunk
 
 struct RepInfo {
     int32_t nx, ny, nz;
     uint32_t V;
     uint64_t off;          // element offset of the replica in a population buffer
     uint32_t key0, key1;
-    uint32_t tile0, ntiles;
+    uint32_t chunk0, nchunks;
     uint32_t inv_nx, inv_ny;   // ceil(2^32 / n): exact division for n < 256, s < 2^24
 };
 
@@ -43,87 +50,102 @@ template <int LAT, typename Real, bool STATS>
 __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
                                                    Real* __restrict__ fout,
                                                    const RepInfo* __restrict__ reps,
-                                                   const uint32_t* __restrict__ tile_rep,
-                                                   uint32_t ntiles, CollideParams<Real> P,
+                                                   const uint32_t* __restrict__ chunk_rep,
+                                                   uint32_t nchunks, CollideParams<Real> P,
                                                    StepIndex st, double* __restrict__ partial) {
     using L = Lattice<LAT>;
     using M = Moments<LAT, Real>;
     constexpr int Q = L::Q, D = L::D;
-    __shared__ double lds_stats[STATS ? 4 * (BT / 64) * 2 * Q : 1];
+    constexpr int LDS1 = 4 * (BT / 64) * 2 * Q;
+    __shared__ double lds_stats[STATS ? 2 * LDS1 : 1];
     const uint32_t step = st.get();
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const uint32_t r = tile_rep[t];
+    uint32_t it = 0;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x, ++it) {
+        const uint32_t r = chunk_rep[c];
         const RepInfo R = reps[r];
         Geom g;
         g.nx = R.nx;
         g.ny = R.ny;
         g.nz = R.nz;
         g.V = R.V;
-        const uint32_t s = (t - R.tile0) * BT + threadIdx.x;
-        Real v[2 * Q];
-        if (s < R.V) {
-            const uint32_t yz = div_small(s, R.inv_nx);
-            const int x = (int)(s - yz * (uint32_t)R.nx);
-            const uint32_t z = div_small(yz, R.inv_ny);
-            const int y = (int)(yz - z * (uint32_t)R.ny);
-            Real f[Q], m[Q];
-            pull<LAT, Real>(fin + R.off, x, y, (int)z, g, f);
-            M::forward(f, m);
-            if constexpr (STATS) {
-#pragma unroll
-                for (int a = 0; a < Q; ++a) {
-                    v[a] = m[a];
-                    v[Q + a] = m[a] * m[a];
-                }
-            }
-            Real zn[2 * L::NPAIR];
-            if (P.noise_on) site_normals<L::NPAIR, Real>(s, step, 0u, r, R.key0, R.key1, zn);
-            const Real F[D] = {};
-            collide_moments<LAT, Real, false>(m, F, zn, P);
-            M::inverse(m, f);
-            Real* out = fout + R.off;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) out[(size_t)i * R.V + s] = f[i];
-        } else if constexpr (STATS) {
+        const uint32_t s0 = (c - R.chunk0) * (uint32_t)BT;
+        const uint32_t ds = R.nchunks * (uint32_t)BT;
+        Real v[STATS ? 2 * Q : 1];
+        if constexpr (STATS) {
 #pragma unroll
             for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
         }
+#pragma unroll 1
+        for (int tt = 0; tt < CH; ++tt) {
+            if (s0 + (uint32_t)tt * ds >= R.V) break;   // chunk with fewer tiles (uniform)
+            const uint32_t s = s0 + (uint32_t)tt * ds + threadIdx.x;
+            if (s < R.V) {
+                const uint32_t yz = div_small(s, R.inv_nx);
+                const int x = (int)(s - yz * (uint32_t)R.nx);
+                const uint32_t z = div_small(yz, R.inv_ny);
+                const int y = (int)(yz - z * (uint32_t)R.ny);
+                Real f[Q], m[Q];
+                pull<LAT, Real>(fin + R.off, x, y, (int)z, g, f);
+                M::forward(f, m);
+                if constexpr (STATS) {
+#pragma unroll
+                    for (int a = 0; a < Q; ++a) {
+                        v[a] += m[a];
+                        v[Q + a] += m[a] * m[a];
+                    }
+                }
+                Real zn[2 * L::NPAIR];
+                if (P.noise_on) site_normals<L::NPAIR, Real>(s, step, 0u, r, R.key0, R.key1, zn);
+                const Real F[D] = {};
+                collide_moments<LAT, Real, false>(m, F, zn, P);
+                M::inverse(m, f);
+                Real* out = fout + R.off;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) out[(size_t)i * R.V + s] = f[i];
+            }
+        }
+        // the two LDS buffers alternate: the barrier inside the finish of
+        // chunk j + 1 orders the reads of chunk j before the writes of j + 2
         if constexpr (STATS) {
-            block_accumulate<2 * Q, BT>(v, partial + (size_t)t * 2 * Q, lds_stats);
-            __syncthreads();   // lds_stats is reused by the next tile
+            double* lds = lds_stats + (it & 1) * LDS1;
+            rows_to_lds<2 * Q, false>(v, lds);
+            lds_rows_finish<2 * Q, BT, false>(lds, partial + c, nchunks);
         }
     }
 }
 
-// out[r][k] = sum over replica r's tiles (in order) of partial[tile][k].
-__global__ void k_batch_finalize(const double* __restrict__ partial,
-                                 const RepInfo* __restrict__ reps, int nvals,
-                                 double* __restrict__ out) {
+// acc[r][k] += sum over replica r's chunks (fixed order) of partial[k][chunk].
+__global__ void k_batch_accumulate(const double* __restrict__ partial,
+                                   const RepInfo* __restrict__ reps, uint32_t nchunks, int nvals,
+                                   double* __restrict__ acc_out) {
     __shared__ double red[256];
     const int k = blockIdx.x, r = blockIdx.y;
     const RepInfo R = reps[r];
+    const double* col = partial + (size_t)k * nchunks + R.chunk0;
     double acc = 0.0;
-    for (uint32_t t = threadIdx.x; t < R.ntiles; t += 256)
-        acc += partial[(size_t)(R.tile0 + t) * nvals + k];
+    for (uint32_t t = threadIdx.x; t < R.nchunks; t += 256) acc += col[t];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[(size_t)r * nvals + k] = red[0];
+    if (threadIdx.x == 0) acc_out[(size_t)r * nvals + k] += red[0];
 }
 
 template <int LAT, typename Real>
 __global__ void k_batch_init(Real* __restrict__ f, const RepInfo* __restrict__ reps,
-                             const uint32_t* __restrict__ tile_rep, uint32_t ntiles) {
+                             const uint32_t* __restrict__ chunk_rep, uint32_t nchunks) {
     using L = Lattice<LAT>;
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const RepInfo R = reps[tile_rep[t]];
-        const uint32_t s = (t - R.tile0) * BT + threadIdx.x;
-        if (s < R.V) {
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const RepInfo R = reps[chunk_rep[c]];
+        const uint32_t s0 = (c - R.chunk0) * (uint32_t)BT;
+        for (int tt = 0; tt < CH; ++tt) {
+            const uint32_t s = s0 + (uint32_t)tt * R.nchunks * (uint32_t)BT + threadIdx.x;
+            if (s < R.V) {
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i) f[R.off + (size_t)i * R.V + s] = Real(0);
+                for (int i = 0; i < L::Q; ++i) f[R.off + (size_t)i * R.V + s] = Real(0);
+            }
         }
     }
 }
@@ -157,7 +179,7 @@ constexpr double CS2 = 1.0 / 3.0;
 
 struct Layout {
     std::vector<RepInfo> reps;
-    std::vector<uint32_t> tile_rep;
+    std::vector<uint32_t> chunk_rep;
     size_t elems;          // reals per population buffer
     size_t reps_off, tiles_off, ctr_off, scratch_bytes, stats_bytes;
 };
@@ -171,9 +193,9 @@ flb_status batch_layout(const flb_params* p, int32_t nrep, const int32_t* dims,
     flb_params q = *p;
     const int Q = p->lattice == FLB_D2Q9 ? 9 : 19;
     L->reps.clear();
-    L->tile_rep.clear();
+    L->chunk_rep.clear();
     size_t off = 0;
-    uint32_t tile = 0;
+    uint32_t chunk = 0;
     for (int r = 0; r < nrep; ++r) {
         q.nx = dims[3 * r];
         q.ny = dims[3 * r + 1];
@@ -196,12 +218,12 @@ flb_status batch_layout(const flb_params* p, int32_t nrep, const int32_t* dims,
         const uint64_t seed = seeds ? seeds[r] : (uint64_t)r;
         R.key0 = (uint32_t)(seed & 0xffffffffu);
         R.key1 = (uint32_t)(seed >> 32);
-        R.tile0 = tile;
-        R.ntiles = (R.V + BT - 1) / BT;
+        R.chunk0 = chunk;
+        R.nchunks = (R.V + CH * BT - 1) / (CH * BT);
         R.inv_nx = (uint32_t)(((1ull << 32) + R.nx - 1) / R.nx);
         R.inv_ny = (uint32_t)(((1ull << 32) + R.ny - 1) / R.ny);
-        for (uint32_t t = 0; t < R.ntiles; ++t) L->tile_rep.push_back((uint32_t)r);
-        tile += R.ntiles;
+        for (uint32_t c = 0; c < R.nchunks; ++c) L->chunk_rep.push_back((uint32_t)r);
+        chunk += R.nchunks;
         off += (size_t)Q * R.V;
         L->reps.push_back(R);
     }
@@ -212,9 +234,9 @@ flb_status batch_layout(const flb_params* p, int32_t nrep, const int32_t* dims,
     L->reps_off = s;
     s += align_up(L->reps.size() * sizeof(RepInfo));
     L->tiles_off = s;
-    s += align_up(L->tile_rep.size() * sizeof(uint32_t));
+    s += align_up(L->chunk_rep.size() * sizeof(uint32_t));
     L->scratch_bytes = s;
-    L->stats_bytes = align_up(((size_t)tile * 2 * Q + (size_t)nrep * 2 * Q) * sizeof(double));
+    L->stats_bytes = align_up(((size_t)chunk * 2 * Q + (size_t)nrep * 2 * Q) * sizeof(double));
     return FLB_OK;
 }
 
@@ -233,10 +255,11 @@ struct flb_batch {
     RepInfo* reps_dev;
     uint32_t* tiles_dev;
     unsigned long long* ctr_dev;
-    uint32_t ntiles;
+    uint32_t nchunks;
     uint64_t step;
     int64_t nsamples;
-    int grid_cfg;
+    int grid_cfg;          // persistent grid of plain steps
+    int grid_cfg_stats;    // persistent grid of steps with statistics
     int ncu;
     hipGraph_t graph;
     hipGraphExec_t gexec;
@@ -274,14 +297,14 @@ void batch_launch(flb_batch* b, int cfg, const void* fin, void* fout,
     P.key0 = P.key1 = 0;   // per replica
     P.replica = 0;
     StepIndex si{step_dev, step_host};
-    const uint32_t grid = std::min<uint32_t>(b->ntiles, (uint32_t)(b->ncu * GRID_PER_CU[cfg]));
+    const uint32_t grid = std::min<uint32_t>(b->nchunks, (uint32_t)(b->ncu * GRID_PER_CU[cfg]));
     if (partial)
         hipLaunchKernelGGL((k_batch_step<LAT, Real, true>), dim3(grid), dim3(BT), 0, st,
-                           (const Real*)fin, (Real*)fout, b->reps_dev, b->tiles_dev, b->ntiles, P,
+                           (const Real*)fin, (Real*)fout, b->reps_dev, b->tiles_dev, b->nchunks, P,
                            si, partial);
     else
         hipLaunchKernelGGL((k_batch_step<LAT, Real, false>), dim3(grid), dim3(BT), 0, st,
-                           (const Real*)fin, (Real*)fout, b->reps_dev, b->tiles_dev, b->ntiles, P,
+                           (const Real*)fin, (Real*)fout, b->reps_dev, b->tiles_dev, b->nchunks, P,
                            si, partial);
 }
 
@@ -296,14 +319,23 @@ hipError_t batch_one(flb_batch* b, int cfg, const void* fin, void* fout,
     return hipGetLastError();
 }
 
+double* batch_acc(flb_batch* b) { return b->stats + (size_t)b->nchunks * 2 * b->q; }
+
 flb_status batch_run(flb_batch* b, int64_t nsteps, int32_t stride, bool graph_mode,
                      hipStream_t st, int64_t* samples) {
     int64_t ns = 0;
+    const int nv = 2 * b->q;
     for (int64_t k = 0; k < nsteps; ++k) {
         const bool sample = stride > 0 && ((k + 1) % stride) == 0;
-        BHIP(batch_one(b, b->grid_cfg, b->cur(), b->other(), graph_mode ? b->ctr_dev : nullptr,
+        BHIP(batch_one(b, sample ? b->grid_cfg_stats : b->grid_cfg, b->cur(), b->other(),
+                       graph_mode ? b->ctr_dev : nullptr,
                        graph_mode ? (unsigned long long)k : (unsigned long long)(b->step + k),
                        sample ? b->stats : nullptr, st));
+        if (sample) {
+            hipLaunchKernelGGL(k_batch_accumulate, dim3(nv, b->nrep), dim3(256), 0, st, b->stats,
+                               b->reps_dev, b->nchunks, nv, batch_acc(b));
+            BHIP(hipGetLastError());
+        }
         b->cur_a = !b->cur_a;
         ns += sample;
     }
@@ -356,10 +388,11 @@ flb_status flb_batch_init(const flb_params* base, int32_t nrep, const int32_t* d
     b->reps_dev = (RepInfo*)(b->scratch + b->L.reps_off);
     b->tiles_dev = (uint32_t*)(b->scratch + b->L.tiles_off);
     b->ctr_dev = (unsigned long long*)(b->scratch + b->L.ctr_off);
-    b->ntiles = (uint32_t)b->L.tile_rep.size();
+    b->nchunks = (uint32_t)b->L.chunk_rep.size();
     b->step = base->step0;
     b->nsamples = 0;
     b->grid_cfg = 0;
+    b->grid_cfg_stats = 0;
     b->graph = nullptr;
     b->gexec = nullptr;
     int dev = 0;
@@ -369,20 +402,20 @@ flb_status flb_batch_init(const flb_params* base, int32_t nrep, const int32_t* d
         e = hipMemcpyAsync(b->reps_dev, b->L.reps.data(), b->L.reps.size() * sizeof(RepInfo),
                            hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b->tiles_dev, b->L.tile_rep.data(), b->ntiles * sizeof(uint32_t),
+        e = hipMemcpyAsync(b->tiles_dev, b->L.chunk_rep.data(), b->nchunks * sizeof(uint32_t),
                            hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_set_u64(b->ctr_dev, b->step, st);
     if (e == hipSuccess) e = launch_fill_zero(stats, b->L.stats_bytes, st);
     if (e == hipSuccess) {
-        const uint32_t grid = std::min<uint32_t>(b->ntiles, 2048);
+        const uint32_t grid = std::min<uint32_t>(b->nchunks, 2048);
         if (b->p.lattice == 0 && b->p.precision == 0)
-            hipLaunchKernelGGL((k_batch_init<0, float>), dim3(grid), dim3(BT), 0, st, (float*)f_a, b->reps_dev, b->tiles_dev, b->ntiles);
+            hipLaunchKernelGGL((k_batch_init<0, float>), dim3(grid), dim3(BT), 0, st, (float*)f_a, b->reps_dev, b->tiles_dev, b->nchunks);
         else if (b->p.lattice == 0)
-            hipLaunchKernelGGL((k_batch_init<0, double>), dim3(grid), dim3(BT), 0, st, (double*)f_a, b->reps_dev, b->tiles_dev, b->ntiles);
+            hipLaunchKernelGGL((k_batch_init<0, double>), dim3(grid), dim3(BT), 0, st, (double*)f_a, b->reps_dev, b->tiles_dev, b->nchunks);
         else if (b->p.precision == 0)
-            hipLaunchKernelGGL((k_batch_init<1, float>), dim3(grid), dim3(BT), 0, st, (float*)f_a, b->reps_dev, b->tiles_dev, b->ntiles);
+            hipLaunchKernelGGL((k_batch_init<1, float>), dim3(grid), dim3(BT), 0, st, (float*)f_a, b->reps_dev, b->tiles_dev, b->nchunks);
         else
-            hipLaunchKernelGGL((k_batch_init<1, double>), dim3(grid), dim3(BT), 0, st, (double*)f_a, b->reps_dev, b->tiles_dev, b->ntiles);
+            hipLaunchKernelGGL((k_batch_init<1, double>), dim3(grid), dim3(BT), 0, st, (double*)f_a, b->reps_dev, b->tiles_dev, b->nchunks);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -411,10 +444,7 @@ flb_status flb_batch_moments(flb_batch* b, double* mode_sum, double* mode_sumsq,
     if (!b) return bfail(FLB_ERR_INVALID_ARG, "batch is NULL");
     hipStream_t st = (hipStream_t)stream;
     const int nv = 2 * b->q;
-    double* out = b->stats + (size_t)b->ntiles * nv;
-    hipLaunchKernelGGL(k_batch_finalize, dim3(nv, b->nrep), dim3(256), 0, st, b->stats,
-                       b->reps_dev, nv, out);
-    BHIP(hipGetLastError());
+    const double* out = batch_acc(b);
     std::vector<double> host((size_t)b->nrep * nv);
     BHIP(hipMemcpyAsync(host.data(), out, host.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     BHIP(hipStreamSynchronize(st));
@@ -488,28 +518,36 @@ flb_status flb_batch_autotune(flb_batch* b, int32_t repeats, int32_t* best, doub
     hipEvent_t e0, e1;
     BHIP(hipEventCreate(&e0));
     BHIP(hipEventCreate(&e1));
-    int bi = b->grid_cfg;
-    float bt = 1e30f;
-    for (int c = 0; c < N_GRID_CFG; ++c) {
-        BHIP(batch_one(b, c, b->cur(), b->other(), nullptr, b->step, nullptr, st));
-        BHIP(hipEventRecord(e0, st));
-        for (int r = 0; r < repeats; ++r)
-            BHIP(batch_one(b, c, b->cur(), b->other(), nullptr, b->step, nullptr, st));
-        BHIP(hipEventRecord(e1, st));
-        BHIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        BHIP(hipEventElapsedTime(&ms, e0, e1));
-        ms /= repeats;
-        if (ms < bt) {
-            bt = ms;
-            bi = c;
+    int bi[2] = {b->grid_cfg, b->grid_cfg_stats};
+    float bt[2] = {1e30f, 1e30f};
+    // statistics trials only write the per-tile table, which every sampled
+    // step overwrites before it is read; the accumulators are not touched
+    for (int mode = 0; mode < 2; ++mode) {
+        double* part = mode ? b->stats : nullptr;
+        for (int c = 0; c < N_GRID_CFG; ++c) {
+            BHIP(batch_one(b, c, b->cur(), b->other(), nullptr, b->step, part, st));
+            BHIP(hipEventRecord(e0, st));
+            for (int r = 0; r < repeats; ++r)
+                BHIP(batch_one(b, c, b->cur(), b->other(), nullptr, b->step, part, st));
+            BHIP(hipEventRecord(e1, st));
+            BHIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            BHIP(hipEventElapsedTime(&ms, e0, e1));
+            ms /= repeats;
+            if (ms < bt[mode]) {
+                bt[mode] = ms;
+                bi[mode] = c;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    b->grid_cfg = bi;
-    if (best) *best = bi;
-    if (best_ms) *best_ms = bt;
+    b->grid_cfg = bi[0];
+    b->grid_cfg_stats = bi[1];
+    for (int m = 0; m < 2; ++m) {
+        if (best) best[m] = bi[m];
+        if (best_ms) best_ms[m] = bt[m];
+    }
     return FLB_OK;
 }
 

@@ -336,9 +336,10 @@ class Batch:
         call("flb_batch_graph_launch", self._h, _stream(stream))
 
     def autotune(self, repeats=3, stream=None):
-        best, ms = C.c_int32(), C.c_double()
-        call("flb_batch_autotune", self._h, int(repeats), C.byref(best), C.byref(ms), _stream(stream))
-        return best.value, ms.value
+        """((grid plain, grid with statistics), (ms plain, ms with statistics))."""
+        best, ms = (C.c_int32 * 2)(), (C.c_double * 2)()
+        call("flb_batch_autotune", self._h, int(repeats), best, ms, _stream(stream))
+        return tuple(best[:]), tuple(ms[:])
 
     def moments(self, stream=None):
         q = self.params.q

@@ -67,12 +67,16 @@ def test_batch_graph_replay_matches_eager():
 def test_batch_autotune_keeps_state():
     from paper_1012_3632_amd import Batch
     b = Batch(gpu_params(**C2, precision="fp32"), DIMS)
-    b.step(2)
+    b.step(2, stats_stride=1)
     before = [b.replica_state(r).clone() for r in range(len(DIMS))]
+    m_before = b.moments()
     best, ms = b.autotune(repeats=2)
-    assert ms > 0
+    assert all(t > 0 for t in ms) and all(0 <= c < 4 for c in best)
     for r in range(len(DIMS)):
         assert torch.equal(before[r], b.replica_state(r))
+    m_after = b.moments()
+    for x, y in zip(m_before, m_after):
+        np.testing.assert_array_equal(x, y)
 
 
 def test_batch64_workload_fdt():
