@@ -242,25 +242,38 @@ flb_status flb_batch_graph_capture(flb_batch* b, int64_t nsteps, int32_t stats_s
 flb_status flb_batch_graph_launch(flb_batch* b, void* stream);
 flb_status flb_batch_destroy(flb_batch* b);
 
-/* Launch shapes in use and autotuning.  A handle keeps two launch shapes:
- * one for steps without statistics and one for steps that accumulate them.
+/* Launch shapes in use and autotuning.  A handle keeps a launch shape for
+ * steps without statistics, one for steps that accumulate them and, for the
+ * ideal gas, optionally an in-place shape: consecutive pairs of steps then
+ * run in place on the current population buffer (the first step of a pair
+ * pulls and stores each result in the opposite-velocity plane at x + c_i, the
+ * second reads that plane locally and restores the ordinary layout), which
+ * halves the working set; populations, statistics and noise are bit-identical
+ * to ordinary steps, and a lone last step of a call runs the ordinary kernel.
  * flb_autotune times every candidate launch shape of the handle's step kernel
- * (block size, sites per thread, store hints; tile shape for the force
- * kernel) in both modes on its own buffers, without changing the state or the
- * accumulated statistics, keeps the fastest of each and writes best[2] (shape
- * indices) and best_ms[2] (ms per step), entry 0 for plain steps and entry 1
- * for steps with statistics (either pointer may be NULL).  The statistics
- * trials run on the handle's own slots, saved to host memory before and
- * restored after; the call synchronizes the stream.
- * flb_set_launch sets both shapes; flb_launch_configs writes the number of
- * shapes and current[2] (plain, with statistics). */
+ * (block size, sites per thread, store hints, in-place pairs; tile or
+ * z-marching shape for the force kernel) the way a run uses it (ordinary
+ * steps alternate the two buffers, pairs work in place) and afterwards
+ * restores the state and the accumulated statistics from a host copy (host
+ * memory of one population buffer plus the statistics slots); it writes
+ * best[4]: the fastest shape for plain steps, for steps with statistics, the
+ * fastest in-place shape (-1 if none) and the in-place shape now in use (-1:
+ * pairs are used only if they beat ordinary steps with statistics); and
+ * best_ms[3]: ms per step of the first three (either pointer may be NULL).
+ * The statistics trials run on the handle's own slots, saved to host memory
+ * before and restored after; the call synchronizes the stream.
+ * flb_set_launch sets every shape to `config` (an in-place shape then serves
+ * pairs and, as an ordinary kernel of its tile, lone steps);
+ * flb_launch_configs writes the number of shapes and current[3] (plain, with
+ * statistics, in-place or -1). */
 flb_status flb_autotune(flb_handle* h, int32_t repeats, int32_t* best, double* best_ms,
                         void* stream);
 flb_status flb_set_launch(flb_handle* h, int32_t config);
 flb_status flb_launch_configs(const flb_handle* h, int32_t* count, int32_t* current);
-/* shape[6] = threads per block in x, y, z, sites per thread (stacked in y),
- * 1 if populations are stored with non-temporal hints, and the number of z
- * planes a block sweeps (z-marching force step; 0 otherwise). */
+/* shape[7] = threads per block in x, y, z, sites per thread (stacked in y),
+ * 1 if populations are stored with non-temporal hints, the number of z planes
+ * a block sweeps (z-marching force step; 0 otherwise), and 1 for an in-place
+ * shape. */
 flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape);
 /* The same for a batch: the candidates are persistent grids of 8, 4, 16 or 2
  * blocks per compute unit; best[2] / best_ms[2] as for flb_autotune.  The

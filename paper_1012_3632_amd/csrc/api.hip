@@ -150,6 +150,7 @@ struct flb_handle {
     int64_t nsamples;
     int cfg;                // launch shape of steps without statistics
     int cfg_stats;          // launch shape of steps that accumulate statistics
+    int pair_cfg;           // in-place shape for pairs of steps, or -1
     hipGraph_t graph;
     hipGraphExec_t gexec;
     int64_t graph_steps, graph_samples;
@@ -191,13 +192,27 @@ flb_status do_step(flb_handle* h, bool sample, const unsigned long long* step_de
 flb_status run_steps(flb_handle* h, int64_t nsteps, int32_t stride, bool graph_mode,
                      hipStream_t st, int64_t* samples) {
     int64_t ns = 0;
-    for (int64_t k = 0; k < nsteps; ++k) {
+    const unsigned long long* dev = graph_mode ? h->step_dev : nullptr;
+    const unsigned long long base = graph_mode ? 0ull : (unsigned long long)h->step;
+    for (int64_t k = 0; k < nsteps;) {
         const bool sample = stride > 0 && ((k + 1) % stride) == 0;
-        flb_status r;
-        if (graph_mode) r = do_step(h, sample, h->step_dev, (unsigned long long)k, st);
-        else r = do_step(h, sample, nullptr, (unsigned long long)(h->step + k), st);
+        if (h->pair_cfg >= 0 && k + 1 < nsteps) {
+            // two steps in place on the current buffer (no swap)
+            const bool sample1 = stride > 0 && ((k + 2) % stride) == 0;
+            HIP_TRY(launch_step_in_place(h->spec, h->pair_cfg, 0, h->cur(), dev,
+                                         base + (unsigned long long)k,
+                                         sample ? h->stats : nullptr, st));
+            HIP_TRY(launch_step_in_place(h->spec, h->pair_cfg, 1, h->cur(), dev,
+                                         base + (unsigned long long)(k + 1),
+                                         sample1 ? h->stats : nullptr, st));
+            ns += (int64_t)sample + (int64_t)sample1;
+            k += 2;
+            continue;
+        }
+        flb_status r = do_step(h, sample, dev, base + (unsigned long long)k, st);
         if (r != FLB_OK) return r;
         ns += sample;
+        ++k;
     }
     if (graph_mode) HIP_TRY(launch_add_u64(h->step_dev, (unsigned long long)nsteps, st));
     *samples = ns;
@@ -290,6 +305,7 @@ flb_status flb_init(const flb_params* p, void* f_a, void* f_b, void* scratch, vo
     h->nsamples = 0;
     h->cfg = 0;
     h->cfg_stats = 0;
+    h->pair_cfg = -1;
     h->graph = nullptr;
     h->gexec = nullptr;
     size_t drho_off, adj_off, gp_off, total;
@@ -444,53 +460,93 @@ flb_status flb_autotune(flb_handle* h, int32_t repeats, int32_t* best, double* b
     if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
     if (repeats < 1) repeats = 1;
     hipStream_t st = (hipStream_t)stream;
-    // the statistics trials accumulate into the handle's own slots: their
-    // contents are saved to host memory first and put back afterwards
+    // Trials run as real stepping does (ordinary steps alternate the two
+    // buffers, pairs update one buffer in place), so cache residency is the
+    // same as in a run.  The state and the statistics slots are saved to host
+    // memory first and put back afterwards.
     const size_t pbytes = ((size_t)h->slots + 1) * 2 * h->q * sizeof(double);
-    std::vector<double> saved(pbytes / sizeof(double));
-    double* trial_stats = h->stats;
+    const size_t sbytes = (size_t)h->q * h->V * h->real_bytes;
+    std::vector<double> saved_stats(pbytes / sizeof(double));
+    std::vector<unsigned char> saved_state;
+    try {
+        saved_state.resize(sbytes);
+    } catch (...) {
+        return fail(FLB_ERR_INVALID_ARG, "autotune: no host memory for a copy of the state");
+    }
+    void* const A = h->cur();
+    void* const B = h->other();
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipMemcpyAsync(saved.data(), h->stats, pbytes, hipMemcpyDeviceToHost, st);
+    hipError_t e = hipMemcpyAsync(saved_stats.data(), h->stats, pbytes, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(saved_state.data(), A, sbytes, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     const int ncfg = n_configs(h->spec.lat, h->spec.force);
     int bi[2] = {h->cfg, h->cfg_stats};
     float bt[2] = {1e30f, 1e30f};
-    // each trial writes cur -> other without swapping or counting: the state is unchanged
-    if (e == hipSuccess && h->spec.force) e = launch_density(h->spec, h->cur(), h->drho, st);
+    if (e == hipSuccess && h->spec.force) e = launch_density(h->spec, A, h->drho, st);
+    auto timed = [&](auto&& launch, int per_call, float* ms_out) {
+        hipError_t r = launch(0);   // warm-up
+        if (r == hipSuccess) r = hipEventRecord(e0, st);
+        for (int k = 1; k <= repeats && r == hipSuccess; ++k) r = launch(k);
+        if (r == hipSuccess) r = hipEventRecord(e1, st);
+        if (r == hipSuccess) r = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+        *ms_out = ms / (float)(repeats * per_call);
+        return r;
+    };
     for (int mode = 0; mode < 2 && e == hipSuccess; ++mode) {
-        double* part = mode ? trial_stats : nullptr;
+        double* part = mode ? h->stats : nullptr;
         for (int c = 0; c < ncfg && e == hipSuccess; ++c) {
-            e = launch_step(h->spec, c, h->cur(), h->other(), h->drho, nullptr, h->step, part, st);
-            if (e == hipSuccess) e = hipEventRecord(e0, st);
-            for (int r = 0; r < repeats && e == hipSuccess; ++r)
-                e = launch_step(h->spec, c, h->cur(), h->other(), h->drho, nullptr, h->step, part,
-                                st);
-            if (e == hipSuccess) e = hipEventRecord(e1, st);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (config_in_place(h->spec, c)) continue;   // timed as pairs below
             float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            ms /= repeats;
+            e = timed([&](int k) {
+                return launch_step(h->spec, c, (k & 1) ? B : A, (k & 1) ? A : B, h->drho, nullptr,
+                                   h->step, part, st);
+            }, 1, &ms);
             if (e == hipSuccess && ms < bt[mode]) {
                 bt[mode] = ms;
                 bi[mode] = c;
             }
         }
     }
+    int best_pair = -1;
+    float pair_ms = 1e30f;
+    for (int c = 0; c < ncfg && e == hipSuccess; ++c) {
+        if (!config_in_place(h->spec, c)) continue;
+        float ms = 0.f;
+        e = timed([&](int) {
+            hipError_t r = launch_step_in_place(h->spec, c, 0, A, nullptr, h->step, h->stats, st);
+            if (r == hipSuccess)
+                r = launch_step_in_place(h->spec, c, 1, A, nullptr, h->step + 1, h->stats, st);
+            return r;
+        }, 2, &ms);   // per step, statistics every step
+        if (e == hipSuccess && ms < pair_ms) {
+            pair_ms = ms;
+            best_pair = c;
+        }
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    // restore the sums even after a failed trial
-    hipError_t er = hipMemcpyAsync(h->stats, saved.data(), pbytes, hipMemcpyHostToDevice, st);
+    // restore the state and the sums even after a failed trial
+    hipError_t er = hipMemcpyAsync(A, saved_state.data(), sbytes, hipMemcpyHostToDevice, st);
+    if (er == hipSuccess)
+        er = hipMemcpyAsync(h->stats, saved_stats.data(), pbytes, hipMemcpyHostToDevice, st);
     if (er == hipSuccess) er = hipStreamSynchronize(st);
     if (e == hipSuccess) e = er;
     if (e != hipSuccess) return fail(FLB_ERR_HIP, "autotune: %s", hipGetErrorString(e));
     h->cfg = bi[0];
     h->cfg_stats = bi[1];
+    // pairs are used when they beat ordinary steps with statistics
+    h->pair_cfg = (best_pair >= 0 && pair_ms < bt[1]) ? best_pair : -1;
     for (int m = 0; m < 2; ++m) {
         if (best) best[m] = bi[m];
         if (best_ms) best_ms[m] = bt[m];
     }
+    if (best) best[2] = best_pair;
+    if (best_ms) best_ms[2] = best_pair >= 0 ? pair_ms : 0.0;
+    if (best) best[3] = h->pair_cfg;
     return FLB_OK;
 }
 
@@ -498,8 +554,13 @@ flb_status flb_set_launch(flb_handle* h, int32_t config) {
     if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
     if (config < 0 || config >= n_configs(h->spec.lat, h->spec.force))
         return fail(FLB_ERR_INVALID_ARG, "launch config %d out of range", config);
-    h->cfg = config;
-    h->cfg_stats = config;
+    if (config_in_place(h->spec, config)) {
+        h->pair_cfg = config;
+        h->cfg = h->cfg_stats = config;   // a lone step runs the ordinary kernel of this tile
+    } else {
+        h->pair_cfg = -1;
+        h->cfg = h->cfg_stats = config;
+    }
     return FLB_OK;
 }
 
@@ -509,6 +570,7 @@ flb_status flb_launch_configs(const flb_handle* h, int32_t* count, int32_t* curr
     if (current) {
         current[0] = h->cfg;
         current[1] = h->cfg_stats;
+        current[2] = h->pair_cfg;
     }
     return FLB_OK;
 }
@@ -524,6 +586,7 @@ flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape)
     shape[3] = t.spt;
     shape[4] = t.nt;
     shape[5] = t.zc;
+    shape[6] = t.ip;
     return FLB_OK;
 }
 

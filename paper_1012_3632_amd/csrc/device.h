@@ -71,6 +71,45 @@ __device__ __forceinline__ void pull_rows(const Real* __restrict__ fin, int x, i
     }
 }
 
+// In-place step pairs (one population buffer).  The first step of a pair
+// pulls S_i(x - c_i) from plane i and stores its result S*_i(x) in plane
+// opp(i) at x + c_i; the second reads plane opp(i) at x (which then holds
+// S*_i(x - c_i), i.e. the streamed population) and stores S**_i(x) in plane i
+// at x, the ordinary layout again.  Each location a thread writes is one it
+// has itself read, and no other thread touches it, so the update is in place.
+template <int LAT, typename Real>
+__device__ __forceinline__ void push_rows_opp(Real* f, int x, int y, int z, const Geom& g,
+                                              const Real (&v)[Lattice<LAT>::Q]) {
+    using L = Lattice<LAT>;
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int dx = L::cx[i] == 0 ? x : (L::cx[i] > 0 ? xp : xm);
+        const int dy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? yp : ym);
+        const int dz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zp : zm);
+        Real* row = f + ((size_t)L::opp[i] * g.V + (size_t)(uint32_t)((dz * g.ny + dy) * g.nx));
+        plane_st(row, (uint32_t)dx, v[i]);
+    }
+}
+template <int LAT, typename Real>
+__device__ __forceinline__ void load_rows_opp(const Real* f, int x, int y, int z, const Geom& g,
+                                              Real (&v)[Lattice<LAT>::Q]) {
+    using L = Lattice<LAT>;
+    const size_t row = (size_t)(uint32_t)((z * g.ny + y) * g.nx);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) v[i] = plane_ld(f + ((size_t)L::opp[i] * g.V + row), (uint32_t)x);
+}
+template <int LAT, typename Real>
+__device__ __forceinline__ void store_rows(Real* f, int x, int y, int z, const Geom& g,
+                                           const Real (&v)[Lattice<LAT>::Q]) {
+    using L = Lattice<LAT>;
+    const size_t row = (size_t)(uint32_t)((z * g.ny + y) * g.nx);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) plane_st(f + ((size_t)i * g.V + row), (uint32_t)x, v[i]);
+}
+
 // Row sums with DPP lane shifts (no LDS traffic): four row_shr steps leave the
 // sum of each 16-lane row in its lane 15.  Out-of-row source lanes read 0 (old
 // operand 0).  Stage-outer over NV independent values, so consecutive DPP reads

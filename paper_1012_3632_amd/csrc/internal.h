@@ -11,14 +11,17 @@ struct TileShape {
     int spt;          // sites per thread, stacked in y: the site tile is tx x (ty spt) x tz
     int nt;           // 1: populations are stored with non-temporal hints
     int zc;           // > 0: the block sweeps zc planes in z (D3Q19 force step), tz = 1
+    int ip;           // 1: in-place step pairs in one buffer (ideal gas); a lone
+                      //    step runs the ordinary kernel of the same tile
 };
 
 // Candidate tiles (the autotuner picks one per handle).
-constexpr int N_IDEAL_CFG = 10;
+constexpr int N_IDEAL_CFG = 13;
 constexpr TileShape IDEAL_CFG[N_IDEAL_CFG] = {
     {64, 4, 1, 1, 0},  {128, 2, 1, 1, 0}, {256, 1, 1, 1, 0}, {32, 8, 1, 1, 0},
     {128, 2, 1, 2, 0}, {64, 4, 1, 2, 0},  {128, 2, 1, 4, 0}, {256, 1, 1, 2, 0},
-    {128, 2, 1, 1, 1}, {256, 1, 1, 1, 1}};
+    {128, 2, 1, 1, 1}, {256, 1, 1, 1, 1}, {128, 2, 1, 1, 0, 0, 1}, {64, 4, 1, 1, 0, 0, 1},
+    {256, 1, 1, 1, 0, 0, 1}};
 constexpr int N_FORCE3_CFG = 8;
 constexpr TileShape FORCE3_CFG[N_FORCE3_CFG] = {
     {32, 4, 2, 1, 0}, {16, 4, 4, 1, 0}, {64, 2, 2, 1, 0}, {64, 4, 1, 1, 0, 16},
@@ -53,6 +56,12 @@ hipError_t launch_density(const StepSpec& s, const void* fin, void* drho_out, hi
 hipError_t launch_step(const StepSpec& s, int cfg, const void* fin, void* fout, const void* drho,
                        const unsigned long long* step_dev, unsigned long long step_host,
                        double* partial, hipStream_t st);
+// In-place shapes: one step of a pair on the single buffer f (phase 0 then 1;
+// see push_rows_opp).  The state is in the ordinary layout after phase 1.
+bool config_in_place(const StepSpec& s, int cfg);
+hipError_t launch_step_in_place(const StepSpec& s, int cfg, int phase, void* f,
+                                const unsigned long long* step_dev, unsigned long long step_host,
+                                double* partial, hipStream_t st);
 hipError_t launch_fields(const StepSpec& s, const void* fin, const void* drho, void* out,
                          hipStream_t st);
 hipError_t launch_stats_finalize(const double* partial, uint32_t nslots, int nvals, double* out,

@@ -143,6 +143,64 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
     }
 }
 
+// One step of an in-place pair (ideal gas), phase PH = 0 (pull, push to the
+// opposite plane at x + c_i) or 1 (local read of the opposite plane, store in
+// the ordinary layout); see push_rows_opp.  Tiles of TX x TY sites, TX a
+// multiple of 64; the collision, noise counters and statistics are those of
+// k_step, so a pair gives bit-identical populations to two ordinary steps.
+// With one buffer instead of two the working set of a lattice is halved,
+// which lets a 128^3 FP32 D3Q19 state stay in the 256 MB last-level cache.
+template <int LAT, typename Real, bool STATS, int PH, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_step_ip(Real* f, Geom g, CollideParams<Real> P,
+                                                     StepIndex st, double* __restrict__ partial) {
+    using L = Lattice<LAT>;
+    using M = Moments<LAT, Real>;
+    constexpr int Q = L::Q, D = L::D, NT = TX * TY;
+    static_assert(TX % 64 == 0, "one (y, z) row per wavefront");
+    constexpr int LDS_S = STATS ? 4 * (NT / 64) * 2 * Q : 1;
+    __shared__ double lds_stats[LDS_S];
+    int x0, y0, z0;
+    tile_origin<LAT, TX, TY, 1>(g, x0, y0, z0);
+    const int tx = threadIdx.x % TX;
+    const int ty = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / TX));
+    const int x = x0 + tx, y = y0 + ty, z = z0;
+    Real v[STATS ? 2 * Q : 1];
+    if constexpr (STATS) {
+#pragma unroll
+        for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
+    }
+    if (x < g.nx && y < g.ny && z < g.nz) {
+        Real fl[Q], m[Q];
+        if constexpr (PH == 0) pull_rows<LAT, Real>(f, x, y, z, g, fl);
+        else load_rows_opp<LAT, Real>(f, x, y, z, g, fl);
+        M::forward(fl, m);
+        if constexpr (STATS) {
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                v[a] = m[a];
+                v[Q + a] = m[a] * m[a];
+            }
+        }
+        const uint32_t site = site_index<LAT>(x, y, z, g);
+        Real zn[2 * L::NPAIR];
+        if (P.noise_on)
+            site_normals<L::NPAIR, Real>(site, st.get(), 0u, P.replica, P.key0, P.key1, zn);
+        const Real F[D] = {};
+        collide_moments<LAT, Real, false>(m, F, zn, P);
+        M::inverse(m, fl);
+        // x is re-read here so that the store addresses are formed late
+        // (not held in registers through the collision)
+        int xs = x;
+        asm volatile("" : "+v"(xs));
+        if constexpr (PH == 0) push_rows_opp<LAT, Real>(f, xs, y, z, g, fl);
+        else store_rows<LAT, Real>(f, xs, y, z, g, fl);
+    }
+    if constexpr (STATS) {
+        const uint32_t b = xcd_remap(blockIdx.x, g.nblocks);
+        block_accumulate<2 * Q, NT>(v, partial + (size_t)b * 2 * Q, lds_stats);
+    }
+}
+
 // D3Q19 force step, z-marching form: block b owns the column tile (x0, y0)
 // of TX x TY sites and the planes [zb, zb + ZC) of it (ZC = g.zc).  The density
 // and chemical potential live in LDS ring buffers (ForceMarch); the density
@@ -397,7 +455,7 @@ hipError_t launch_init(const StepSpec& s, void* f, const double* drho, hipStream
 }
 
 hipError_t launch_density(const StepSpec& s, const void* fin, void* out, hipStream_t st) {
-    const Geom g = make_geom(s, TileShape{1, 1, 1, 1, 0, 0});
+    const Geom g = make_geom(s, TileShape{1, 1, 1, 1, 0, 0, 0});
     const dim3 grid((g.V + 255) / 256), block(256);
     if (s.lat == 0 && s.prec == 0) hipLaunchKernelGGL((k_density<0, float>), grid, block, 0, st, (const float*)fin, (float*)out, g);
     else if (s.lat == 0) hipLaunchKernelGGL((k_density<0, double>), grid, block, 0, st, (const double*)fin, (double*)out, g);
@@ -409,7 +467,7 @@ hipError_t launch_density(const StepSpec& s, const void* fin, void* out, hipStre
 template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ, int SPT = 1, bool NTS = false>
 static void step_tile(const StepSpec& s, const void* fin, void* fout, const void* drho,
                       StepIndex si, double* partial, hipStream_t st) {
-    const Geom g = make_geom(s, TileShape{TX, TY, TZ, SPT, NTS, 0});
+    const Geom g = make_geom(s, TileShape{TX, TY, TZ, SPT, NTS, 0, 0});
     const dim3 grid(g.nblocks), block(TX * TY * TZ);
     const CollideParams<Real> P = collide_params<Real>(s);
     const ForceParams<Real> fp = force_params<Real>(s);
@@ -424,7 +482,7 @@ static void step_tile(const StepSpec& s, const void* fin, void* fout, const void
 template <typename Real, int TX, int TY>
 static void step_march(const StepSpec& s, int zc, const void* fin, void* fout, const void* drho,
                        StepIndex si, double* partial, hipStream_t st) {
-    const Geom g = make_geom(s, TileShape{TX, TY, 1, 1, 0, zc});
+    const Geom g = make_geom(s, TileShape{TX, TY, 1, 1, 0, zc, 0});
     const dim3 grid(g.nblocks), block(TX * TY);
     const CollideParams<Real> P = collide_params<Real>(s);
     const ForceParams<Real> fp = force_params<Real>(s);
@@ -450,7 +508,11 @@ static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fou
             case 6: step_tile<LAT, Real, false, 128, 2, 1, 4>(s, fin, fout, drho, si, partial, st); break;
             case 7: step_tile<LAT, Real, false, 256, 1, 1, 2>(s, fin, fout, drho, si, partial, st); break;
             case 8: step_tile<LAT, Real, false, 128, 2, 1, 1, true>(s, fin, fout, drho, si, partial, st); break;
-            default: step_tile<LAT, Real, false, 256, 1, 1, 1, true>(s, fin, fout, drho, si, partial, st); break;
+            case 9: step_tile<LAT, Real, false, 256, 1, 1, 1, true>(s, fin, fout, drho, si, partial, st); break;
+            // in-place shapes: a lone step (not part of a pair) uses the ordinary kernel
+            case 10: step_tile<LAT, Real, false, 128, 2, 1, 1>(s, fin, fout, drho, si, partial, st); break;
+            case 11: step_tile<LAT, Real, false, 64, 4, 1, 1>(s, fin, fout, drho, si, partial, st); break;
+            default: step_tile<LAT, Real, false, 256, 1, 1, 1>(s, fin, fout, drho, si, partial, st); break;
         }
     } else if constexpr (LAT == 1) {
         switch (cfg) {
@@ -472,6 +534,47 @@ static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fou
     }
 }
 
+template <int LAT, typename Real, int TX, int TY>
+static void step_ip(const StepSpec& s, int phase, void* f, StepIndex si, double* partial,
+                    hipStream_t st) {
+    const Geom g = make_geom(s, TileShape{TX, TY, 1, 1, 0, 0, 1});
+    const dim3 grid(g.nblocks), block(TX * TY);
+    const CollideParams<Real> P = collide_params<Real>(s);
+    if (phase == 0) {
+        if (partial) hipLaunchKernelGGL((k_step_ip<LAT, Real, true, 0, TX, TY>), grid, block, 0, st, (Real*)f, g, P, si, partial);
+        else hipLaunchKernelGGL((k_step_ip<LAT, Real, false, 0, TX, TY>), grid, block, 0, st, (Real*)f, g, P, si, partial);
+    } else {
+        if (partial) hipLaunchKernelGGL((k_step_ip<LAT, Real, true, 1, TX, TY>), grid, block, 0, st, (Real*)f, g, P, si, partial);
+        else hipLaunchKernelGGL((k_step_ip<LAT, Real, false, 1, TX, TY>), grid, block, 0, st, (Real*)f, g, P, si, partial);
+    }
+}
+
+template <int LAT, typename Real>
+static void ip_dispatch(const StepSpec& s, int cfg, int phase, void* f, StepIndex si,
+                        double* partial, hipStream_t st) {
+    switch (cfg) {
+        case 10: step_ip<LAT, Real, 128, 2>(s, phase, f, si, partial, st); break;
+        case 11: step_ip<LAT, Real, 64, 4>(s, phase, f, si, partial, st); break;
+        default: step_ip<LAT, Real, 256, 1>(s, phase, f, si, partial, st); break;
+    }
+}
+
+bool config_in_place(const StepSpec& s, int cfg) {
+    return cfg >= 0 && cfg < n_configs(s.lat, s.force) && config_shape(s.lat, s.force, cfg).ip;
+}
+
+hipError_t launch_step_in_place(const StepSpec& s, int cfg, int phase, void* f,
+                                const unsigned long long* step_dev, unsigned long long step_host,
+                                double* partial, hipStream_t st) {
+    if (!config_in_place(s, cfg) || phase < 0 || phase > 1) return hipErrorInvalidValue;
+    StepIndex si{step_dev, step_host};
+    if (s.lat == 0 && s.prec == 0) ip_dispatch<0, float>(s, cfg, phase, f, si, partial, st);
+    else if (s.lat == 0) ip_dispatch<0, double>(s, cfg, phase, f, si, partial, st);
+    else if (s.prec == 0) ip_dispatch<1, float>(s, cfg, phase, f, si, partial, st);
+    else ip_dispatch<1, double>(s, cfg, phase, f, si, partial, st);
+    return hipGetLastError();
+}
+
 hipError_t launch_step(const StepSpec& s, int cfg, const void* fin, void* fout, const void* drho,
                        const unsigned long long* step_dev, unsigned long long step_host,
                        double* partial, hipStream_t st) {
@@ -487,7 +590,7 @@ template <int LAT, typename Real, bool FORCE>
 static void fields_launch(const StepSpec& s, const void* fin, const void* drho, void* out,
                           hipStream_t st) {
     constexpr int TX = (LAT == 1) ? 32 : 64, TY = 4, TZ = (LAT == 1) ? 2 : 1;
-    const Geom g = make_geom(s, TileShape{TX, TY, TZ, 1, 0, 0});
+    const Geom g = make_geom(s, TileShape{TX, TY, TZ, 1, 0, 0, 0});
     hipLaunchKernelGGL((k_fields<LAT, Real, FORCE, TX, TY, TZ>), dim3(g.nblocks),
                        dim3(TX * TY * TZ), 0, st, (const Real*)fin, (const Real*)drho, (Real*)out,
                        g, (Real)s.rho0, force_params<Real>(s));

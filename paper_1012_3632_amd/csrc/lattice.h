@@ -54,6 +54,7 @@ template <> struct Lattice<0> {
                                    CLS_GHOST, CLS_GHOST, CLS_GHOST};
     static constexpr int odd[Q] = {0, 1, 1, 0, 0, 0, 1, 1, 0};
     static constexpr int pair[NP][2] = {{1, 3}, {2, 4}, {5, 7}, {6, 8}};
+    static constexpr int opp[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};   // c_opp(i) = -c_i
 };
 
 // ---------------------------------------------------------------- D3Q19
@@ -102,6 +103,20 @@ template <> struct Lattice<1> {
     static constexpr int odd[Q] = {0, 1, 1, 1, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 0, 0, 0};
     static constexpr int pair[NP][2] = {{1, 2},   {3, 4},   {5, 6},   {7, 10},  {8, 9},
                                         {11, 14}, {12, 13}, {15, 18}, {16, 17}};
+    static constexpr int opp[Q] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
 };
+
+// opp really maps every velocity to its negative
+template <int LAT>
+constexpr bool opp_ok() {
+    using L = Lattice<LAT>;
+    for (int i = 0; i < L::Q; ++i) {
+        const int j = L::opp[i];
+        if (L::cx[j] != -L::cx[i] || L::cy[j] != -L::cy[i] || L::cz[j] != -L::cz[i]) return false;
+        if (L::opp[j] != i) return false;
+    }
+    return true;
+}
+static_assert(opp_ok<0>() && opp_ok<1>(), "opposite-velocity tables");
 
 }  // namespace flb

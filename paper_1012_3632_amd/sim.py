@@ -226,9 +226,10 @@ class Simulation:
         call("flb_graph_launch", self.handle, _stream(stream))
 
     def autotune(self, repeats=5, stream=None):
-        """Time every launch shape, for steps without and with statistics;
-        returns ((shape_plain, shape_stats), (ms_plain, ms_stats))."""
-        best, ms = (C.c_int32 * 2)(), (C.c_double * 2)()
+        """Time every launch shape; returns
+        ((shape_plain, shape_stats, best_in_place or -1, in_place_in_use or -1),
+         (ms_plain, ms_stats, ms_in_place))."""
+        best, ms = (C.c_int32 * 4)(), (C.c_double * 3)()
         call("flb_autotune", self.handle, int(repeats), best, ms, _stream(stream))
         return tuple(best[:]), tuple(ms[:])
 
@@ -236,15 +237,16 @@ class Simulation:
         call("flb_set_launch", self.handle, int(config))
 
     def launch_configs(self):
-        """(number of launch shapes, (shape of plain steps, shape of steps with statistics))."""
-        n, cur = C.c_int32(), (C.c_int32 * 2)()
+        """(number of launch shapes, (shape of plain steps, shape of steps with
+        statistics, in-place shape or -1))."""
+        n, cur = C.c_int32(), (C.c_int32 * 3)()
         call("flb_launch_configs", self.handle, C.byref(n), cur)
         return n.value, tuple(cur[:])
 
     def launch_shape(self, config):
-        """(tx, ty, tz, sites_per_thread, nontemporal, z_planes_per_block) of a
-        launch configuration."""
-        sh = (C.c_int32 * 6)()
+        """(tx, ty, tz, sites_per_thread, nontemporal, z_planes_per_block,
+        in_place) of a launch configuration."""
+        sh = (C.c_int32 * 7)()
         call("flb_launch_shape", self.handle, int(config), sh)
         return tuple(sh[:])
 

@@ -157,7 +157,7 @@ def test_fields_match_oracle(force):
 
 def test_full_size_step_parity_d3q19_128():
     """d3q19_128 at full size in the launch shape the autotuner picks (the one
-    the benchmark times): the GPU state after 40 steps is advanced one step by
+    the benchmark times): the GPU state after 40 steps is advanced two steps by
     the oracle and by the GPU; every site is compared (FP32 bar)."""
     from oracle import flb
     from paper_1012_3632_amd import Simulation
@@ -166,10 +166,10 @@ def test_full_size_step_parity_d3q19_128():
     sim.autotune(repeats=2)
     sim.step(40, stats_stride=1)
     S40 = sim.populations()
-    sim.step(1, stats_stride=1)
+    sim.step(2, stats_stride=1)   # one in-place pair if the autotuner chose pairs
     got = sim.populations().numpy()
     po = oracle_params(**kw)
-    ref = flb.step(S40, 40, po).numpy()
+    ref = flb.step(flb.step(S40, 40, po), 41, po).numpy()
     assert rel_err(got, ref) < 1e-5
     del S40
 
@@ -233,8 +233,65 @@ def test_launch_configs_bitwise_identical_and_autotune_keeps_state():
     m_after = s.moments()
     for x, y in zip(m_before, m_after):
         np.testing.assert_array_equal(x, y)
-    assert s.launch_configs() == (n, best)
-    assert all(t > 0 for t in ms) and all(0 <= b < n for b in best)
+    assert s.launch_configs() == (n, (best[0], best[1], best[3]))
+    assert all(t > 0 for t in ms) and 0 <= best[0] < n and 0 <= best[1] < n
+    assert best[2] >= 0 and best[3] in (-1, best[2])
+
+
+@pytest.mark.parametrize("lattice,precision", [("D3Q19", "fp32"), ("D3Q19", "fp64"),
+                                               ("D2Q9", "fp32"), ("D2Q9", "fp64")])
+@pytest.mark.parametrize("shape", [(5, 7, 130), (3, 64, 64), (1, 1, 1), (2, 3, 65)])
+def test_in_place_pairs_bit_identical(lattice, precision, shape):
+    """In-place pairs (one buffer) against ordinary steps (two buffers): same
+    populations and statistics bit for bit, for odd and even step counts and
+    statistics strides, over boxes ragged in x and y and boxes of one site."""
+    from paper_1012_3632_amd import Simulation
+    nz, ny, nx = shape
+    if lattice == "D2Q9":
+        nz = 1
+    kw = dict(C2, lattice=lattice, precision=precision, nx=nx, ny=ny, nz=nz)
+    drho = W.initial_drho((nz, ny, nx), 5, 0.01)
+    probe = Simulation(gpu_params(**kw))
+    shapes = [probe.launch_shape(c) for c in range(probe.launch_configs()[0])]
+    probe.close()
+    for ip in [c for c, sh in enumerate(shapes) if sh[6]]:
+        # the ordinary kernel of the same tile: same FP64 reduction order of the statistics
+        base = next(c for c, sh in enumerate(shapes) if sh[:6] == shapes[ip][:6] and not sh[6])
+        ref = Simulation(gpu_params(**kw), drho_init=drho)
+        ref.set_launch(base)
+        got = Simulation(gpu_params(**kw), drho_init=drho)
+        got.set_launch(ip)
+        assert got.launch_configs()[1][2] == ip
+        for nsteps, stride in ((1, 1), (4, 1), (5, 2), (6, 3), (3, 0)):
+            ref.step(nsteps, stats_stride=stride)
+            got.step(nsteps, stats_stride=stride)
+            torch.cuda.synchronize()
+            assert torch.equal(ref.state(), got.state()), (ip, nsteps, stride)
+            assert ref.step_index == got.step_index
+        for a, b in zip(ref.moments(), got.moments()):
+            np.testing.assert_array_equal(a, b)
+        ref.close()
+        got.close()
+
+
+def test_in_place_pairs_graph_replay():
+    from paper_1012_3632_amd import Simulation
+    kw = dict(C2, precision="fp32", nx=64, ny=24, nz=16)
+    a = Simulation(gpu_params(**kw))
+    b = Simulation(gpu_params(**kw))
+    ip = next(c for c in range(b.launch_configs()[0]) if b.launch_shape(c)[6])
+    a.set_launch(next(c for c in range(a.launch_configs()[0])
+                      if a.launch_shape(c)[:6] == b.launch_shape(ip)[:6] and not a.launch_shape(c)[6]))
+    b.set_launch(ip)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b.graph_capture(6, stats_stride=2)
+        for r in range(3):
+            a.step(6, stats_stride=2)
+            b.graph_launch()
+            torch.cuda.synchronize()
+            assert torch.equal(a.state(), b.state()), r
+    np.testing.assert_array_equal(a.moments()[1], b.moments()[1])
 
 
 def test_conservation_gpu():
