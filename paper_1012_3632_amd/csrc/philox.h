@@ -44,12 +44,10 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 // Uniforms u = (r + 1) 2^-32 in (0, 1].  FP32 evaluates it as
 // fma(float(r), 2^-32, 2^-32): exact for r < 2^24, so the small-u tail that sets
 // the large Box-Muller radii keeps full 32-bit resolution; larger r round to 24
-// significant bits (r = 2^32 - 1 gives exactly 1).
+// significant bits (r = 2^32 - 1 gives exactly 1).  FP64 works from the exact
+// r + 1 (neg2_log_u32).
 __device__ __forceinline__ float u01f(uint32_t r) {
     return __builtin_fmaf((float)r, 0x1.0p-32f, 0x1.0p-32f);
-}
-__device__ __forceinline__ double u01d(uint32_t r) {
-    return ((double)r + 1.0) * 0x1.0p-32;
 }
 
 // Box-Muller with a 32-bit radius word r and a 16-bit angle h:
@@ -66,12 +64,96 @@ __device__ __forceinline__ void box_muller(uint32_t r, uint32_t h, float& z0, fl
     z0 = rad * __builtin_amdgcn_cosf(v);
     z1 = rad * __builtin_amdgcn_sinf(v);
 }
+// sin and cos of 2 pi k / 65536 for an integer k in [1, 65536].  The angle is
+// reduced exactly in integers: quadrant q = k / 16384 and t = k mod 16384,
+// angle = q pi/2 + pi t / 32768; with a = min(t, 16384 - t) the reduced
+// argument y = pi a / 32768 lies in [0, pi/4], where the Taylor series of sin
+// to y^17 and of cos to y^18 are evaluated in Horner form (first omitted
+// terms below 1e-19).  The co-function and quadrant identities then give the
+// result; the only rounding before the series is that of y itself.
+__device__ __forceinline__ void sincos_turn16(uint32_t k, double& s, double& c) {
+    const uint32_t q = (k >> 14) & 3u;
+    const uint32_t t = k & 16383u;
+    const bool upper = t > 8192u;
+    const uint32_t a = upper ? 16384u - t : t;
+    constexpr double PI_32768 = 3.141592653589793 / 32768.0;
+    const double y = (double)a * PI_32768;
+    const double y2 = y * y;
+    // 1/n! for the series terms
+    constexpr double F3 = 1.0 / 6.0, F5 = F3 / 20.0, F7 = F5 / 42.0, F9 = F7 / 72.0,
+                     F11 = F9 / 110.0, F13 = F11 / 156.0, F15 = F13 / 210.0, F17 = F15 / 272.0;
+    constexpr double F2 = 0.5, F4 = F2 / 12.0, F6 = F4 / 30.0, F8 = F6 / 56.0, F10 = F8 / 90.0,
+                     F12 = F10 / 132.0, F14 = F12 / 182.0, F16 = F14 / 240.0, F18 = F16 / 306.0;
+    double ps = -F17;
+    ps = fma(ps, y2, F15);
+    ps = fma(ps, y2, -F13);
+    ps = fma(ps, y2, F11);
+    ps = fma(ps, y2, -F9);
+    ps = fma(ps, y2, F7);
+    ps = fma(ps, y2, -F5);
+    ps = fma(ps, y2, F3);
+    const double sy = fma(-ps * y2, y, y);   // y - y^3/3! + ...
+    double pc = F18;
+    pc = fma(pc, y2, -F16);
+    pc = fma(pc, y2, F14);
+    pc = fma(pc, y2, -F12);
+    pc = fma(pc, y2, F10);
+    pc = fma(pc, y2, -F8);
+    pc = fma(pc, y2, F6);
+    pc = fma(pc, y2, -F4);
+    pc = fma(pc, y2, F2);
+    const double cy = fma(-pc, y2, 1.0);     // 1 - y^2/2! + ...
+    // sin and cos of the angle within the quadrant
+    const double sp = upper ? cy : sy;
+    const double cp = upper ? sy : cy;
+    switch (q) {
+        case 0: s = sp; c = cp; break;
+        case 1: s = cp; c = -sp; break;
+        case 2: s = -sp; c = -cp; break;
+        default: s = -cp; c = sp; break;
+    }
+}
+
+// -2 ln u for u = (r + 1) 2^-32.  With d = r + 1 = 2^e m (exact; the mantissa
+// is moved to m in [sqrt(1/2), sqrt(2))), ln u = (e - 32) ln 2 + ln m and
+// ln m = 2 artanh(s), s = (m - 1) / (m + 1), |s| < 0.172, from the series
+// 2 (s + s^3/3 + ... + s^21/21) (first omitted term below 1e-18 relative).
+// ln 2 is split into a 24-bit head, whose products with e - 32 are exact,
+// and the remainder.
+__device__ __forceinline__ double neg2_log_u32(uint32_t r) {
+    const double d = (double)r + 1.0;
+    const long long bits = __double_as_longlong(d);
+    int e = (int)(bits >> 52) - 1023;
+    double m = __longlong_as_double((bits & 0x000fffffffffffffLL) | 0x3ff0000000000000LL);
+    if (m > 1.4142135623730951) {
+        m *= 0.5;
+        e += 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 21.0;
+    p = fma(p, s2, 1.0 / 19.0);
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    const double two_s = 2.0 * s;
+    const double ln_m = fma(two_s * s2, p, two_s);
+    constexpr double LN2 = 0.6931471805599453;
+    constexpr double LN2_HEAD = (double)(float)LN2;
+    constexpr double LN2_TAIL = LN2 - LN2_HEAD;
+    const double k = (double)(e - 32);
+    return -2.0 * fma(k, LN2_HEAD, fma(k, LN2_TAIL, ln_m));
+}
+
 __device__ __forceinline__ void box_muller(uint32_t r, uint32_t h, double& z0, double& z1) {
-    const double u = u01d(r);
-    const double v = (double)(h + 1u) * 0x1.0p-16;
-    const double rad = sqrt(-2.0 * log(u));
+    const double rad = sqrt(neg2_log_u32(r));
     double s, c;
-    sincos(2.0 * 3.141592653589793 * v, &s, &c);
+    sincos_turn16(h + 1u, s, c);   // theta = 2 pi (h + 1) 2^-16
     z0 = rad * c;
     z1 = rad * s;
 }
