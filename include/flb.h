@@ -151,6 +151,17 @@ flb_status flb_fields(flb_handle* h, void* out, void* stream);
 flb_status flb_noise_words(const flb_params* p, uint64_t step, uint32_t block, uint32_t tag,
                            uint64_t site0, uint64_t nsites, uint32_t* out_dev, void* stream);
 
+/* Verification: the standard normals the collision of step `step` draws at
+ * sites site0 .. site0 + nsites - 1 (Sec. V eq. noise-lbe: the xi_a are these
+ * normals times the per-mode amplitudes), written to out_dev[2 P s + k]
+ * (device, reals of p->precision), P = 8 Box-Muller pairs for D3Q19 and 3 for
+ * D2Q9: z[2j], z[2j+1] = R (cos theta, sin theta) of pair j, with R from word
+ * j and theta from half of word P + j/2 of the site's Philox blocks (the
+ * layout flb_noise_words exposes); the collision uses the first 15 (D3Q19) or
+ * 6 (D2Q9).  Uses p->seed and p->replica.  Asynchronous. */
+flb_status flb_noise_normals(const flb_params* p, uint64_t step, uint64_t site0, uint64_t nsites,
+                             void* out_dev, void* stream);
+
 /* Verification: the library's constant tables for a lattice, written to host
  * arrays: c[3 Q] (int, z = 0 in 2-D), w[Q], T[Q Q] (row-major, rows = modes),
  * N[Q], cls[Q] (0 rho, 1 momentum, 2 bulk, 3 shear, 4 ghost); *q receives Q.

@@ -81,6 +81,7 @@ PROTOS = {
     "flb_set_launch": [vp, C.c_int32],
     "flb_launch_configs": [vp, P(C.c_int32), P(C.c_int32)],
     "flb_launch_shape": [vp, C.c_int32, P(C.c_int32)],
+    "flb_noise_normals": [vp, C.c_uint64, C.c_uint64, C.c_uint64, vp, vp],
     "flb_batch_autotune": [vp, C.c_int32, P(C.c_int32), P(C.c_double), vp],
 }
 

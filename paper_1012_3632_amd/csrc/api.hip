@@ -410,6 +410,15 @@ flb_status flb_noise_words(const flb_params* p, uint64_t step, uint32_t block, u
     return FLB_OK;
 }
 
+flb_status flb_noise_normals(const flb_params* p, uint64_t step, uint64_t site0, uint64_t nsites,
+                             void* out_dev, void* stream) {
+    flb_status r = validate(p);
+    if (r != FLB_OK) return r;
+    if (!out_dev && nsites) return fail(FLB_ERR_INVALID_ARG, "out_dev is NULL");
+    HIP_TRY(launch_noise_normals(spec_of(*p), step, site0, nsites, out_dev, (hipStream_t)stream));
+    return FLB_OK;
+}
+
 flb_status flb_graph_capture(flb_handle* h, int64_t nsteps, int32_t stats_stride, void* stream) {
     if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
     if (nsteps <= 0 || stats_stride < 0)

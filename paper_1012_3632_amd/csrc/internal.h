@@ -69,6 +69,9 @@ hipError_t launch_stats_finalize(const double* partial, uint32_t nslots, int nva
 hipError_t launch_noise_words(const StepSpec& s, unsigned long long step, uint32_t block,
                               uint32_t tag, unsigned long long site0, unsigned long long nsites,
                               uint32_t* out, hipStream_t st);
+hipError_t launch_noise_normals(const StepSpec& s, unsigned long long step,
+                                unsigned long long site0, unsigned long long nsites, void* out,
+                                hipStream_t st);
 hipError_t launch_add_u64(unsigned long long* ctr, unsigned long long inc, hipStream_t st);
 hipError_t launch_set_u64(unsigned long long* ctr, unsigned long long v, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);

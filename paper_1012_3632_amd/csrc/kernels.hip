@@ -372,6 +372,19 @@ __global__ void k_noise_words(unsigned long long site0, unsigned long long nsite
     out[4 * s + 3] = r.w;
 }
 
+// The 2 NPAIR Box-Muller normals of sites site0 .. site0 + nsites - 1 (tag 0).
+template <int NPAIR, typename Real>
+__global__ void k_noise_normals(unsigned long long site0, unsigned long long nsites, uint32_t step,
+                                uint32_t replica, uint32_t k0, uint32_t k1,
+                                Real* __restrict__ out) {
+    const unsigned long long s = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsites) return;
+    Real z[2 * NPAIR];
+    site_normals<NPAIR, Real>((uint32_t)(site0 + s), step, 0u, replica, k0, k1, z);
+#pragma unroll
+    for (int k = 0; k < 2 * NPAIR; ++k) out[(size_t)(2 * NPAIR) * s + k] = z[k];
+}
+
 __global__ void k_add_u64(unsigned long long* ctr, unsigned long long inc) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *ctr += inc;
 }
@@ -628,6 +641,23 @@ hipError_t launch_noise_words(const StepSpec& s, unsigned long long step, uint32
     const dim3 grid((unsigned)((nsites + 255) / 256)), blk(256);
     hipLaunchKernelGGL(k_noise_words, grid, blk, 0, st, site0, nsites, (uint32_t)step,
                        block | (tag << 16), s.replica, s.key0, s.key1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise_normals(const StepSpec& s, unsigned long long step,
+                                unsigned long long site0, unsigned long long nsites, void* out,
+                                hipStream_t st) {
+    if (nsites == 0) return hipSuccess;
+    const dim3 grid((unsigned)((nsites + 255) / 256)), blk(256);
+    const uint32_t t = (uint32_t)step;
+    if (s.lat == 0 && s.prec == 0)
+        hipLaunchKernelGGL((k_noise_normals<Lattice<0>::NPAIR, float>), grid, blk, 0, st, site0, nsites, t, s.replica, s.key0, s.key1, (float*)out);
+    else if (s.lat == 0)
+        hipLaunchKernelGGL((k_noise_normals<Lattice<0>::NPAIR, double>), grid, blk, 0, st, site0, nsites, t, s.replica, s.key0, s.key1, (double*)out);
+    else if (s.prec == 0)
+        hipLaunchKernelGGL((k_noise_normals<Lattice<1>::NPAIR, float>), grid, blk, 0, st, site0, nsites, t, s.replica, s.key0, s.key1, (float*)out);
+    else
+        hipLaunchKernelGGL((k_noise_normals<Lattice<1>::NPAIR, double>), grid, blk, 0, st, site0, nsites, t, s.replica, s.key0, s.key1, (double*)out);
     return hipGetLastError();
 }
 

@@ -125,6 +125,17 @@ def noise_words(params, step, block, site0, nsites, tag=0, device="cuda", stream
     return out.cpu().to(torch.int64) & 0xFFFFFFFF
 
 
+def noise_normals(params, step, site0, nsites, device="cuda", stream=None):
+    """The Box-Muller normals the collision of ``step`` draws at a range of
+    sites: CPU tensor of shape (nsites, 2P) in the parameters' precision,
+    P = 8 pairs (D3Q19) or 3 (D2Q9)."""
+    npair = 8 if params.q == 19 else 3
+    out = torch.empty((nsites, 2 * npair), dtype=params.dtype, device=device)
+    call("flb_noise_normals", C.byref(params.to_c()), int(step), int(site0), int(nsites),
+         _ptr(out), _stream(stream))
+    return out.cpu()
+
+
 class Simulation:
     """One lattice advanced by the HIP library; buffers are torch tensors."""
 

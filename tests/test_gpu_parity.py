@@ -33,6 +33,36 @@ def test_noise_words_bit_exact():
     np.testing.assert_array_equal(got, ref.T.astype(np.int64))
 
 
+@pytest.mark.parametrize("lattice", ["D3Q19", "D2Q9"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_noise_normals_match_oracle(lattice, precision):
+    """Box-Muller normals of 2^20 sites (every 16-bit angle many times over)
+    against the oracle's numpy log/cos/sin, pair by pair with R the pair's
+    radius.  FP64 (series sin/cos and log on the device): within 1e-15
+    max(1, R), a few ulp.  FP32: u = (r + 1) 2^-32 is rounded to 24 bits for
+    r >= 2^24 (an error up to 2^-25 in u near 1, i.e. up to ~3e-8 / R in R)
+    and v_log/v_sqrt/v_sin/v_cos are hardware approximations: within
+    4e-6 max(1, R) + 1e-7 / R."""
+    from oracle import philox
+    from paper_1012_3632_amd import noise_normals
+    p = gpu_params(**dict(C2, lattice=lattice), nx=8, ny=8, nz=8 if lattice == "D3Q19" else 1,
+                   precision=precision).with_(replica=3)
+    n = 1 << 20
+    got = noise_normals(p, 1234, 0, n).numpy().astype(np.float64).T
+    ref = philox.normals(n, 1234, got.shape[0], 7, replica=3)
+    err = np.abs(got - ref)
+    R = np.repeat(np.hypot(ref[0::2], ref[1::2]), 2, axis=0)[:ref.shape[0]]
+    if precision == "fp64":
+        bar = 1e-15 * np.maximum(1.0, R)
+    else:
+        bar = 4e-6 * np.maximum(1.0, R) + 1e-7 / R
+    assert (err <= bar).all(), (err.max(), (err / bar).max())
+    # the first pair of site 5 at another step and site offset
+    got2 = noise_normals(p, 99, 5, 3).numpy().astype(np.float64)
+    ref2 = philox.normals(8, 99, got.shape[0], 7, replica=3)[:, 5:8].T
+    np.testing.assert_allclose(got2, ref2, rtol=0, atol=1e-14 if precision == "fp64" else 1e-4)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_parity_d2q9_ideal_full_run(precision):
     kw = dict(W.params_of("d2q9_32_fp64"), precision=precision)
