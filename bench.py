@@ -70,6 +70,23 @@ def time_steps(sim, steps, stride, stream):
     return e0.elapsed_time(e1) / steps   # ms per step
 
 
+def fdt_check(sim):
+    """Measured variance of each non-conserved mode over the sampled sites and
+    steps against the fluctuation-dissipation value rho0 kT N_a / cs2."""
+    import numpy as np
+
+    from paper_1012_3632_amd import lattice_tables
+    p = sim.params
+    s, s2, n = sim.moments()
+    cnt = float(n) * p.nx * p.ny * p.nz
+    var = s2 / cnt - (s / cnt) ** 2
+    N = lattice_tables("D3Q19" if p.q == 19 else "D2Q9")["N"]
+    d = 3 if p.q == 19 else 2
+    ratio = var[d + 1:] / (p.rho0 * p.kT * N[d + 1:] * 3.0)
+    return {"samples": int(n), "max_rel_dev": round(float(np.abs(ratio - 1).max()), 5),
+            "mean_ratio": round(float(ratio.mean()), 5)}
+
+
 def profile_key(shape):
     """Name(s) of a stats-on D3Q19 FP32 step launch in the committed counter
     table (an in-place shape has one entry per phase of a pair)."""
@@ -96,10 +113,12 @@ def bench_main(args):
     (plain_cfg, best_cfg, _, pair_cfg), _ = tuned
     run_cfg = pair_cfg if pair_cfg >= 0 else best_cfg
     sim.step(args.warmup, stats_stride=1)
+    sim.reset_stats()   # the statistics of the timed steps alone (after the burn-in)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ms = time_steps(sim, args.steps, 1, stream)
     wall = time.perf_counter() - t0
+    fdt = fdt_check(sim)
     mlups = V / (ms * 1e-3) / 1e6
     bytes_site = 2 * 19 * 4
     achieved = bytes_site * V / (ms * 1e-3) / 1e9
@@ -132,6 +151,7 @@ def bench_main(args):
                      # resident there and the rate can exceed a two-buffer HBM stream
                      "working_set_bytes": (1 if pair_cfg >= 0 else 2) * 19 * 4 * V},
         "wall_timed_s": round(wall, 3),
+        "fdt": fdt,
         "autotune": {"shapes": list(tuned[0]), "ms_per_step": [round(x, 5) for x in tuned[1]]},
     }
     # the same step without statistics
@@ -201,6 +221,16 @@ def extras(args, stream):
                                "hbm_frac_algorithmic_236B": round(236 * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                "launch_config": cfg_stats, "launch_shape": list(s.launch_shape(cfg_stats)),
                                "statistics": "every step"}
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    # the paper's own force (eta = 1: the ideal-gas pressure replaced), same cost
+    s = Simulation(p.with_(eta=1), drho_init=W.initial_drho(p.shape, 7, W.WORKLOADS["d3q19_256_landau"]["init_noise"]))
+    (_, cfg_stats, _, _), _ = s.autotune(repeats=3)
+    s.step(5, stats_stride=1)
+    ms = time_steps(s, n, 1, stream)
+    res["d3q19_256_landau_eta1"] = {"ms_per_step": round(ms, 4), "MLUPS": round(V / (ms * 1e-3) / 1e6, 1),
+                                    "launch_config": cfg_stats, "statistics": "every step"}
     s.close()
     del s
     torch.cuda.empty_cache()
