@@ -91,9 +91,10 @@ def pair_normals(r, h):
     return R * np.cos(theta), R * np.sin(theta)
 
 
-def normals(nsites, step, count, seed, tag=0, replica=0):
-    """``count`` standard normals per site for sites 0..nsites-1: shape (count, nsites)."""
-    sites = np.arange(nsites, dtype=np.uint64)
+def normals(nsites, step, count, seed, tag=0, replica=0, sites=None):
+    """``count`` standard normals per site for sites 0..nsites-1 (or for the
+    given linear site indices ``sites``): shape (count, number of sites)."""
+    sites = np.arange(nsites, dtype=np.uint64) if sites is None else np.asarray(sites, np.uint64)
     npair = (count + 1) // 2
     nword = npair + (npair + 1) // 2
     nblk = (nword + 3) // 4

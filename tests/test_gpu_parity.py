@@ -370,3 +370,83 @@ def test_invalid_arguments_rejected():
         kw.update(b)
         with pytest.raises(FLBError):
             Simulation(gpu_params(**kw))
+
+
+def _window_ids(n, start, size):
+    return (start + np.arange(size)) % n
+
+
+def test_full_size_landau_256_windows():
+    """d3q19_256_landau at full size (256^3, FP32) in the launch shape the
+    autotuner picks (the one the benchmark times).  A site's update depends on
+    the state within three sites (pull, density, chemical potential, force),
+    so 14^3 windows of the GPU state S_n (periodic in the big box, some across
+    its edges) are advanced by the oracle with the noise of their global site
+    indices, and the inner 8^3 sites are compared with the GPU's S_{n+1}."""
+    from oracle import flb, philox
+    from paper_1012_3632_amd import Simulation, lattice_tables
+    wl = W.WORKLOADS["d3q19_256_landau"]
+    kw = dict(W.params_of("d3q19_256_landau"), precision="fp32")
+    n = kw["nx"]
+    sim = Simulation(gpu_params(**kw), drho_init=W.initial_drho((n, n, n), 7, wl["init_noise"]))
+    sim.autotune(repeats=2)
+    sim.step(30, stats_stride=1)
+    w = torch.as_tensor(lattice_tables("D3Q19")["w"]).view(-1, 1, 1, 1)
+    rng = np.random.default_rng(11)
+    starts = [(0, 0, 0), (n - 7, n - 7, n - 7), (120, 3, 250)] + \
+             [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(3)]
+    Wd, M = 14, 3
+    wins = []
+    for (z0, y0, x0) in starts:
+        iz, iy, ix = (torch.as_tensor(_window_ids(n, s0, Wd), device="cuda") for s0 in (z0, y0, x0))
+        wins.append((iz, iy, ix))
+    before = [sim.state()[:, iz][:, :, iy][:, :, :, ix].to("cpu", torch.float64) + w * kw["rho0"]
+              for iz, iy, ix in wins]
+    step_n = sim.step_index
+    sim.step(1, stats_stride=1)
+    after = [sim.state()[:, iz][:, :, iy][:, :, :, ix].to("cpu", torch.float64) + w * kw["rho0"]
+             for iz, iy, ix in wins]
+    pw = oracle_params(**dict(kw, nx=Wd, ny=Wd, nz=Wd))
+    lat = flb.lattice_of(pw)
+    K = len(lat.noncons())
+    worst = 0.0
+    for (iz, iy, ix), S0, S1 in zip(wins, before, after):
+        gz, gy, gx = (t.cpu().numpy().astype(np.int64) for t in (iz, iy, ix))
+        sites = ((gz[:, None, None] * n + gy[None, :, None]) * n + gx[None, None, :]).reshape(-1)
+        z = torch.as_tensor(philox.normals(None, step_n, K, kw["seed"], sites=sites)).reshape(K, Wd, Wd, Wd)
+        f = flb.pull(S0, lat)
+        F = flb.landau_force(flb.density(f), pw, lat)
+        ref = flb.collide(f, F, step_n, pw, lat, z=z)
+        inner = (slice(None), slice(M, Wd - M), slice(M, Wd - M), slice(M, Wd - M))
+        worst = max(worst, rel_err(S1[inner].numpy(), ref[inner].numpy()))
+    assert worst < 1e-5, worst
+    sim.close()
+
+
+def test_full_size_batch64_replicas():
+    """d3q19_batch64 at full size (64 replicas, 21.6 M sites) with the grid the
+    autotuner picks, stepped through a captured graph as in the benchmark;
+    the smallest, a middle and the largest replica are compared with the
+    oracle run from the same initial state."""
+    from oracle import flb
+    from paper_1012_3632_amd import Batch
+    wl = W.WORKLOADS["d3q19_batch64"]
+    edges = W.batch_edges(wl["replicas"], wl["edges"], wl["size_seed"])
+    kw = dict(lattice="D3Q19", precision="fp32", rho0=1.0, kT=wl["kT"], rate_bulk=wl["rate_bulk"],
+              rate_shear=wl["rate_shear"], rate_ghost=wl["rate_ghost"])
+    b = Batch(gpu_params(**kw), [(e, e, e) for e in edges], seeds=list(range(wl["replicas"])))
+    b.autotune(repeats=2)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b.graph_capture(4, stats_stride=1)
+        b.graph_launch()
+    torch.cuda.synchronize()
+    order = np.argsort(edges, kind="stable")
+    for r in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        e = int(edges[r])
+        po = oracle_params(**dict(kw, nx=e, ny=e, nz=e, seed=r, replica=r))
+        S, _ = flb.run(flb.initial_state(po), po, 4)
+        w = torch.as_tensor(flb.lattice_of(po).w).view(-1, 1, 1, 1)
+        got = b.replica_state(r).to("cpu", torch.float64) + w * 1.0
+        assert rel_err(got.numpy(), S.numpy()) < 1e-5, (r, e)
+    b.close()
