@@ -204,6 +204,26 @@ flb_status flb_adjoint_segment(flb_handle* h, const void* s_k0, void* abar, void
                                uint64_t k0, uint64_t k1, double* grad, void* stream);
 flb_status flb_adjoint_segment_bytes(const flb_handle* h, int64_t nsteps, size_t* bytes);
 
+/* Reverse pass over a whole checkpointed run in one call: steps 0 .. nsteps-1
+ * in nseg segments of seg_len steps (the last may be shorter), ckpts[s]
+ * (host array of device pointers, Q V reals each) holding the state the step
+ * with index s * seg_len starts from.  abar (device, Q V reals) holds
+ * dL/dS_{nsteps} on entry and dL/dS_0 on return; parameter derivatives as in
+ * flb_adjoint_segment, grad (host, nullable) added to at the end.  The
+ * results equal those of flb_adjoint_segment called for the segments from
+ * last to first; the difference is scheduling: the recompute of segment
+ * s - 1 runs on a helper stream of the handle (created on first use, default
+ * priority) while the reverse sweep of segment s runs on `stream`, the two
+ * halves of `work` (device, flb_adjoint_run_bytes(h, seg_len) bytes, 256-byte
+ * aligned) alternating under events.  Work the caller queued on `stream`
+ * before the call is complete before anything of it starts; when it returns
+ * (without grad: asynchronously) everything it queued is ordered before later
+ * work on `stream`. */
+flb_status flb_adjoint_run(flb_handle* h, const void* const* ckpts, int32_t nseg,
+                           int64_t seg_len, int64_t nsteps, void* abar, void* work,
+                           double* grad, void* stream);
+flb_status flb_adjoint_run_bytes(const flb_handle* h, int64_t seg_len, size_t* bytes);
+
 /* Adjoint seed of the loss of the final density: given S_N (device) and
  * rhobar[V] = dL/drho_N (device, handle precision), where
  * rho_N(x) = rho0 + sum_i delta S_{N,i}(x - c_i), writes abar_N = dL/dS_N

@@ -82,6 +82,8 @@ PROTOS = {
     "flb_launch_configs": [vp, P(C.c_int32), P(C.c_int32)],
     "flb_launch_shape": [vp, C.c_int32, P(C.c_int32)],
     "flb_noise_normals": [vp, C.c_uint64, C.c_uint64, C.c_uint64, vp, vp],
+    "flb_adjoint_run": [vp, P(vp), C.c_int32, C.c_int64, C.c_int64, vp, vp, P(C.c_double), vp],
+    "flb_adjoint_run_bytes": [vp, C.c_int64, P(C.c_size_t)],
     "flb_batch_autotune": [vp, C.c_int32, P(C.c_int32), P(C.c_double), vp],
 }
 

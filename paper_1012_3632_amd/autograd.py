@@ -9,7 +9,8 @@ rho_N(x) = rho0 + sum_i delta S_{N,i}(x - c_i), as an FP64 tensor.  The backward
 dL/dS_N from dL/drho_N, then walks the checkpoints (one every
 ``checkpoint_every`` steps) from last to first: it recomputes the states of a
 segment with the forward kernel and applies the adjoint step kernel to each in
-reverse, regenerating the same Philox noise.  It returns dL/d(delta_f0),
+reverse, regenerating the same Philox noise (one library call; the recompute
+of a segment runs beside the reverse sweep of the next on a second stream).  It returns dL/d(delta_f0),
 dL/d(rate_shear) and dL/d(kT); the bulk and ghost rate derivatives are kept in
 ``FLBRun.last_grads``.
 """
@@ -47,14 +48,9 @@ class FLBRun(torch.autograd.Function):
         sim, ck, N = ctx.sim, ctx.ck, ctx.nsteps
         abar = sim.adjoint_seed(grad_rho.to(sim.params.dtype).contiguous())
         g = np.zeros(4)
-        work = None
-        nseg = len(ctx.ckpts)
-        for seg in range(nseg - 1, -1, -1):
-            k0 = seg * ck
-            k1 = min(k0 + ck, N)
-            # one library call per segment: recompute on the GPU, then the reverse sweep
-            work = sim.adjoint_segment(ctx.ckpts[seg], abar, k0, k1, work=work,
-                                       grad=g if seg == 0 else None)
+        # one library call for all segments: the recompute of each earlier
+        # segment overlaps the reverse sweep of the later one
+        sim.adjoint_run(ctx.ckpts, abar, ck, N, grad=g)
         FLBRun.last_grads = dict(rate_shear=g[0], kT=g[1], rate_bulk=g[2], rate_ghost=g[3])
         dev = grad_rho.device
         return (abar.to(ctx.dtype), torch.tensor(g[0], dtype=torch.float64, device=dev),

@@ -154,6 +154,7 @@ struct flb_handle {
     hipGraph_t graph;
     hipGraphExec_t gexec;
     int64_t graph_steps, graph_samples;
+    hipStream_t aux;        // helper stream of flb_adjoint_run (created on first use)
     // scratch regions
     unsigned long long* step_dev;
     void* drho;             // V reals (force model)
@@ -637,39 +638,51 @@ flb_status flb_adjoint_segment_bytes(const flb_handle* h, int64_t nsteps, size_t
     return FLB_OK;
 }
 
-flb_status flb_adjoint_segment(flb_handle* h, const void* s_k0, void* abar, void* work,
-                               uint64_t k0, uint64_t k1, double* grad, void* stream) {
-    if (!h || !s_k0 || !abar || !work) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
-    if (k1 <= k0) return fail(FLB_ERR_INVALID_ARG, "empty segment [%llu, %llu)",
-                              (unsigned long long)k0, (unsigned long long)k1);
-    if (!aligned(work)) return fail(FLB_ERR_INVALID_ARG, "work must be 256-byte aligned");
-    hipStream_t st = (hipStream_t)stream;
-    const size_t k = (size_t)(k1 - k0);
-    const size_t plane = align_up((size_t)h->q * h->V * h->real_bytes);
-    const size_t dens = align_up(h->V * h->real_bytes);
-    char* w = (char*)work;
-    auto state = [&](size_t j) -> const void* {
-        return j == 0 ? s_k0 : (const void*)(w + (j - 1) * plane);
-    };
-    char* spare = w + (k - 1) * plane;
-    char* dbase = w + k * plane;
-    auto density = [&](size_t j) -> void* { return h->spec.force ? dbase + j * dens : nullptr; };
-    // recompute S_{k0+1} .. S_{k1-1}, keeping each state's density after streaming
-    if (h->spec.force) HIP_TRY(launch_density(h->spec, state(0), density(0), st));
-    for (size_t j = 1; j < k; ++j) {
-        HIP_TRY(launch_step(h->spec, h->cfg, state(j - 1), (void*)state(j), density(j - 1), nullptr,
-                            (unsigned long long)(k0 + j - 1), nullptr, st));
-        if (h->spec.force) HIP_TRY(launch_density(h->spec, state(j), density(j), st));
+}  // extern "C"
+
+namespace {
+
+// Work layout of one segment [k0, k0 + k): states S_{k0+1} .. S_{k0+k-1},
+// one spare adjoint buffer, then k densities (force model).
+struct SegWork {
+    flb_handle* h;
+    const void* s_k0;
+    char* w;
+    size_t k, plane, dens;
+    SegWork(flb_handle* h_, const void* s0, void* work, size_t k_)
+        : h(h_), s_k0(s0), w((char*)work), k(k_),
+          plane(align_up((size_t)h_->q * h_->V * h_->real_bytes)),
+          dens(align_up(h_->V * h_->real_bytes)) {}
+    const void* state(size_t j) const { return j == 0 ? s_k0 : (const void*)(w + (j - 1) * plane); }
+    void* spare() const { return w + (k - 1) * plane; }
+    void* density(size_t j) const { return h->spec.force ? w + k * plane + j * dens : nullptr; }
+};
+
+// Recompute S_{k0+1} .. S_{k0+k-1} (and every state's density) with the forward kernels.
+flb_status seg_recompute(const SegWork& sw, uint64_t k0, hipStream_t st) {
+    flb_handle* h = sw.h;
+    if (h->spec.force) HIP_TRY(launch_density(h->spec, sw.state(0), sw.density(0), st));
+    for (size_t j = 1; j < sw.k; ++j) {
+        HIP_TRY(launch_step(h->spec, h->cfg, sw.state(j - 1), (void*)sw.state(j),
+                            sw.density(j - 1), nullptr, (unsigned long long)(k0 + j - 1), nullptr,
+                            st));
+        if (h->spec.force) HIP_TRY(launch_density(h->spec, sw.state(j), sw.density(j), st));
     }
-    // reverse sweep: abar and spare alternate
-    // abar and spare alternate; each step's density adjoint is spread into
-    // the populations by the next (earlier) step, the last one's at the end
+    return FLB_OK;
+}
+
+// Reverse sweep n = k0 + k - 1 .. k0: abar holds dL/dS_{k0+k} on entry and
+// dL/dS_{k0} on return.  abar and the spare buffer alternate; each step's
+// density adjoint is spread into the populations by the next (earlier) step,
+// the last one's at the end.
+flb_status seg_reverse(const SegWork& sw, void* abar, uint64_t k0, hipStream_t st) {
+    flb_handle* h = sw.h;
     void* cur = abar;
-    void* nxt = spare;
+    void* nxt = sw.spare();
     int rb_in = -1;
-    for (size_t j = k; j-- > 0;) {
+    for (size_t j = sw.k; j-- > 0;) {
         const int rb_out = (int)(j & 1);
-        AdjointStepArgs a{state(j), density(j), cur, nxt, h->adj_work, rb_in, rb_out, false,
+        AdjointStepArgs a{sw.state(j), sw.density(j), cur, nxt, h->adj_work, rb_in, rb_out, false,
                           (unsigned long long)(k0 + j), h->gpartial};
         HIP_TRY(launch_adjoint_step(h->spec, a, st));
         rb_in = rb_out;
@@ -679,22 +692,119 @@ flb_status flb_adjoint_segment(flb_handle* h, const void* s_k0, void* abar, void
     if (cur != abar)
         HIP_TRY(hipMemcpyAsync(abar, cur, (size_t)h->q * h->V * h->real_bytes,
                                hipMemcpyDeviceToDevice, st));
-    if (grad) {
-        double* out = h->gpartial + (size_t)h->gslots * 4;
-        HIP_TRY(launch_stats_finalize(h->gpartial, h->gslots, 4, out, st));
-        double host[4];
-        HIP_TRY(hipMemcpyAsync(host, out, sizeof host, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        for (int q = 0; q < 4; ++q) grad[q] += host[q];
-        HIP_TRY(launch_fill_zero(h->gpartial, (size_t)h->gslots * 4 * sizeof(double), st));
-    }
     return FLB_OK;
+}
+
+// Finalize the parameter-derivative accumulators, add them to grad[4], clear.
+flb_status grad_finalize(flb_handle* h, double* grad, hipStream_t st) {
+    double* out = h->gpartial + (size_t)h->gslots * 4;
+    HIP_TRY(launch_stats_finalize(h->gpartial, h->gslots, 4, out, st));
+    double host[4];
+    HIP_TRY(hipMemcpyAsync(host, out, sizeof host, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int q = 0; q < 4; ++q) grad[q] += host[q];
+    HIP_TRY(launch_fill_zero(h->gpartial, (size_t)h->gslots * 4 * sizeof(double), st));
+    return FLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+flb_status flb_adjoint_segment(flb_handle* h, const void* s_k0, void* abar, void* work,
+                               uint64_t k0, uint64_t k1, double* grad, void* stream) {
+    if (!h || !s_k0 || !abar || !work) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    if (k1 <= k0) return fail(FLB_ERR_INVALID_ARG, "empty segment [%llu, %llu)",
+                              (unsigned long long)k0, (unsigned long long)k1);
+    if (!aligned(work)) return fail(FLB_ERR_INVALID_ARG, "work must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    const SegWork sw(h, s_k0, work, (size_t)(k1 - k0));
+    flb_status r = seg_recompute(sw, k0, st);
+    if (r == FLB_OK) r = seg_reverse(sw, abar, k0, st);
+    if (r == FLB_OK && grad) r = grad_finalize(h, grad, st);
+    return r;
+}
+
+flb_status flb_adjoint_run_bytes(const flb_handle* h, int64_t seg_len, size_t* bytes) {
+    size_t one = 0;
+    flb_status r = flb_adjoint_segment_bytes(h, seg_len, &one);
+    if (r != FLB_OK) return r;
+    *bytes = 2 * align_up(one);
+    return FLB_OK;
+}
+
+flb_status flb_adjoint_run(flb_handle* h, const void* const* ckpts, int32_t nseg,
+                           int64_t seg_len, int64_t nsteps, void* abar, void* work,
+                           double* grad, void* stream) {
+    if (!h || !ckpts || !abar || !work) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    if (nseg < 1 || seg_len < 1 || nsteps <= (int64_t)(nseg - 1) * seg_len ||
+        nsteps > (int64_t)nseg * seg_len)
+        return fail(FLB_ERR_INVALID_ARG, "%d segments of %lld steps do not cover %lld steps",
+                    nseg, (long long)seg_len, (long long)nsteps);
+    for (int s = 0; s < nseg; ++s)
+        if (!ckpts[s]) return fail(FLB_ERR_INVALID_ARG, "checkpoint %d is NULL", s);
+    if (!aligned(work)) return fail(FLB_ERR_INVALID_ARG, "work must be 256-byte aligned");
+    size_t one = 0;
+    flb_status r = flb_adjoint_segment_bytes(h, seg_len, &one);
+    if (r != FLB_OK) return r;
+    one = align_up(one);
+    hipStream_t A = (hipStream_t)stream;
+    if (!h->aux) HIP_TRY(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    hipStream_t B = h->aux;
+    hipEvent_t start = nullptr, ready[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreateWithFlags(&start, hipEventDisableTiming);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipEventCreateWithFlags(&ready[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&freed[i], hipEventDisableTiming);
+    }
+    auto seg = [&](int s) {
+        const uint64_t k0 = (uint64_t)s * (uint64_t)seg_len;
+        const uint64_t k1 = std::min<uint64_t>(k0 + (uint64_t)seg_len, (uint64_t)nsteps);
+        return SegWork(h, ckpts[s], (char*)work + (size_t)(s & 1) * one, (size_t)(k1 - k0));
+    };
+    // The recompute of segment s - 1 (helper stream) overlaps the reverse
+    // sweep of segment s (caller's stream); the two halves of `work`
+    // alternate, guarded by events.
+    if (e == hipSuccess) e = hipEventRecord(start, A);
+    if (e == hipSuccess) e = hipStreamWaitEvent(B, start, 0);
+    if (e != hipSuccess) r = fail(FLB_ERR_HIP, "adjoint run: %s", hipGetErrorString(e));
+    const int last = nseg - 1;
+    if (r == FLB_OK) r = seg_recompute(seg(last), (uint64_t)last * seg_len, B);
+    if (r == FLB_OK && hipEventRecord(ready[last & 1], B) != hipSuccess)
+        r = fail(FLB_ERR_HIP, "adjoint run: event record failed");
+    for (int s = last; s >= 0 && r == FLB_OK; --s) {
+        if (s >= 1) {
+            const int hb = (s - 1) & 1;
+            if (s + 1 <= last && hipStreamWaitEvent(B, freed[hb], 0) != hipSuccess)
+                r = fail(FLB_ERR_HIP, "adjoint run: wait failed");
+            if (r == FLB_OK) r = seg_recompute(seg(s - 1), (uint64_t)(s - 1) * seg_len, B);
+            if (r == FLB_OK && hipEventRecord(ready[hb], B) != hipSuccess)
+                r = fail(FLB_ERR_HIP, "adjoint run: event record failed");
+        }
+        if (r == FLB_OK && hipStreamWaitEvent(A, ready[s & 1], 0) != hipSuccess)
+            r = fail(FLB_ERR_HIP, "adjoint run: wait failed");
+        if (r == FLB_OK) r = seg_reverse(seg(s), abar, (uint64_t)s * seg_len, A);
+        if (r == FLB_OK && hipEventRecord(freed[s & 1], A) != hipSuccess)
+            r = fail(FLB_ERR_HIP, "adjoint run: event record failed");
+    }
+    if (r != FLB_OK) (void)hipStreamSynchronize(B);   // nothing of ours left running
+    if (r == FLB_OK && grad) r = grad_finalize(h, grad, A);
+    if (start) (void)hipEventDestroy(start);
+    for (int i = 0; i < 2; ++i) {
+        if (ready[i]) (void)hipEventDestroy(ready[i]);
+        if (freed[i]) (void)hipEventDestroy(freed[i]);
+    }
+    return r;
 }
 
 flb_status flb_destroy(flb_handle* h) {
     if (!h) return FLB_OK;
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->aux) {
+        (void)hipStreamSynchronize(h->aux);
+        (void)hipStreamDestroy(h->aux);
+    }
     delete h;
     return FLB_OK;
 }

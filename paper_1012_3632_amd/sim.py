@@ -301,6 +301,24 @@ class Simulation:
         call("flb_adjoint_segment_bytes", self.handle, int(nsteps), C.byref(n))
         return n.value
 
+    def adjoint_run(self, ckpts, abar, seg_len, nsteps, work=None, grad=None, stream=None):
+        """In place: abar = dL/dS_N -> dL/dS_0 over a run checkpointed every
+        ``seg_len`` steps (``ckpts[s]`` = state at step s * seg_len); the
+        recompute of each earlier segment overlaps the reverse sweep of the
+        later one on a second stream.  Returns the work tensor for reuse."""
+        n = C.c_size_t()
+        call("flb_adjoint_run_bytes", self.handle, int(seg_len), C.byref(n))
+        if work is None or work.numel() < n.value:
+            work = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        cks = [c.contiguous() for c in ckpts]
+        arr = (C.c_void_p * len(cks))(*[c.data_ptr() for c in cks])
+        g = (C.c_double * 4)(*grad) if grad is not None else None
+        call("flb_adjoint_run", self.handle, arr, len(cks), int(seg_len), int(nsteps), _ptr(abar),
+             _ptr(work), g, _stream(stream))
+        if grad is not None:
+            grad[:] = np.array(g[:])
+        return work
+
     def close(self):
         if self._h is not None:
             lib.flb_destroy(self._h)

@@ -171,3 +171,37 @@ def test_d2q9_256_adjoint_full_size_vs_fd():
         lm = grad.loss_only(S0 - h * v, po, nsteps, target)
         fd = (lp - lm) / (2 * h)
         np.testing.assert_allclose(float((gS * v).sum()), fd, rtol=1e-4)
+
+
+@pytest.mark.parametrize("lattice,force,precision,nsteps,ck", [
+    ("D2Q9", True, "fp32", 47, 10), ("D2Q9", True, "fp64", 20, 20), ("D3Q19", False, "fp32", 9, 2),
+    ("D3Q19", True, "fp64", 13, 4), ("D2Q9", False, "fp64", 5, 5)])
+def test_adjoint_run_equals_segment_loop(lattice, force, precision, nsteps, ck):
+    """flb_adjoint_run (recompute of segment s - 1 on a helper stream beside
+    the reverse sweep of segment s) gives dL/dS_0 and the parameter
+    derivatives bit for bit equal to flb_adjoint_segment called per segment
+    from last to first, for ragged last segments and single segments."""
+    from paper_1012_3632_amd import Simulation
+    shape = (1, 37, 70) if lattice == "D2Q9" else (9, 10, 21)
+    kw = dict(C2, lattice=lattice, precision=precision, nz=shape[0], ny=shape[1], nx=shape[2])
+    if force:
+        kw.update(LANDAU, kT=1e-6)
+    sim = Simulation(gpu_params(**kw), drho_init=W.initial_drho(shape, 3, 0.01))
+    ckpts = []
+    for k0 in range(0, nsteps, ck):
+        ckpts.append(sim.state().clone())
+        sim.step(min(ck, nsteps - k0))
+    rhobar = torch.as_tensor(W.initial_drho(shape, 4, 1.0), dtype=sim.params.dtype, device="cuda")
+    seed = sim.adjoint_seed(rhobar)
+    a1, g1 = seed.clone(), np.zeros(4)
+    for s in range(len(ckpts) - 1, -1, -1):
+        k0 = s * ck
+        sim.adjoint_segment(ckpts[s], a1, k0, min(k0 + ck, nsteps), grad=g1 if s == 0 else None)
+    a2, g2 = seed.clone(), np.zeros(4)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sim.adjoint_run(ckpts, a2, ck, nsteps, grad=g2, stream=stream)
+    torch.cuda.synchronize()
+    assert torch.equal(a1, a2)
+    np.testing.assert_array_equal(g1, g2)
+    sim.close()
