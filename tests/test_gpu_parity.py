@@ -285,15 +285,17 @@ def test_in_place_pairs_bit_identical(lattice, precision, shape):
     shapes = [probe.launch_shape(c) for c in range(probe.launch_configs()[0])]
     probe.close()
     for ip in [c for c, sh in enumerate(shapes) if sh[6]]:
-        # the ordinary kernel of the same tile: same FP64 reduction order of the statistics
-        base = next(c for c, sh in enumerate(shapes) if sh[:6] == shapes[ip][:6] and not sh[6])
+        # the reference takes one step per call: every step is then a lone
+        # step, run by the ordinary kernel of the same tile (same FP64
+        # reduction order of the statistics)
         ref = Simulation(gpu_params(**kw), drho_init=drho)
-        ref.set_launch(base)
+        ref.set_launch(ip)
         got = Simulation(gpu_params(**kw), drho_init=drho)
         got.set_launch(ip)
         assert got.launch_configs()[1][2] == ip
         for nsteps, stride in ((1, 1), (4, 1), (5, 2), (6, 3), (3, 0)):
-            ref.step(nsteps, stats_stride=stride)
+            for k in range(nsteps):
+                ref.step(1, stats_stride=1 if stride and (k + 1) % stride == 0 else 0)
             got.step(nsteps, stats_stride=stride)
             torch.cuda.synchronize()
             assert torch.equal(ref.state(), got.state()), (ip, nsteps, stride)
@@ -312,7 +314,7 @@ def test_in_place_pairs_graph_replay():
     ip = next(c for c in range(b.launch_configs()[0]) if b.launch_shape(c)[6])
     a.set_launch(next(c for c in range(a.launch_configs()[0])
                       if a.launch_shape(c)[:6] == b.launch_shape(ip)[:6] and not a.launch_shape(c)[6]))
-    b.set_launch(ip)
+    b.set_launch(ip)   # the first in-place shape (128 x 2) has an ordinary twin
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         b.graph_capture(6, stats_stride=2)
