@@ -108,7 +108,7 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
         // chunk j + 1 orders the reads of chunk j before the writes of j + 2
         if constexpr (STATS) {
             double* lds = lds_stats + (it & 1) * LDS1;
-            rows_to_lds<2 * Q, false>(v, lds);
+            rows_to_lds<2 * Q>(v, lds);
             lds_rows_finish<2 * Q, BT, false>(lds, partial + c, nchunks);
         }
     }

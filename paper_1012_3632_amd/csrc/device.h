@@ -139,26 +139,19 @@ __device__ __forceinline__ void row_sums_to_lane15(Acc (&v)[NV]) {
 }
 
 // Block reductions in two phases, in a fixed order.  Phase 1 (rows_to_lds):
-// 16-lane row sums by DPP, then lane 15 of every row writes (or, with ADD,
-// adds) its NV sums in FP64 to its own LDS row; no barrier, and each row
-// belongs to one lane, so a block may add several site sets into its rows
-// before phase 2.  Phase 2 (lds_rows_finish): a barrier, then thread k < NV
-// sums the rows and adds (ADD) or stores its value at out[k * stride].  lds
-// holds 4 * NW * NV doubles (NW wavefronts).  All lanes must be active in
-// phase 1 (the DPP reads neighbouring lanes).
-// (RS: LDS row stride when a row's values are staged in several calls, each
-// with lds offset by its first value.)
-template <int NV, bool ADD, typename Acc, int RS = NV>
+// 16-lane row sums by DPP, then lane 15 of every row stores its NV sums in
+// FP64 to its own LDS row; no barrier.  Phase 2 (lds_rows_finish): a barrier,
+// then thread k < NV sums the rows and adds (ADD) or stores its value at
+// out[k * stride].  lds holds 4 * NW * NV doubles (NW wavefronts).  All lanes
+// must be active in phase 1 (the DPP reads neighbouring lanes).
+template <int NV, typename Acc>
 __device__ __forceinline__ void rows_to_lds(Acc (&v)[NV], double* lds) {
     const int lane = threadIdx.x & 63;
     const int row = threadIdx.x >> 4;
     row_sums_to_lane15<NV, Acc>(v);
     if ((lane & 15) == 15) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            if constexpr (ADD) lds[row * RS + k] += (double)v[k];
-            else lds[row * RS + k] = (double)v[k];
-        }
+        for (int k = 0; k < NV; ++k) lds[row * NV + k] = (double)v[k];
     }
 }
 template <int NV, int NT, bool ADD>
@@ -174,23 +167,13 @@ __device__ __forceinline__ void lds_rows_finish(const double* lds, double* __res
         else out[(size_t)threadIdx.x * stride] = acc;
     }
 }
-// Zero this lane's LDS row before rows_to_lds<ADD = true> (the same lane adds).
-template <int NV>
-__device__ __forceinline__ void lds_rows_zero(double* lds) {
-    if ((threadIdx.x & 15) == 15) {
-        const int row = threadIdx.x >> 4;
-#pragma unroll
-        for (int k = 0; k < NV; ++k) lds[row * NV + k] = 0.0;
-    }
-}
-
 // Reduce NV values over the block and add them, in FP64, to slot[0..NV):
 // the 16-lane row sums are formed in Acc, the sums over rows, wavefronts and
 // steps in FP64.
 template <int NV, int NT, typename Acc>
 __device__ __forceinline__ void block_accumulate(Acc (&v)[NV], double* __restrict__ slot,
                                                  double* lds) {
-    rows_to_lds<NV, false, Acc>(v, lds);
+    rows_to_lds<NV, Acc>(v, lds);
     lds_rows_finish<NV, NT, true>(lds, slot, 1);
 }
 

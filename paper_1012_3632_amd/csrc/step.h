@@ -47,7 +47,4 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nblocks) {
     return (b % NX) * per + b / NX;
 }
 
-__device__ __forceinline__ int wrapm(int v, int n) { return v < 0 ? v + n : v; }
-__device__ __forceinline__ int wrapp(int v, int n) { return v >= n ? v - n : v; }
-
 }  // namespace flb
