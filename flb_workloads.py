@@ -22,6 +22,17 @@ Workloads (all periodic, rho0 = 1, fluid initially at rest, lattice units):
                         the same run at shear rate 1.5, kT 1e-6, seed 1234,
                         400 steps, checkpoint every 20.
 
+* ``d2q9_128_equilibration``  the equilibration test of Sec. VI: D2Q9 128^2,
+                        homogeneous fluid at rho0 = 1 with the paper's force
+                        (eta = 1), Landau double well with rho_L 1, rho_V 0.5 and
+                        beta set by c_s 0.265 (a, b, rho_c below are that well
+                        written about rho_c: a = -beta (rho_L - rho_V)^2 / 2,
+                        b = beta, rho_c = (rho_L + rho_V) / 2, beta = c_s^2 /
+                        (2 rho0 (rho_L - rho_V)^2) = 0.14045), kappa 0.08,
+                        kT 1e-7, all rates 1.0 (tau = 1), FP32, seed 2010;
+                        400 snapshots every 250 steps after 20000 steps of
+                        burn-in (the paper states neither of the last two).
+
 The paper's own runs use no public dataset; its 2-D demonstrations (128^2
 homogeneous fluid, 1024x400 liquid stripe) are parameter sets, not data.
 """
@@ -47,6 +58,12 @@ WORKLOADS = {
                              rho0=1.0, kT=1e-6, rate_bulk=1.0, rate_shear=1.0,
                              rate_ghost=1.0, target_rate_shear=1.5, seed=1234, steps=400,
                              checkpoint_every=20, init_noise=0.01, **LANDAU),
+    "d2q9_128_equilibration": dict(lattice="D2Q9", precision="fp32", nx=128, ny=128, nz=1,
+                                   rho0=1.0, kT=1e-7, rate_bulk=1.0, rate_shear=1.0,
+                                   rate_ghost=1.0, seed=2010, force_model=1,
+                                   a=-0.01755625, b=0.14045, rho_c=0.75, kappa=0.08, eta=1,
+                                   rho_L=1.0, rho_V=0.5, cs=0.265, snapshots=400,
+                                   interval=250, burn_in=20000),
 }
 
 PARAM_KEYS = ("lattice", "nx", "ny", "nz", "rho0", "kT", "rate_bulk", "rate_shear",

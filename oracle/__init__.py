@@ -21,6 +21,10 @@ fluctuations in the discrete Boltzmann equation"):
   Guo form), the lattice-corrected velocity (Sec. V eq. lbe-moments), the LB
   noise covariance (Sec. V eq. noise-lbe) and the non-ideal force
   F = -rho grad mu (App. A eq. he-force, Sec. VI eq. f0-bulk).
+* ``spectra``  -- the equilibration analysis of Sec. VI: per-mode equal-time
+  spectra, the paper's G(k) (Sec. IV eq. g-mat-forcing with the OZ structure
+  factor of App. A) and the exact stationary spectra of the linearized
+  lattice step.
 * ``grad``     -- reference gradients of a scalar loss of the final density
   w.r.t. the initial populations, the shear rate and kT, by reverse-mode
   automatic differentiation of ``flb`` (plain definition of the derivative).
