@@ -144,7 +144,31 @@ flb_status flb_reset_stats(flb_handle* h, void* stream);
  * (1 + d) V reals).  Asynchronous. */
 flb_status flb_fields(flb_handle* h, void* out, void* stream);
 
-/* Verification: the raw Philox4x32-10 words the step draws for noise block
+/* All Q mode densities of the current state after streaming, FP64 (Sec. III
+ * eq. moments on the shifted populations): out[a V + s] = sum_i T_ai df_i(s),
+ * so row 0 is rho - rho0, and the momentum rows 1..d are rho u = j + F/2
+ * (Sec. V eq. lbe-moments).  out: device pointer to Q V doubles, caller-owned,
+ * 8-byte aligned.  These are the fields whose equal-time correlations Sec. VI
+ * compares with the theory.  Asynchronous. */
+flb_status flb_mode_fields(flb_handle* h, double* out, void* stream);
+
+/* Bytes of the device work buffer flb_mode_spectrum needs: 24 Q V. */
+flb_status flb_spectrum_work_bytes(const flb_handle* h, size_t* bytes);
+
+/* Equal-time mode spectra of the current state (the measurement of the
+ * equilibration ratio of Sec. VI): with m_a(k) = sum_x m_a(x) exp(-i k.x) the
+ * DFT of the flb_mode_fields rows, k = 2 pi (kx/nx, ky/ny, kz/nz),
+ *   spec[a V + k]       += |m_a(k)|^2                      (a < Q)
+ *   spec[(Q + p) V + k] += Re(m_{1+al}(k) conj m_{1+be}(k))  (momentum pairs)
+ * with k = kx + nx (ky + ny kz) and the pairs p = (al, be) = (x, y) for D2Q9,
+ * (x, y), (y, z), (z, x) for D3Q19.  spec: device, (Q + 1) V doubles (D2Q9) or
+ * (Q + 3) V (D3Q19), caller-owned and caller-zeroed; calls add to it, so a
+ * sum over snapshots is one buffer.  work: device, flb_spectrum_work_bytes,
+ * 256-byte aligned, contents not kept.  FLB_ERR_UNSUPPORTED if an extent
+ * exceeds 1024.  Asynchronous. */
+flb_status flb_mode_spectrum(flb_handle* h, void* work, double* spec, void* stream);
+
+/* Verification: the raw Philox4x32-10 words/* Verification: the raw Philox4x32-10 words the step draws for noise block
  * `block` (tag `tag`) at step `step` for sites site0 .. site0 + nsites - 1,
  * written to out_dev[4 * s + k] (device, uint32).  Uses p->seed and
  * p->replica.  Asynchronous. */

@@ -66,6 +66,9 @@ PROTOS = {
     "flb_adjoint_segment": [vp, vp, vp, vp, C.c_uint64, C.c_uint64, P(C.c_double), vp],
     "flb_adjoint_segment_bytes": [vp, C.c_int64, P(C.c_size_t)],
     "flb_density": [vp, vp, vp, vp],
+    "flb_mode_fields": [vp, vp, vp],
+    "flb_spectrum_work_bytes": [vp, P(C.c_size_t)],
+    "flb_mode_spectrum": [vp, vp, vp, vp],
     "flb_destroy": [vp],
     "flb_batch_query_sizes": [P(flb_params), C.c_int32, P(C.c_int32), P(C.c_size_t),
                               P(C.c_size_t), P(C.c_size_t)],

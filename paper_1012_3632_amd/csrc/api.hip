@@ -394,6 +394,37 @@ flb_status flb_fields(flb_handle* h, void* out, void* stream) {
     return FLB_OK;
 }
 
+flb_status flb_mode_fields(flb_handle* h, double* out, void* stream) {
+    if (!h || !out) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    if ((uintptr_t)out % sizeof(double)) return fail(FLB_ERR_INVALID_ARG, "out must be 8-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    if (h->spec.force) HIP_TRY(launch_density(h->spec, h->cur(), h->drho, st));
+    HIP_TRY(launch_mode_fields(h->spec, h->cur(), h->drho, out, st));
+    return FLB_OK;
+}
+
+flb_status flb_spectrum_work_bytes(const flb_handle* h, size_t* bytes) {
+    if (!h || !bytes) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    *bytes = (size_t)h->q * h->V * (2 * sizeof(double) + sizeof(double));
+    return FLB_OK;
+}
+
+flb_status flb_mode_spectrum(flb_handle* h, void* work, double* spec, void* stream) {
+    if (!h || !work || !spec) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    if (!aligned(work)) return fail(FLB_ERR_INVALID_ARG, "work must be 256-byte aligned");
+    if ((uintptr_t)spec % sizeof(double)) return fail(FLB_ERR_INVALID_ARG, "spec must be 8-byte aligned");
+    const StepSpec& s = h->spec;
+    if (s.nx > SPECTRUM_MAX_N || s.ny > SPECTRUM_MAX_N || s.nz > SPECTRUM_MAX_N)
+        return fail(FLB_ERR_UNSUPPORTED, "mode spectra need every extent <= 1024");
+    hipStream_t st = (hipStream_t)stream;
+    // work: q V complex transforms, then the q V real mode fields
+    double* fields = (double*)((char*)work + (size_t)h->q * h->V * 2 * sizeof(double));
+    if (s.force) HIP_TRY(launch_density(s, h->cur(), h->drho, st));
+    HIP_TRY(launch_mode_fields(s, h->cur(), h->drho, fields, st));
+    HIP_TRY(launch_spectrum(h->q, h->d, s.nx, s.ny, s.nz, fields, work, spec, st));
+    return FLB_OK;
+}
+
 flb_status flb_density(flb_handle* h, const void* s, void* out, void* stream) {
     if (!h || !s || !out) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
     HIP_TRY(launch_density(h->spec, s, out, (hipStream_t)stream));

@@ -64,6 +64,10 @@ hipError_t launch_step_in_place(const StepSpec& s, int cfg, int phase, void* f,
                                 double* partial, hipStream_t st);
 hipError_t launch_fields(const StepSpec& s, const void* fin, const void* drho, void* out,
                          hipStream_t st);
+// All Q mode densities of fin after streaming (FP64, out[a V + s]); momentum
+// rows are j + F/2.  drho as for launch_fields.
+hipError_t launch_mode_fields(const StepSpec& s, const void* fin, const void* drho, double* out,
+                              hipStream_t st);
 hipError_t launch_stats_finalize(const double* partial, uint32_t nslots, int nvals, double* out,
                                  hipStream_t st);
 hipError_t launch_noise_words(const StepSpec& s, unsigned long long step, uint32_t block,
@@ -75,6 +79,12 @@ hipError_t launch_noise_normals(const StepSpec& s, unsigned long long step,
 hipError_t launch_add_u64(unsigned long long* ctr, unsigned long long inc, hipStream_t st);
 hipError_t launch_set_u64(unsigned long long* ctr, unsigned long long v, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+
+// Mode spectra (spectrum.hip).  fields: q real fields of nx ny nz sites;
+// work: q V complex; spec: (q + npairs) V doubles, added to.
+constexpr int SPECTRUM_MAX_N = 1024;
+hipError_t launch_spectrum(int q, int d, int nx, int ny, int nz, const double* fields,
+                           void* work, double* spec, hipStream_t st);
 
 // Adjoint launchers (adjoint.hip).
 hipError_t launch_adjoint_seed(const StepSpec& s, const void* rhobar, void* abar, hipStream_t st);

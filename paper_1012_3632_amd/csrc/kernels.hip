@@ -599,6 +599,47 @@ hipError_t launch_step(const StepSpec& s, int cfg, const void* fin, void* fout, 
     return hipGetLastError();
 }
 
+// All Q mode densities of fin after streaming, in FP64: out[a V + s] =
+// sum_i T_ai df_i(s) (shifted populations, so row 0 is rho - rho0), with the
+// momentum rows replaced by rho u = j + F/2.
+template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX* TY* TZ) void k_mode_fields(const Real* __restrict__ fin,
+                                                             const Real* __restrict__ drho,
+                                                             double* __restrict__ out, Geom g,
+                                                             Real rho0, ForceParams<Real> fp) {
+    using L = Lattice<LAT>;
+    using FT = ForceTile<LAT, Real, TX, TY, TZ>;
+    constexpr int Q = L::Q, D = L::D;
+    constexpr int LDS_F = FORCE ? (FT::NR + FT::NM) : 1;
+    __shared__ Real lds_force[LDS_F];
+    int x0, y0, z0;
+    tile_origin<LAT, TX, TY, TZ>(g, x0, y0, z0);
+    const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
+    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+    const bool inside = x < g.nx && y < g.ny && z < g.nz;
+    Real F[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) F[a] = Real(0);
+    if constexpr (FORCE) {
+        FT::stage(drho, g, fp, x0, y0, z0, lds_force, lds_force + FT::NR);
+        if (inside) FT::force(lds_force, lds_force + FT::NR, fp, rho0, tx, ty, tz, F);
+    }
+    if (!inside) return;
+    Real f[Q];
+    pull<LAT, Real>(fin, x, y, z, g, f);
+    const uint32_t s = site_index<LAT>(x, y, z, g);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        double m = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if (L::T[a][i] != 0) m += (double)L::T[a][i] * (double)f[i];
+        }
+        if (a >= 1 && a <= D) m += 0.5 * (double)F[a - 1];
+        out[(size_t)a * g.V + s] = m;
+    }
+}
+
 template <int LAT, typename Real, bool FORCE>
 static void fields_launch(const StepSpec& s, const void* fin, const void* drho, void* out,
                           hipStream_t st) {
@@ -623,6 +664,34 @@ hipError_t launch_fields(const StepSpec& s, const void* fin, const void* drho, v
     } else {
         if (s.force) fields_launch<1, double, true>(s, fin, drho, out, st);
         else fields_launch<1, double, false>(s, fin, drho, out, st);
+    }
+    return hipGetLastError();
+}
+
+template <int LAT, typename Real, bool FORCE>
+static void mode_fields_launch(const StepSpec& s, const void* fin, const void* drho, double* out,
+                               hipStream_t st) {
+    constexpr int TX = (LAT == 1) ? 32 : 64, TY = 4, TZ = (LAT == 1) ? 2 : 1;
+    const Geom g = make_geom(s, TileShape{TX, TY, TZ, 1, 0, 0, 0});
+    hipLaunchKernelGGL((k_mode_fields<LAT, Real, FORCE, TX, TY, TZ>), dim3(g.nblocks),
+                       dim3(TX * TY * TZ), 0, st, (const Real*)fin, (const Real*)drho, out, g,
+                       (Real)s.rho0, force_params<Real>(s));
+}
+
+hipError_t launch_mode_fields(const StepSpec& s, const void* fin, const void* drho, double* out,
+                              hipStream_t st) {
+    if (s.lat == 0 && s.prec == 0) {
+        if (s.force) mode_fields_launch<0, float, true>(s, fin, drho, out, st);
+        else mode_fields_launch<0, float, false>(s, fin, drho, out, st);
+    } else if (s.lat == 0) {
+        if (s.force) mode_fields_launch<0, double, true>(s, fin, drho, out, st);
+        else mode_fields_launch<0, double, false>(s, fin, drho, out, st);
+    } else if (s.prec == 0) {
+        if (s.force) mode_fields_launch<1, float, true>(s, fin, drho, out, st);
+        else mode_fields_launch<1, float, false>(s, fin, drho, out, st);
+    } else {
+        if (s.force) mode_fields_launch<1, double, true>(s, fin, drho, out, st);
+        else mode_fields_launch<1, double, false>(s, fin, drho, out, st);
     }
     return hipGetLastError();
 }

@@ -223,6 +223,37 @@ class Simulation:
         call("flb_fields", self.handle, _ptr(out), _stream(stream))
         return out
 
+    def mode_fields(self, stream=None):
+        """All q mode densities after streaming, float64 (q, nz, ny, nx): row 0
+        is rho - rho0, the momentum rows are rho u = j + F/2."""
+        p = self.params
+        out = torch.empty((p.q,) + p.shape, dtype=torch.float64, device=self.device)
+        call("flb_mode_fields", self.handle, _ptr(out), _stream(stream))
+        return out
+
+    def spectrum_buffer(self):
+        """A zeroed float64 buffer (q + npairs, nz, ny, nx) for accumulate_spectrum:
+        |m_a(k)|^2 for the q modes, then Re(j_al conj j_be) for the momentum
+        pairs (x, y) [2-D] or (x, y), (y, z), (z, x) [3-D]."""
+        p = self.params
+        npairs = 1 if p.d == 2 else 3
+        return torch.zeros((p.q + npairs,) + p.shape, dtype=torch.float64, device=self.device)
+
+    def accumulate_spectrum(self, spec, stream=None):
+        """Add the equal-time mode spectra of the current state to spec (see
+        spectrum_buffer); k = (kx, ky, kz) is at spec[:, kz, ky, kx]."""
+        if getattr(self, "_spec_work", None) is None:
+            n = C.c_size_t()
+            call("flb_spectrum_work_bytes", self.handle, C.byref(n))
+            self._spec_work = torch.empty(max(n.value, 256), dtype=torch.uint8,
+                                          device=self.device)
+        assert spec.dtype == torch.float64 and spec.is_contiguous()
+        p = self.params
+        assert spec.numel() == (p.q + (1 if p.d == 2 else 3)) * p.nx * p.ny * p.nz
+        call("flb_mode_spectrum", self.handle, _ptr(self._spec_work), _ptr(spec),
+             _stream(stream))
+        return spec
+
     def density(self, s, stream=None):
         """rho - rho0 after streaming of state s (q, nz, ny, nx)."""
         p = self.params

@@ -64,3 +64,28 @@ def test_product_path_does_not_use_oracle():
                         assert all(not a.name.startswith(forbidden) for a in node.names), fn
                     elif isinstance(node, ast.ImportFrom) and node.module:
                         assert not node.module.startswith(forbidden), fn
+
+
+@pytest.mark.parametrize("eta", [0, 1])
+def test_equilibration_theory_equals_oracle(eta):
+    """The library's host-side Sec. VI closed forms (G_aa(k), the double well,
+    the longitudinal/transverse momentum split) equal the oracle's,
+    written independently."""
+    import flb_workloads as W
+    from oracle import flb, spectra
+    from paper_1012_3632_amd import equilibration as E
+    wl = W.WORKLOADS["d2q9_128_equilibration"]
+    np.testing.assert_allclose(E.double_well(wl["rho_L"], wl["rho_V"], wl["cs"], wl["rho0"]),
+                               spectra.double_well(wl["rho_L"], wl["rho_V"], wl["cs"],
+                                                   wl["rho0"]), rtol=1e-15)
+    for lat, shape in (("D2Q9", (1, 12, 20)), ("D3Q19", (6, 5, 8))):
+        p = E.paper_params(nx=shape[2], ny=shape[1]).with_(lattice=lat, nz=shape[0], eta=eta)
+        po = flb.Params(lattice=lat, nx=p.nx, ny=p.ny, nz=p.nz, rho0=p.rho0, kT=p.kT,
+                        force_model=1, a=p.a, b=p.b, rho_c=p.rho_c, kappa=p.kappa, eta=eta)
+        np.testing.assert_allclose(E.paper_variance(p), spectra.theory_variance(po), rtol=1e-13)
+        np.testing.assert_allclose(E.paper_variance(p.with_(force_model=0)),
+                                   spectra.theory_variance(po.with_(force_model=0)), rtol=1e-13)
+        rng = np.random.default_rng(4)
+        spec = rng.random((p.q + (1 if p.d == 2 else 3),) + shape)
+        a, b = E.momentum_split(spec, p), spectra.momentum_split(spec, po)
+        np.testing.assert_allclose(a, b, rtol=1e-12, equal_nan=True)
