@@ -264,6 +264,51 @@ def extras(args, stream):
     del b
     torch.cuda.empty_cache()
 
+    # the equilibration test of Sec. VI: D2Q9 128^2, the paper's parameters
+    from paper_1012_3632_amd import equilibration as E
+    wl = W.WORKLOADS["d2q9_128_equilibration"]
+    pe = E.paper_params(nx=wl["nx"], ny=wl["ny"], kT=wl["kT"], kappa=wl["kappa"], cs=wl["cs"],
+                        rho_L=wl["rho_L"], rho_V=wl["rho_V"], seed=wl["seed"])
+    se = Simulation(pe)
+    spec = se.spectrum_buffer()
+    se.graph_capture(wl["interval"], stats_stride=0, stream=stream)
+    se.graph_launch(stream=stream)
+    se.accumulate_spectrum(spec, stream=stream)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    e0.record(stream)
+    se.graph_launch(stream=stream)
+    e1.record(stream)
+    nspec = 20
+    for _ in range(nspec):
+        se.accumulate_spectrum(spec, stream=stream)
+    e2.record(stream)
+    e2.synchronize()
+    ms_step = e0.elapsed_time(e1) / wl["interval"]
+    us_spec = e1.elapsed_time(e2) / nspec * 1e3
+    Ve = pe.nx * pe.ny
+    # direct DFT along x then y: 8 FP64 flops per complex multiply-add
+    dft_flops = 8 * pe.q * Ve * (pe.nx + pe.ny)
+    se.close()
+    del se, spec
+    t0 = time.perf_counter()
+    spec_sum, se = E.run(pe, wl["snapshots"], wl["interval"], wl["burn_in"])
+    run_s = time.perf_counter() - t0
+    se.close()
+    r = E.equilibration_ratio(spec_sum, wl["snapshots"], pe)
+    kc, dens, _ = E.shell_average(r[0], pe, 16)
+    dev = lambda rows: float(max(np.nanmax(np.abs(E.shell_average(r[a], pe, 16)[1][kc < 2.5] - 1))
+                                 for a in rows))
+    res["d2q9_128_equilibration"] = {
+        "ms_per_step": round(ms_step, 5), "MLUPS": round(Ve / (ms_step * 1e-3) / 1e6, 1),
+        "spectrum_us": round(us_spec, 2),
+        "spectrum_fp64_tflops": round(dft_flops / (us_spec * 1e-6) / 1e12, 3),
+        "run_s": round(run_s, 3), "steps": wl["burn_in"] + wl["snapshots"] * wl["interval"],
+        "snapshots": wl["snapshots"],
+        "density_ratio_by_shell": [round(float(x), 3) for x in dens],
+        "momentum_max_dev_k_lt_2.5": round(dev(range(1, 3)), 4),
+        "nonconserved_max_dev_k_lt_2.5": round(dev(range(3, 9)), 4)}
+
     # differentiable run: adjoint / forward time
     from paper_1012_3632_amd.autograd import FLBRun
     wl = W.WORKLOADS["d2q9_256_adjoint"]
