@@ -33,6 +33,18 @@ Workloads (all periodic, rho0 = 1, fluid initially at rest, lattice units):
                         400 snapshots every 250 steps after 20000 steps of
                         burn-in (the paper states neither of the last two).
 
+* ``d2q9_capillary``   the capillary-fluctuation test of Sec. VI: D2Q9
+                        1024 x 400, a liquid stripe (rho_L 1) between y = 100
+                        and y = 300 in vapour (rho_V 0.5), the paper's force
+                        (eta = 1) and double well with beta 0.1 (a, b, rho_c as
+                        above: a = -beta (rho_L - rho_V)^2 / 2, b = beta,
+                        rho_c = 0.75), kappa 0.08, kT 1e-7, all rates 1.0,
+                        FP32 with rho0 0.75, seed 1995; started from the
+                        mean-field profile of width sqrt(8 kappa / beta) /
+                        (rho_L - rho_V) (``stripe_drho``); 10^6 steps, 2000
+                        snapshots (every 475 steps after 50000; the paper gives
+                        neither the burn-in nor the spacing).
+
 The paper's own runs use no public dataset; its 2-D demonstrations (128^2
 homogeneous fluid, 1024x400 liquid stripe) are parameter sets, not data.
 """
@@ -64,6 +76,12 @@ WORKLOADS = {
                                    a=-0.01755625, b=0.14045, rho_c=0.75, kappa=0.08, eta=1,
                                    rho_L=1.0, rho_V=0.5, cs=0.265, snapshots=400,
                                    interval=250, burn_in=20000),
+    "d2q9_capillary": dict(lattice="D2Q9", precision="fp32", nx=1024, ny=400, nz=1,
+                           rho0=0.75, kT=1e-7, rate_bulk=1.0, rate_shear=1.0, rate_ghost=1.0,
+                           seed=1995, force_model=1, a=-0.0125, b=0.1, rho_c=0.75,
+                           kappa=0.08, eta=1, rho_L=1.0, rho_V=0.5, beta=0.1,
+                           stripe=(100.0, 300.0), steps=1000000, burn_in=50000,
+                           snapshots=2000, interval=475),
 }
 
 PARAM_KEYS = ("lattice", "nx", "ny", "nz", "rho0", "kT", "rate_bulk", "rate_shear",
@@ -82,6 +100,20 @@ def initial_drho(shape, seed, amplitude=0.01, offset=0.0):
     float64 array of ``shape`` (nz, ny, nx), from numpy's PCG64 with ``seed``."""
     rng = np.random.default_rng(seed)
     return offset + amplitude * rng.standard_normal(shape)
+
+
+def stripe_drho(shape, y1, y2, rho_L, rho_V, width, rho0):
+    """rho(y) - rho0 of a liquid stripe between y1 and y2 (periodic in y, the
+    profile axis, which is y in 2-D and z in 3-D): the mean-field tanh
+    interfaces of width ``width``, float64 array of ``shape`` (nz, ny, nx)."""
+    nz, ny, nx = shape
+    n = ny if nz == 1 else nz
+    y = np.arange(n, dtype=np.float64)
+    half = 0.5 * (rho_L - rho_V)
+    prof = rho_V + half * (np.tanh(2 * (y - y1) / width) - np.tanh(2 * (y - y2) / width)) - rho0
+    if nz == 1:
+        return np.broadcast_to(prof[None, :, None], shape).copy()
+    return np.broadcast_to(prof[:, None, None], shape).copy()
 
 
 def batch_edges(replicas=64, edges=(32, 48, 64, 80, 96), seed=2024):

@@ -25,6 +25,10 @@ fluctuations in the discrete Boltzmann equation"):
   spectra, the paper's G(k) (Sec. IV eq. g-mat-forcing with the OZ structure
   factor of App. A) and the exact stationary spectra of the linearized
   lattice step.
+* ``capillary`` -- the capillary-fluctuation analysis of Sec. VI: interface
+  heights by fitting the mean-field profile (eqs. height-def, denprof), their
+  spectrum, eq. surf-tension and the capillary structure factor
+  (eq. capill-static), and the effective tension of this lattice scheme.
 * ``grad``     -- reference gradients of a scalar loss of the final density
   w.r.t. the initial populations, the shear rate and kT, by reverse-mode
   automatic differentiation of ``flb`` (plain definition of the derivative).

@@ -1,0 +1,121 @@
+"""Capillary fluctuations of a planar interface (Sec. VI, capillary fluctuations).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+The paper's second test: a liquid stripe in a periodic box; the local height
+h of each interface (eq. height-def: rho(r) = rho_int(y - h(x))) is obtained
+by fitting the mean-field profile of eq. denprof to the density of every
+column, and the equal-time spectrum of h is compared with the capillary
+structure factor kT / (sigma k^2) (eq. capill-static), k^2 read on the lattice
+as 2 - 2 cos k, sigma from eq. surf-tension.
+
+* ``mean_field_profile`` eq. denprof, rising (sign +1) or falling (sign -1).
+* ``interface_heights``  per column, the h minimizing the squared misfit of
+                         the profile over the 2 W + 1 sites nearest y_ref
+                         (a bounded scalar minimization to 1e-12).
+* ``height_spectrum``    |h(k)|^2, h(k) = sum_x h(x) exp(-i k.x) over the
+                         interface plane (1-D for D2Q9, 2-D for D3Q19).
+* ``surface_tension``    eq. surf-tension; ``capillary_theory`` the expected
+                         |h(k)|^2 = A kT / (sigma sum_a (2 - 2 cos k_a)), A the
+                         interface area in sites.
+* ``effective_kappa`` / ``effective_surface_tension``: a reading.  This
+  lattice scheme's density fluctuations follow the Ornstein-Zernike form with
+  kappa_eff(rho0) = kappa + (eta cs2 - rho0 psi''(rho0)) / (4 rho0) in place of
+  kappa (pinned against ``spectra.stationary_spectrum``); the tension of an
+  interface is then taken as the square-gradient integral
+  sigma_eff = int sqrt(2 kappa_eff(rho) W(rho)) drho between the bulk
+  densities, W the double well above its common tangent.
+
+Pins: ``tests/test_oracle_capillary.py``.
+"""
+
+import numpy as np
+from scipy.integrate import quad
+from scipy.optimize import minimize_scalar
+
+from . import lattice as _lattice
+
+CS2 = _lattice.CS2
+
+
+def mean_field_profile(y, h, rho_L, rho_V, width, sign):
+    """(rho_L + rho_V)/2 + sign (rho_L - rho_V)/2 tanh(2 (y - h) / width)."""
+    return 0.5 * (rho_L + rho_V) + sign * 0.5 * (rho_L - rho_V) * np.tanh(2.0 * (y - h) / width)
+
+
+def interface_heights(rho, y_ref, sign, half_window, rho_L, rho_V, width):
+    """Height of one interface in every column.
+
+    rho: array (n, ncol), the density along the profile axis (periodic, n
+    sites) for each column.  The window is y = y0 + j, j = -W..W, with
+    y0 = floor(y_ref + 1/2), read at y mod n; h is returned in the same
+    (unwrapped) coordinate, searched in [y0 - W, y0 + W]."""
+    rho = np.asarray(rho, dtype=np.float64)
+    n, ncol = rho.shape
+    y0 = int(np.floor(y_ref + 0.5))
+    ys = np.arange(y0 - half_window, y0 + half_window + 1)
+    win = rho[ys % n]
+    out = np.empty(ncol)
+    for c in range(ncol):
+        r = win[:, c]
+        res = minimize_scalar(
+            lambda h: np.sum((r - mean_field_profile(ys, h, rho_L, rho_V, width, sign)) ** 2),
+            bounds=(y0 - half_window, y0 + half_window), method="bounded",
+            options={"xatol": 1e-12, "maxiter": 500})
+        out[c] = res.x
+    return out
+
+
+def height_spectrum(h):
+    """|h(k)|^2 of heights over the interface plane (shape (nx,) or (ny, nx))."""
+    return np.abs(np.fft.fftn(np.asarray(h, dtype=np.float64))) ** 2
+
+
+def surface_tension(rho_L, rho_V, kappa, beta):
+    """sigma = (rho_L - rho_V)^3 sqrt(2 kappa beta) / 6 (eq. surf-tension)."""
+    return (rho_L - rho_V) ** 3 / 6.0 * np.sqrt(2.0 * kappa * beta)
+
+
+def interface_width(rho_L, rho_V, kappa, beta):
+    """w = sqrt(8 kappa / beta) / (rho_L - rho_V) (eq. interf-width)."""
+    return np.sqrt(8.0 * kappa / beta) / (rho_L - rho_V)
+
+
+def capillary_theory(k_axes, kT, sigma, area):
+    """Expected |h(k)|^2 of one snapshot: area kT / (sigma sum_a (2 - 2 cos k_a))
+    (eq. capill-static with the lattice Laplacian's symbol for k^2); NaN at 0."""
+    lap = sum(2.0 - 2.0 * np.cos(k) for k in k_axes)
+    with np.errstate(divide="ignore"):
+        return np.where(lap > 0, area * kT / (sigma * np.where(lap > 0, lap, 1.0)), np.nan)
+
+
+def _psi(p, r):
+    d = r - p.rho_c
+    return p.a * d * d + p.b * d ** 4
+
+
+def _psi2(p, r):
+    return 2 * p.a + 12 * p.b * (r - p.rho_c) ** 2
+
+
+def effective_kappa(p, rho):
+    """kappa + (eta cs2 - rho psi''(rho)) / (4 rho): the square-gradient
+    coefficient of this lattice scheme's small-k density fluctuations (a
+    reading, pinned against the linearized step)."""
+    return p.kappa + (p.eta * CS2 - rho * _psi2(p, rho)) / (4.0 * rho)
+
+
+def effective_surface_tension(p, rho_L, rho_V):
+    """int_{rho_V}^{rho_L} sqrt(2 kappa_eff(rho) W(rho)) drho, W = psi minus its
+    chord between the bulk densities (the common tangent of a symmetric well).
+    For the paper's force (eta = 1), where psi is the whole bulk free energy."""
+    if p.eta != 1:
+        raise ValueError("the bulk free energy is psi alone only for eta = 1")
+    pl, pv = _psi(p, rho_L), _psi(p, rho_V)
+
+    def W(r):
+        return _psi(p, r) - (pv + (r - rho_V) * (pl - pv) / (rho_L - rho_V))
+
+    val, _ = quad(lambda r: np.sqrt(max(2.0 * effective_kappa(p, r) * W(r), 0.0)), rho_V, rho_L,
+                  epsabs=1e-14, epsrel=1e-12)
+    return val
