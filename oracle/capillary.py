@@ -11,8 +11,9 @@ as 2 - 2 cos k, sigma from eq. surf-tension.
 
 * ``mean_field_profile`` eq. denprof, rising (sign +1) or falling (sign -1).
 * ``interface_heights``  per column, the h minimizing the squared misfit of
-                         the profile over the 2 W + 1 sites nearest y_ref
-                         (a bounded scalar minimization to 1e-12).
+                         the profile over the 2 W + 1 sites nearest y_ref (a
+                         bounded scalar minimization, then the zero of the
+                         misfit's derivative to full precision).
 * ``height_spectrum``    |h(k)|^2, h(k) = sum_x h(x) exp(-i k.x) over the
                          interface plane (1-D for D2Q9, 2-D for D3Q19).
 * ``surface_tension``    eq. surf-tension; ``capillary_theory`` the expected
@@ -31,7 +32,7 @@ Pins: ``tests/test_oracle_capillary.py``.
 
 import numpy as np
 from scipy.integrate import quad
-from scipy.optimize import minimize_scalar
+from scipy.optimize import brentq, minimize_scalar
 
 from . import lattice as _lattice
 
@@ -56,13 +57,27 @@ def interface_heights(rho, y_ref, sign, half_window, rho_L, rho_V, width):
     ys = np.arange(y0 - half_window, y0 + half_window + 1)
     win = rho[ys % n]
     out = np.empty(ncol)
+    lo, hi = y0 - half_window, y0 + half_window
     for c in range(ncol):
         r = win[:, c]
-        res = minimize_scalar(
-            lambda h: np.sum((r - mean_field_profile(ys, h, rho_L, rho_V, width, sign)) ** 2),
-            bounds=(y0 - half_window, y0 + half_window), method="bounded",
-            options={"xatol": 1e-12, "maxiter": 500})
-        out[c] = res.x
+
+        def misfit(h):
+            return np.sum((r - mean_field_profile(ys, h, rho_L, rho_V, width, sign)) ** 2)
+
+        def slope(h):
+            # -dE/dh / 2 = sum (rho - m) dm/dy at y - h: zero at the minimizer
+            t = np.tanh(2.0 * (ys - h) / width)
+            m = 0.5 * (rho_L + rho_V) + sign * 0.5 * (rho_L - rho_V) * t
+            return np.sum((r - m) * sign * 0.5 * (rho_L - rho_V) * (1 - t * t) * 2.0 / width)
+
+        # the bounded minimizer stops at a relative tolerance of sqrt(eps) |h|;
+        # the stationarity condition is then solved to full precision
+        h = minimize_scalar(misfit, bounds=(lo, hi), method="bounded",
+                            options={"xatol": 1e-12, "maxiter": 500}).x
+        a, b = max(lo, h - 1e-4), min(hi, h + 1e-4)
+        if slope(a) * slope(b) < 0:
+            h = brentq(slope, a, b, xtol=1e-14, rtol=4 * np.finfo(float).eps)
+        out[c] = h
     return out
 
 
