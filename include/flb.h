@@ -168,7 +168,40 @@ flb_status flb_spectrum_work_bytes(const flb_handle* h, size_t* bytes);
  * exceeds 1024.  Asynchronous. */
 flb_status flb_mode_spectrum(flb_handle* h, void* work, double* spec, void* stream);
 
-/* Verification: the raw Philox4x32-10 words/* Verification: the raw Philox4x32-10 words the step draws for noise block
+/* Power spectra of real fields: for f = 0 .. nfields - 1,
+ *   spec[f V + k] += |sum_x fields[f V + x] exp(-i k.x)|^2,
+ * x and k laid out as sites (x fastest), V = nx ny nz, periodic, direct DFT
+ * along each axis.  Used for interface-height spectra (Sec. VI capillary
+ * fluctuations, eq. capill-static).  fields, spec: device doubles, 8-byte
+ * aligned, caller-owned (spec caller-zeroed; calls add to it).  work: device,
+ * 16 nfields V bytes, 256-byte aligned.  FLB_ERR_UNSUPPORTED if an extent
+ * exceeds 1024.  Asynchronous. */
+flb_status flb_field_spectrum(const double* fields, int32_t nfields, int32_t nx, int32_t ny,
+                              int32_t nz, void* work, double* spec, void* stream);
+
+/* One planar interface across the profile axis (y for D2Q9, z for D3Q19). */
+typedef struct {
+    double y_ref;        /* approximate position along the profile axis, in [0, n) */
+    int32_t sign;        /* +1: the density rises from rho_V to rho_L as y grows; -1: falls */
+    int32_t half_window; /* the fit uses the 2 W + 1 sites y0 - W .. y0 + W, y0 =
+                            floor(y_ref + 1/2), read periodically; 1 <= W, 2 W + 1 <= n */
+} flb_interface;
+
+/* Local interface heights of the current state (Sec. VI, capillary
+ * fluctuations; eq. height-def): for every column (x for D2Q9, x + nx y for
+ * D3Q19) and interface j, the h that minimizes
+ *   sum_{y in window} (rho(y) - rho_MF(y - h))^2,
+ *   rho_MF(u) = (rho_L + rho_V)/2 + sign (rho_L - rho_V)/2 tanh(2 u / width)
+ * (the mean-field profile of eq. denprof), rho the density after streaming;
+ * Gauss-Newton from y0, clamped to the window.  h is in the window's unwrapped
+ * coordinate.  heights: device, n_if x ncol doubles (interface-major),
+ * caller-owned.  Needs force_model = 1 (FLB_ERR_UNSUPPORTED otherwise); at most
+ * 8 interfaces.  Uses the handle's density scratch.  Asynchronous. */
+flb_status flb_interface_heights(flb_handle* h, const flb_interface* ifs, int32_t n_if,
+                                 double rho_L, double rho_V, double width, double* heights,
+                                 void* stream);
+
+/* Verification: the raw Philox4x32-10 words the step draws for noise block
  * `block` (tag `tag`) at step `step` for sites site0 .. site0 + nsites - 1,
  * written to out_dev[4 * s + k] (device, uint32).  Uses p->seed and
  * p->replica.  Asynchronous. */

@@ -7,5 +7,5 @@ runs in hand-written HIP kernels behind the C ABI of include/flb.h
 torch is used for device memory and streams only.
 """
 
-from .sim import (Batch, Params, Simulation, lattice_tables, noise_normals,  # noqa: F401
-                  noise_words, query_sizes)
+from .sim import (Batch, Params, Simulation, field_spectrum, lattice_tables,  # noqa: F401
+                  noise_normals, noise_words, query_sizes)

@@ -38,6 +38,10 @@ class flb_params(C.Structure):
     ]
 
 
+class flb_interface(C.Structure):
+    _fields_ = [("y_ref", C.c_double), ("sign", C.c_int32), ("half_window", C.c_int32)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
                       "(python -m paper_1012_3632_amd.build)")
@@ -69,6 +73,9 @@ PROTOS = {
     "flb_mode_fields": [vp, vp, vp],
     "flb_spectrum_work_bytes": [vp, P(C.c_size_t)],
     "flb_mode_spectrum": [vp, vp, vp, vp],
+    "flb_field_spectrum": [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp],
+    "flb_interface_heights": [vp, P(flb_interface), C.c_int32, C.c_double, C.c_double,
+                              C.c_double, vp, vp],
     "flb_destroy": [vp],
     "flb_batch_query_sizes": [P(flb_params), C.c_int32, P(C.c_int32), P(C.c_size_t),
                               P(C.c_size_t), P(C.c_size_t)],

@@ -1,0 +1,124 @@
+"""The capillary-fluctuation test of Sec. VI on the HIP library.
+
+A liquid stripe in vapour (periodic box, the paper's 1024 x 400 with the
+stripe 200 sites thick) is driven by the fluctuating step with the paper's
+force (eta = 1) and Landau double well (eq. f0-bulk).  At every snapshot the
+GPU fits the mean-field profile (eq. denprof) to every column to get the
+local heights h(x) of both interfaces (eq. height-def,
+``Simulation.interface_heights``) and adds |h(k)|^2 to a spectrum buffer
+(``field_spectrum``).  The result is compared with the capillary structure
+factor A kT / (sigma (2 - 2 cos k)) (eq. capill-static on the lattice).
+
+Two tensions are available: eq. surf-tension with the model's kappa, and the
+effective tension of this lattice scheme, the square-gradient integral with
+kappa_eff(rho) = kappa + (eta cs2 - rho psi''(rho)) / (4 rho), the coefficient
+its small-k density fluctuations show.
+"""
+
+import numpy as np
+import torch
+
+from .sim import Params, Simulation, field_spectrum
+
+CS2 = 1.0 / 3.0
+
+
+def well(rho_L, rho_V, beta):
+    """(a, b, rho_c) of beta (r - rho_V)^2 (r - rho_L)^2 written as
+    a (r - rho_c)^2 + b (r - rho_c)^4 + const (eq. f0-bulk)."""
+    return -0.5 * beta * (rho_L - rho_V) ** 2, beta, 0.5 * (rho_L + rho_V)
+
+
+def paper_params(nx=1024, ny=400, rho_L=1.0, rho_V=0.5, beta=0.1, kappa=0.08, kT=1e-7,
+                 rate=1.0, seed=1995, precision="fp32"):
+    """Params of the Sec. VI capillary run (rho0 midway between the phases)."""
+    a, b, rc = well(rho_L, rho_V, beta)
+    return Params(lattice="D2Q9", precision=precision, nx=nx, ny=ny, nz=1,
+                  rho0=0.5 * (rho_L + rho_V), kT=kT, rate_bulk=rate, rate_shear=rate,
+                  rate_ghost=rate, force_model=1, a=a, b=b, rho_c=rc, kappa=kappa, eta=1,
+                  seed=seed)
+
+
+def mean_field_width(rho_L, rho_V, kappa, beta):
+    """w = sqrt(8 kappa / beta) / (rho_L - rho_V) (eq. interf-width)."""
+    return np.sqrt(8.0 * kappa / beta) / (rho_L - rho_V)
+
+
+def stripe(p, y1, y2, rho_L, rho_V, width):
+    """rho - rho0 of a liquid stripe between y1 and y2 along the profile axis
+    (y in 2-D, z in 3-D) with mean-field interfaces (eq. denprof)."""
+    n = p.ny if p.d == 2 else p.nz
+    y = np.arange(n, dtype=np.float64)
+    prof = rho_V + 0.5 * (rho_L - rho_V) * (np.tanh(2 * (y - y1) / width)
+                                            - np.tanh(2 * (y - y2) / width))
+    shape = (1, n, 1) if p.d == 2 else (n, 1, 1)
+    return np.broadcast_to((prof - p.rho0).reshape(shape), p.shape).copy()
+
+
+def surface_tension(rho_L, rho_V, kappa, beta):
+    """(rho_L - rho_V)^3 sqrt(2 kappa beta) / 6 (eq. surf-tension)."""
+    return (rho_L - rho_V) ** 3 * np.sqrt(2.0 * kappa * beta) / 6.0
+
+
+def effective_surface_tension(p, rho_L, rho_V, n=200001):
+    """int sqrt(2 kappa_eff(rho) W(rho)) drho over [rho_V, rho_L] (Simpson),
+    W = psi above its chord between the phases; the paper's force (eta = 1)."""
+    if p.eta != 1:
+        raise ValueError("defined for eta = 1, where psi is the whole bulk free energy")
+    r = np.linspace(rho_V, rho_L, n)
+    psi = lambda x: p.a * (x - p.rho_c) ** 2 + p.b * (x - p.rho_c) ** 4
+    W = psi(r) - (psi(rho_V) + (r - rho_V) * (psi(rho_L) - psi(rho_V)) / (rho_L - rho_V))
+    psi2 = 2 * p.a + 12 * p.b * (r - p.rho_c) ** 2
+    keff = p.kappa + (p.eta * CS2 - r * psi2) / (4.0 * r)
+    f = np.sqrt(np.maximum(2.0 * keff * W, 0.0))
+    h = (rho_L - rho_V) / (n - 1)
+    return h / 3.0 * (f[0] + f[-1] + 4.0 * f[1:-1:2].sum() + 2.0 * f[2:-1:2].sum())
+
+
+def capillary_theory(p, kT, sigma):
+    """Expected |h(k)|^2 of one snapshot over the interface plane:
+    A kT / (sigma sum_a (2 - 2 cos k_a)), A the interface area in sites; NaN
+    at k = 0.  Shape (nx,) in 2-D, (ny, nx) in 3-D."""
+    dims = (p.nx,) if p.d == 2 else (p.ny, p.nx)
+    ks = np.meshgrid(*[2 * np.pi * np.arange(n) / n for n in dims], indexing="ij")
+    lap = sum(2.0 - 2.0 * np.cos(k) for k in ks)
+    area = float(np.prod(dims))
+    with np.errstate(divide="ignore"):
+        return np.where(lap > 0, area * kT / (sigma * np.where(lap > 0, lap, 1.0)), np.nan)
+
+
+def run(p, y_refs, rho_L, rho_V, width, steps, burn_in, interval, half_window=25,
+        drho=None, sim=None):
+    """Burn in from the stripe (or ``drho``), then sum the height spectra of
+    both interfaces over snapshots every ``interval`` steps until ``steps``.
+    y_refs = (rising, falling) interface positions; after the burn-in each is
+    moved to its column-mean height.  Returns (spectrum sum (2, plane) numpy,
+    number of snapshots, mean heights, the Simulation)."""
+    if sim is None:
+        if drho is None:
+            drho = stripe(p, y_refs[0], y_refs[1], rho_L, rho_V, width)
+        sim = Simulation(p, drho_init=drho)
+    stream = torch.cuda.Stream()
+    n_axis = p.ny if p.d == 2 else p.nz
+    nsnap = (steps - burn_in) // interval
+    with torch.cuda.stream(stream):
+        sim.graph_capture(interval, stats_stride=0, stream=stream)
+        for _ in range(burn_in // interval):
+            sim.graph_launch(stream)
+        if burn_in % interval:
+            sim.step(burn_in % interval, stream=stream)
+        ifs = [(y_refs[0], 1, half_window), (y_refs[1], -1, half_window)]
+        h = sim.interface_heights(ifs, rho_L, rho_V, width, stream=stream)
+        means = h.reshape(2, -1).mean(1).cpu().numpy()
+        ifs = [(float(means[0]) % n_axis, 1, half_window),
+               (float(means[1]) % n_axis, -1, half_window)]
+        spec = torch.zeros_like(h)
+        hsum = torch.zeros(2, dtype=torch.float64, device=h.device)
+        work = torch.empty(16 * h.numel(), dtype=torch.uint8, device=h.device)
+        for _ in range(nsnap):
+            sim.graph_launch(stream)
+            h = sim.interface_heights(ifs, rho_L, rho_V, width, stream=stream)
+            field_spectrum(h, spec, work=work, stream=stream)
+            hsum += h.reshape(2, -1).mean(1)
+    stream.synchronize()
+    return spec.cpu().numpy(), nsnap, (hsum / max(nsnap, 1)).cpu().numpy(), sim

@@ -421,7 +421,55 @@ flb_status flb_mode_spectrum(flb_handle* h, void* work, double* spec, void* stre
     double* fields = (double*)((char*)work + (size_t)h->q * h->V * 2 * sizeof(double));
     if (s.force) HIP_TRY(launch_density(s, h->cur(), h->drho, st));
     HIP_TRY(launch_mode_fields(s, h->cur(), h->drho, fields, st));
-    HIP_TRY(launch_spectrum(h->q, h->d, s.nx, s.ny, s.nz, fields, work, spec, st));
+    HIP_TRY(launch_spectrum(h->q, h->d == 2 ? 1 : 3, s.nx, s.ny, s.nz, fields, work, spec, st));
+    return FLB_OK;
+}
+
+flb_status flb_field_spectrum(const double* fields, int32_t nfields, int32_t nx, int32_t ny,
+                              int32_t nz, void* work, double* spec, void* stream) {
+    if (!fields || !work || !spec) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    if (nfields < 1 || nx < 1 || ny < 1 || nz < 1)
+        return fail(FLB_ERR_INVALID_ARG, "nfields and extents must be positive");
+    if (nx > SPECTRUM_MAX_N || ny > SPECTRUM_MAX_N || nz > SPECTRUM_MAX_N)
+        return fail(FLB_ERR_UNSUPPORTED, "field spectra need every extent <= 1024");
+    if (!aligned(work)) return fail(FLB_ERR_INVALID_ARG, "work must be 256-byte aligned");
+    if ((uintptr_t)fields % sizeof(double) || (uintptr_t)spec % sizeof(double))
+        return fail(FLB_ERR_INVALID_ARG, "fields and spec must be 8-byte aligned");
+    HIP_TRY(launch_spectrum(nfields, 0, nx, ny, nz, fields, work, spec, (hipStream_t)stream));
+    return FLB_OK;
+}
+
+flb_status flb_interface_heights(flb_handle* h, const flb_interface* ifs, int32_t n_if,
+                                 double rho_L, double rho_V, double width, double* heights,
+                                 void* stream) {
+    if (!h || !ifs || !heights) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    if (!h->spec.force)
+        return fail(FLB_ERR_UNSUPPORTED, "interface heights need the non-ideal fluid");
+    if (n_if < 1 || n_if > MAX_INTERFACES)
+        return fail(FLB_ERR_INVALID_ARG, "n_if must be in [1, 8]");
+    if (!(width > 0.0) || !(rho_L != rho_V) || !std::isfinite(rho_L) || !std::isfinite(rho_V))
+        return fail(FLB_ERR_INVALID_ARG, "width must be positive and rho_L != rho_V");
+    if ((uintptr_t)heights % sizeof(double))
+        return fail(FLB_ERR_INVALID_ARG, "heights must be 8-byte aligned");
+    const StepSpec& s = h->spec;
+    const int n = h->d == 2 ? s.ny : s.nz;           // profile axis: y (2-D) or z (3-D)
+    const long ncol = (long)(h->V / (size_t)n);
+    InterfaceSet set{};
+    set.n = n_if;
+    for (int j = 0; j < n_if; ++j) {
+        const flb_interface& f = ifs[j];
+        if (!(f.y_ref >= 0.0 && f.y_ref < n) || (f.sign != 1 && f.sign != -1) ||
+            f.half_window < 1 || 2 * f.half_window + 1 > n)
+            return fail(FLB_ERR_INVALID_ARG,
+                        "interface: y_ref in [0, n), sign +-1, 1 <= half_window, 2 W + 1 <= n");
+        set.y0[j] = (int)std::floor(f.y_ref + 0.5);
+        set.sign[j] = f.sign;
+        set.half_window[j] = f.half_window;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_density(s, h->cur(), h->drho, st));
+    HIP_TRY(launch_interface_heights(s.prec, h->drho, s.rho0, n, ncol, set, rho_L, rho_V, width,
+                                     heights, st));
     return FLB_OK;
 }
 

@@ -81,10 +81,22 @@ hipError_t launch_set_u64(unsigned long long* ctr, unsigned long long v, hipStre
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
 // Mode spectra (spectrum.hip).  fields: q real fields of nx ny nz sites;
-// work: q V complex; spec: (q + npairs) V doubles, added to.
+// work: q V complex; spec: (q + npairs) V doubles, added to; npairs momentum
+// cross spectra (rows 1..3 of fields), 0 for plain power spectra.
 constexpr int SPECTRUM_MAX_N = 1024;
-hipError_t launch_spectrum(int q, int d, int nx, int ny, int nz, const double* fields,
+hipError_t launch_spectrum(int q, int npairs, int nx, int ny, int nz, const double* fields,
                            void* work, double* spec, hipStream_t st);
+// Interface heights: up to 8 interfaces, window centre y0 = floor(y_ref + 1/2).
+constexpr int MAX_INTERFACES = 8;
+struct InterfaceSet {
+    int n;
+    int y0[MAX_INTERFACES];
+    int sign[MAX_INTERFACES];
+    int half_window[MAX_INTERFACES];
+};
+hipError_t launch_interface_heights(int prec, const void* drho, double rho0, int n, long ncol,
+                                    const InterfaceSet& set, double rho_L, double rho_V,
+                                    double width, double* out, hipStream_t st);
 
 // Adjoint launchers (adjoint.hip).
 hipError_t launch_adjoint_seed(const StepSpec& s, const void* rhobar, void* abar, hipStream_t st);

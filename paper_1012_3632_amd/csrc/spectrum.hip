@@ -14,7 +14,12 @@
 // in the work array; k_spec_accumulate then adds |m_a(k)|^2 for every mode
 // and Re(j_alpha(k) conj j_beta(k)) for the momentum pairs (x, y) [2-D] or
 // (x, y), (y, z), (z, x) [3-D], the cross spectra that split the momentum
-// into longitudinal and transverse parts.
+// into longitudinal and transverse parts.  The same passes give the spectra
+// of any real fields (flb_field_spectrum), e.g. of interface heights.
+//
+// Interface heights (the capillary test of Sec. VI): for every column across
+// a planar interface, the shift h of the mean-field profile (eq. denprof)
+// that best fits the column's density (eq. height-def), by Gauss-Newton.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -62,7 +67,7 @@ __global__ __launch_bounds__(DFT_THREADS) void k_dft_lines(const double* __restr
 }
 
 // spec[a V + s] += |W_a(s)|^2 (a < q); spec[(q + p) V + s] += Re(W_{1+al} conj W_{1+be})
-// for the momentum pair p = (al, be) = (p, (p + 1) mod 3).
+// for the momentum pair p = (al, be) = (p, (p + 1) mod 3), p < npairs.
 __global__ __launch_bounds__(256) void k_spec_accumulate(const double2* __restrict__ W,
                                                          double* __restrict__ spec, int q,
                                                          int npairs, long V) {
@@ -80,9 +85,63 @@ __global__ __launch_bounds__(256) void k_spec_accumulate(const double2* __restri
     }
 }
 
+// Interface heights (capillary test): one thread per column c and interface j
+// (blockIdx.y).  The density of column c at profile coordinate y is
+// rho0 + drho[c + y ncol].  The height h minimizes
+//   E(h) = sum_{k=-W..W} (rho(y0 + k) - m(y0 + k - h))^2,
+//   m(u) = rho_c + sign (rho_L - rho_V)/2 tanh(2 u / w),
+// the mean-field profile; Gauss-Newton from h = y0, clamped to the window,
+// until the update is below 1e-13 (at most 64 iterations).
+template <typename Real>
+__global__ __launch_bounds__(256) void k_interface_heights(const Real* __restrict__ drho,
+                                                           double rho0, int n, long ncol,
+                                                           InterfaceSet set, double rho_c,
+                                                           double half_jump, double two_over_w,
+                                                           double* __restrict__ out) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (c >= ncol) return;
+    const int y0 = set.y0[j], W = set.half_window[j];
+    const double s = set.sign[j] * half_jump;
+    double h = (double)y0;
+    for (int it = 0; it < 64; ++it) {
+        double num = 0.0, den = 0.0;
+        for (int k = -W; k <= W; ++k) {
+            int yy = y0 + k;
+            if (yy < 0) yy += n;
+            if (yy >= n) yy -= n;
+            const double r = rho0 + (double)drho[c + (long)yy * ncol];
+            const double t = tanh(two_over_w * ((double)(y0 + k) - h));
+            const double mp = s * (1.0 - t * t) * two_over_w;
+            num += (r - (rho_c + s * t)) * mp;
+            den += mp * mp;
+        }
+        if (!(den > 0.0)) break;
+        const double hn = fmin(fmax(h - num / den, (double)(y0 - W)), (double)(y0 + W));
+        const double dh = hn - h;
+        h = hn;
+        if (fabs(dh) < 1e-13) break;
+    }
+    out[(long)j * ncol + c] = h;
+}
+
 }  // namespace
 
-hipError_t launch_spectrum(int q, int d, int nx, int ny, int nz, const double* fields,
+hipError_t launch_interface_heights(int prec, const void* drho, double rho0, int n, long ncol,
+                                    const InterfaceSet& set, double rho_L, double rho_V,
+                                    double width, double* out, hipStream_t st) {
+    const dim3 grid((unsigned)((ncol + 255) / 256), set.n);
+    const double rc = 0.5 * (rho_L + rho_V), half = 0.5 * (rho_L - rho_V), tw = 2.0 / width;
+    if (prec == 0)
+        hipLaunchKernelGGL(k_interface_heights<float>, grid, dim3(256), 0, st, (const float*)drho,
+                           rho0, n, ncol, set, rc, half, tw, out);
+    else
+        hipLaunchKernelGGL(k_interface_heights<double>, grid, dim3(256), 0, st,
+                           (const double*)drho, rho0, n, ncol, set, rc, half, tw, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectrum(int q, int npairs, int nx, int ny, int nz, const double* fields,
                            void* work, double* spec, hipStream_t st) {
     const long V = (long)nx * ny * nz;
     double2* W = (double2*)work;
@@ -95,7 +154,6 @@ hipError_t launch_spectrum(int q, int d, int nx, int ny, int nz, const double* f
     if (nz > 1)
         hipLaunchKernelGGL(k_dft_lines, dim3((unsigned)(V / nz), q), dim3(DFT_THREADS), 0, st,
                            nullptr, W, nz, (long)nx * ny, (long)nx * ny, V, V);
-    const int npairs = d == 2 ? 1 : 3;
     const long blocks = (V + 255) / 256 < 4096 ? (V + 255) / 256 : 4096;
     hipLaunchKernelGGL(k_spec_accumulate, dim3((unsigned)blocks), dim3(256), 0, st, W, spec, q,
                        npairs, V);

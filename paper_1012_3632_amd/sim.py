@@ -116,6 +116,27 @@ def lattice_tables(lattice):
                 T=np.array(T[:]).reshape(q, q), N=np.array(N[:]), cls=np.array(cls[:]))
 
 
+def field_spectrum(fields, spec=None, work=None, stream=None):
+    """Add |DFT|^2 of each real field to spec: fields float64 CUDA (nf, nz, ny, nx)
+    (or (nf, ny, nx), (nf, nx)); spec of the same shape, zero-filled if None.
+    Returns spec."""
+    f = fields.contiguous()
+    assert f.dtype == torch.float64 and f.is_cuda and f.dim() >= 2
+    dims = list(f.shape[1:])
+    while len(dims) < 3:
+        dims.insert(0, 1)
+    nz, ny, nx = dims
+    if spec is None:
+        spec = torch.zeros_like(f)
+    assert spec.shape == f.shape and spec.dtype == torch.float64 and spec.is_contiguous()
+    need = 16 * f.numel()
+    if work is None or work.numel() < need:
+        work = torch.empty(max(need, 256), dtype=torch.uint8, device=f.device)
+    call("flb_field_spectrum", _ptr(f), int(f.shape[0]), int(nx), int(ny), int(nz), _ptr(work),
+         _ptr(spec), _stream(stream))
+    return spec
+
+
 def noise_words(params, step, block, site0, nsites, tag=0, device="cuda", stream=None):
     """Raw Philox words of noise block ``block`` at ``step`` for a range of sites:
     uint32 values as an int64 CPU tensor of shape (nsites, 4)."""
@@ -253,6 +274,21 @@ class Simulation:
         call("flb_mode_spectrum", self.handle, _ptr(self._spec_work), _ptr(spec),
              _stream(stream))
         return spec
+
+    def interface_heights(self, interfaces, rho_L, rho_V, width, stream=None):
+        """Heights of planar interfaces across the profile axis (y in 2-D, z in
+        3-D) by fitting the mean-field profile to every column: interfaces is a
+        list of (y_ref, sign, half_window); returns float64 (n_if, nx) in 2-D,
+        (n_if, ny, nx) in 3-D."""
+        p = self.params
+        arr = (_lib.flb_interface * len(interfaces))()
+        for j, (y, sg, w) in enumerate(interfaces):
+            arr[j].y_ref, arr[j].sign, arr[j].half_window = float(y), int(sg), int(w)
+        plane = (p.nx,) if p.d == 2 else (p.ny, p.nx)
+        out = torch.empty((len(interfaces),) + plane, dtype=torch.float64, device=self.device)
+        call("flb_interface_heights", self.handle, arr, len(interfaces), float(rho_L),
+             float(rho_V), float(width), _ptr(out), _stream(stream))
+        return out
 
     def density(self, s, stream=None):
         """rho - rho0 after streaming of state s (q, nz, ny, nx)."""
