@@ -309,6 +309,58 @@ def extras(args, stream):
         "momentum_max_dev_k_lt_2.5": round(dev(range(1, 3)), 4),
         "nonconserved_max_dev_k_lt_2.5": round(dev(range(3, 9)), 4)}
 
+    # the capillary-fluctuation test of Sec. VI: 1024 x 400 stripe, 10^6 steps
+    from paper_1012_3632_amd import capillary as CAP
+    from paper_1012_3632_amd import field_spectrum
+    wl = W.WORKLOADS["d2q9_capillary"]
+    pc = CAP.paper_params(seed=wl["seed"])
+    wc = CAP.mean_field_width(wl["rho_L"], wl["rho_V"], wl["kappa"], wl["beta"])
+    sc = Simulation(pc, drho_init=CAP.stripe(pc, *wl["stripe"], wl["rho_L"], wl["rho_V"], wc))
+    ifs = [(wl["stripe"][0], 1, 25), (wl["stripe"][1], -1, 25)]
+    sc.graph_capture(wl["interval"], stats_stride=0, stream=stream)
+    sc.graph_launch(stream=stream)
+    hh = sc.interface_heights(ifs, wl["rho_L"], wl["rho_V"], wc, stream=stream)
+    hspec = torch.zeros_like(hh)
+    e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sc.graph_launch(stream=stream)
+    e1.record(stream)
+    for _ in range(20):
+        hh = sc.interface_heights(ifs, wl["rho_L"], wl["rho_V"], wc, stream=stream)
+    e2.record(stream)
+    for _ in range(20):
+        field_spectrum(hh, hspec, stream=stream)
+    e3.record(stream)
+    e3.synchronize()
+    ms_step = e0.elapsed_time(e1) / wl["interval"]
+    us_h, us_s = e1.elapsed_time(e2) / 20 * 1e3, e2.elapsed_time(e3) / 20 * 1e3
+    sc.close()
+    del sc, hh, hspec
+    t0 = time.perf_counter()
+    spec_c, nsnap, means, sc = CAP.run(pc, wl["stripe"], wl["rho_L"], wl["rho_V"], wc,
+                                        wl["steps"], wl["burn_in"], wl["interval"])
+    run_s = time.perf_counter() - t0
+    sc.close()
+    kc = 2 * np.pi * np.arange(pc.nx) / pc.nx
+    s_eff = CAP.effective_surface_tension(pc, wl["rho_L"], wl["rho_V"])
+    s_mf = CAP.surface_tension(wl["rho_L"], wl["rho_V"], wl["kappa"], wl["beta"])
+    ratio = lambda sig, lo, hi: round(float(np.mean(
+        spec_c[:, (kc >= lo) & (kc < hi)] / (nsnap * CAP.capillary_theory(pc, pc.kT, sig)[(kc >= lo) & (kc < hi)]))), 3)
+    Vc = pc.nx * pc.ny
+    res["d2q9_capillary"] = {
+        "ms_per_step": round(ms_step, 5), "MLUPS": round(Vc / (ms_step * 1e-3) / 1e6, 1),
+        "heights_us": round(us_h, 2), "height_spectrum_us": round(us_s, 2),
+        "run_s": round(run_s, 3), "steps": wl["steps"], "snapshots": nsnap,
+        "sigma_eq_surf_tension": round(float(s_mf), 6), "sigma_effective": round(float(s_eff), 6),
+        "spectrum_over_theory_sigma_eff": {"k<0.1": ratio(s_eff, 0.005, 0.1),
+                                           "0.1-0.4": ratio(s_eff, 0.1, 0.4),
+                                           "0.4-1": ratio(s_eff, 0.4, 1.0),
+                                           "1-pi": ratio(s_eff, 1.0, 3.2)},
+        "spectrum_over_theory_sigma": {"k<0.1": ratio(s_mf, 0.005, 0.1),
+                                       "0.1-0.4": ratio(s_mf, 0.1, 0.4)},
+        "mean_heights": [round(float(x), 3) for x in means]}
+
     # differentiable run: adjoint / forward time
     from paper_1012_3632_amd.autograd import FLBRun
     wl = W.WORKLOADS["d2q9_256_adjoint"]

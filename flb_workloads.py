@@ -42,7 +42,7 @@ Workloads (all periodic, rho0 = 1, fluid initially at rest, lattice units):
                         FP32 with rho0 0.75, seed 1995; started from the
                         mean-field profile of width sqrt(8 kappa / beta) /
                         (rho_L - rho_V) (``stripe_drho``); 10^6 steps, 2000
-                        snapshots (every 475 steps after 50000; the paper gives
+                        snapshots (every 474 steps after 52000; the paper gives
                         neither the burn-in nor the spacing).
 
 The paper's own runs use no public dataset; its 2-D demonstrations (128^2
@@ -80,8 +80,8 @@ WORKLOADS = {
                            rho0=0.75, kT=1e-7, rate_bulk=1.0, rate_shear=1.0, rate_ghost=1.0,
                            seed=1995, force_model=1, a=-0.0125, b=0.1, rho_c=0.75,
                            kappa=0.08, eta=1, rho_L=1.0, rho_V=0.5, beta=0.1,
-                           stripe=(100.0, 300.0), steps=1000000, burn_in=50000,
-                           snapshots=2000, interval=475),
+                           stripe=(100.0, 300.0), steps=1000000, burn_in=52000,
+                           snapshots=2000, interval=474),
 }
 
 PARAM_KEYS = ("lattice", "nx", "ny", "nz", "rho0", "kT", "rate_bulk", "rate_shear",

@@ -90,7 +90,8 @@ def capillary_theory(p, kT, sigma):
 def run(p, y_refs, rho_L, rho_V, width, steps, burn_in, interval, half_window=25,
         drho=None, sim=None):
     """Burn in from the stripe (or ``drho``), then sum the height spectra of
-    both interfaces over snapshots every ``interval`` steps until ``steps``.
+    both interfaces over snapshots every ``interval`` steps (even: the steps
+    between snapshots are one captured graph) until ``steps``.
     y_refs = (rising, falling) interface positions; after the burn-in each is
     moved to its column-mean height.  Returns (spectrum sum (2, plane) numpy,
     number of snapshots, mean heights, the Simulation)."""

@@ -35,7 +35,10 @@ constexpr int DFT_THREADS = 256;
 // The line is read from `real_in` (imaginary part zero) when that is non-null,
 // else from `work`, and its transform X(k) = sum_j x(j) exp(-2 pi i j k / n)
 // is written to `work` at the same positions (in place: the whole line is in
-// LDS before any thread writes).
+// LDS before any thread writes).  With gridDim.z > 1 (only when reading
+// real_in, so that no block overwrites what another still reads) block z
+// computes the outputs k = z DFT_THREADS + t, t < DFT_THREADS, of every
+// gridDim.z DFT_THREADS.
 __global__ __launch_bounds__(DFT_THREADS) void k_dft_lines(const double* __restrict__ real_in,
                                                             double2* work, int n, long stride,
                                                             long inner, long outer, long V) {
@@ -51,7 +54,7 @@ __global__ __launch_bounds__(DFT_THREADS) void k_dft_lines(const double* __restr
         buf[j] = real_in ? make_double2(real_in[off], 0.0) : work[off];
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < n; k += DFT_THREADS) {
+    for (int k = blockIdx.z * DFT_THREADS + threadIdx.x; k < n; k += DFT_THREADS * gridDim.z) {
         double re = 0.0, im = 0.0;
         int idx = 0;   // j k mod n
         for (int j = 0; j < n; ++j) {
@@ -85,28 +88,30 @@ __global__ __launch_bounds__(256) void k_spec_accumulate(const double2* __restri
     }
 }
 
-// Interface heights (capillary test): one thread per column c and interface j
-// (blockIdx.y).  The density of column c at profile coordinate y is
-// rho0 + drho[c + y ncol].  The height h minimizes
+// Interface heights (capillary test): one wavefront per column c and
+// interface j (blockIdx.y), its lanes over the window.  The density of column
+// c at profile coordinate y is rho0 + drho[c + y ncol].  The height h minimizes
 //   E(h) = sum_{k=-W..W} (rho(y0 + k) - m(y0 + k - h))^2,
 //   m(u) = rho_c + sign (rho_L - rho_V)/2 tanh(2 u / w),
 // the mean-field profile; Gauss-Newton from h = y0, clamped to the window,
-// until the update is below 1e-13 (at most 64 iterations).
+// until the update is below 1e-13 (at most 64 iterations).  The two sums of
+// every iteration are reduced over the wavefront by a fixed butterfly, so
+// all lanes hold the same h and leave the loop together.
+constexpr int HEIGHT_WAVES = 4;
 template <typename Real>
-__global__ __launch_bounds__(256) void k_interface_heights(const Real* __restrict__ drho,
-                                                           double rho0, int n, long ncol,
-                                                           InterfaceSet set, double rho_c,
-                                                           double half_jump, double two_over_w,
-                                                           double* __restrict__ out) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(64 * HEIGHT_WAVES) void k_interface_heights(
+    const Real* __restrict__ drho, double rho0, int n, long ncol, InterfaceSet set, double rho_c,
+    double half_jump, double two_over_w, double* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const long c = (long)blockIdx.x * HEIGHT_WAVES + (threadIdx.x >> 6);
     const int j = blockIdx.y;
-    if (c >= ncol) return;
+    if (c >= ncol) return;   // whole wavefronts leave together
     const int y0 = set.y0[j], W = set.half_window[j];
     const double s = set.sign[j] * half_jump;
     double h = (double)y0;
     for (int it = 0; it < 64; ++it) {
         double num = 0.0, den = 0.0;
-        for (int k = -W; k <= W; ++k) {
+        for (int k = -W + lane; k <= W; k += 64) {
             int yy = y0 + k;
             if (yy < 0) yy += n;
             if (yy >= n) yy -= n;
@@ -116,13 +121,18 @@ __global__ __launch_bounds__(256) void k_interface_heights(const Real* __restric
             num += (r - (rho_c + s * t)) * mp;
             den += mp * mp;
         }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            num += __shfl_xor(num, off, 64);
+            den += __shfl_xor(den, off, 64);
+        }
         if (!(den > 0.0)) break;
         const double hn = fmin(fmax(h - num / den, (double)(y0 - W)), (double)(y0 + W));
         const double dh = hn - h;
         h = hn;
         if (fabs(dh) < 1e-13) break;
     }
-    out[(long)j * ncol + c] = h;
+    if (lane == 0) out[(long)j * ncol + c] = h;
 }
 
 }  // namespace
@@ -130,14 +140,15 @@ __global__ __launch_bounds__(256) void k_interface_heights(const Real* __restric
 hipError_t launch_interface_heights(int prec, const void* drho, double rho0, int n, long ncol,
                                     const InterfaceSet& set, double rho_L, double rho_V,
                                     double width, double* out, hipStream_t st) {
-    const dim3 grid((unsigned)((ncol + 255) / 256), set.n);
+    const dim3 grid((unsigned)((ncol + HEIGHT_WAVES - 1) / HEIGHT_WAVES), set.n);
+    const dim3 block(64 * HEIGHT_WAVES);
     const double rc = 0.5 * (rho_L + rho_V), half = 0.5 * (rho_L - rho_V), tw = 2.0 / width;
     if (prec == 0)
-        hipLaunchKernelGGL(k_interface_heights<float>, grid, dim3(256), 0, st, (const float*)drho,
+        hipLaunchKernelGGL(k_interface_heights<float>, grid, block, 0, st, (const float*)drho,
                            rho0, n, ncol, set, rc, half, tw, out);
     else
-        hipLaunchKernelGGL(k_interface_heights<double>, grid, dim3(256), 0, st,
-                           (const double*)drho, rho0, n, ncol, set, rc, half, tw, out);
+        hipLaunchKernelGGL(k_interface_heights<double>, grid, block, 0, st, (const double*)drho,
+                           rho0, n, ncol, set, rc, half, tw, out);
     return hipGetLastError();
 }
 
@@ -145,8 +156,12 @@ hipError_t launch_spectrum(int q, int npairs, int nx, int ny, int nz, const doub
                            void* work, double* spec, hipStream_t st) {
     const long V = (long)nx * ny * nz;
     double2* W = (double2*)work;
-    // x: lines of contiguous sites, read from the real fields
-    hipLaunchKernelGGL(k_dft_lines, dim3((unsigned)(V / nx), q), dim3(DFT_THREADS), 0, st,
+    // x: lines of contiguous sites, read from the real fields; few long lines
+    // have their outputs split over blocks
+    const long xlines = V / nx;
+    int chunks = 1;
+    while (chunks * DFT_THREADS < nx && xlines * q * chunks < 1024) chunks *= 2;
+    hipLaunchKernelGGL(k_dft_lines, dim3((unsigned)xlines, q, chunks), dim3(DFT_THREADS), 0, st,
                        fields, W, nx, 1L, 1L, (long)nx, V);
     if (ny > 1)
         hipLaunchKernelGGL(k_dft_lines, dim3((unsigned)(V / ny), q), dim3(DFT_THREADS), 0, st,

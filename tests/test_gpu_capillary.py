@@ -156,7 +156,7 @@ def test_capillary_run_follows_the_effective_tension():
     p = C.paper_params(seed=wl["seed"])
     w = C.mean_field_width(wl["rho_L"], wl["rho_V"], wl["kappa"], wl["beta"])
     spec, nsnap, means, _ = C.run(p, wl["stripe"], wl["rho_L"], wl["rho_V"], w, 200000,
-                                  wl["burn_in"], 500)
+                                  50000, 500)
     assert nsnap == 300
     k = 2 * np.pi * np.arange(p.nx) / p.nx
     s_eff = C.effective_surface_tension(p, wl["rho_L"], wl["rho_V"])
