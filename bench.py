@@ -244,21 +244,33 @@ def extras(args, stream):
                                rate_ghost=wl["rate_ghost"]))
     b = Batch(pb, [(e, e, e) for e in edges], seeds=list(range(wl["replicas"])))
     (_, best), _ = b.autotune(repeats=3)
+    pair_bytes, ngroups = b.pairs()
     gsteps = 100
-    b.graph_capture(gsteps, stats_stride=1, stream=stream)
-    b.graph_launch(stream=stream)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    b.graph_launch(stream=stream)
-    e1.record(stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / gsteps
+
+    def batch_graph_ms():
+        b.graph_capture(gsteps, stats_stride=1, stream=stream)
+        b.graph_launch(stream=stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        b.graph_launch(stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / gsteps
+
+    ms = batch_graph_ms()
+    # the other schedule, for the record
+    b.set_pairs(0 if pair_bytes else 128 << 20)
+    ms_other = batch_graph_ms()
+    b.set_pairs(pair_bytes)
     Vt = sum(e ** 3 for e in edges)
     res["d3q19_batch64"] = {"ms_per_step": round(ms, 4), "MLUPS": round(Vt / (ms * 1e-3) / 1e6, 1),
                             "sites": Vt, "grid_config": best,
                             "hbm_frac": round(152 * Vt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "in_place_pair_groups": ngroups, "pair_group_bytes": pair_bytes,
+                            ("ms_per_step_replica_interleaved" if pair_bytes else
+                             "ms_per_step_pairs_128MiB_groups"): round(ms_other, 4),
                             "graph_steps": gsteps, "statistics": "every step"}
     b.close()
     del b

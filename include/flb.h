@@ -303,9 +303,10 @@ flb_status flb_destroy(flb_handle* h);
  * Q V_r consecutive reals starting at element offset Q * sum_{s<r} V_s of
  * each population buffer (replica-major, then SoA within the replica).
  * Statistics buffer: a table of per-chunk sums (2Q x chunks FP64, a chunk
- * being up to 2048 consecutive sites of one replica; rewritten by each
- * sampled step) followed by the per-replica FP64 accumulators (R x 2Q), to
- * which each sampled step adds its sums over the replica's chunks.
+ * being up to 8 tiles of 256 sites of one replica; each sampled step of a
+ * call adds to it) followed by the per-replica FP64 accumulators (R x 2Q), to
+ * which the end of each call (flb_batch_step, a graph replay) adds the sums
+ * over the replica's chunks, clearing the table.
  * -------------------------------------------------------------------------*/
 typedef struct flb_batch flb_batch;
 
@@ -364,11 +365,33 @@ flb_status flb_launch_configs(const flb_handle* h, int32_t* count, int32_t* curr
  * shape. */
 flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape);
 /* The same for a batch: the candidates are persistent grids of 8, 4, 16 or 2
- * blocks per compute unit; best[2] / best_ms[2] as for flb_autotune.  The
- * statistics trials write only the per-chunk table that every sampled step
- * overwrites, so the accumulated statistics are unchanged.  Synchronizes. */
+ * blocks per compute unit; best[2] / best_ms[2] as for flb_autotune.  It then
+ * times in-place pairs group by group (flb_batch_set_pairs) with groups of up
+ * to 64, 128 and 192 MiB on each of the four grids, with statistics, and keeps
+ * the fastest (budget and grid) if it beats
+ * the ordinary step with statistics (else turns pairs off).  The statistics
+ * trials add only to the per-chunk table, which is clear between calls and
+ * cleared again afterwards, so the accumulated statistics are unchanged;
+ * the pair trials run on a copy
+ * of the state in the other buffer, so the state is unchanged.
+ * Synchronizes. */
 flb_status flb_batch_autotune(flb_batch* b, int32_t repeats, int32_t* best, double* best_ms,
                               void* stream);
+
+/* Schedule of the batch's steps.  pair_bytes = 0: every step advances all
+ * replicas, alternating the two buffers.  pair_bytes > 0: consecutive
+ * replicas are grouped up to pair_bytes of populations (a larger replica is a
+ * group of its own) and each group is taken through all the steps of a call
+ * (flb_batch_step, or the steps recorded by flb_batch_graph_capture) before
+ * the next, pairs of steps in place in one buffer (the layout of
+ * flb_step's in-place pairs), a last odd step in the ordinary way; a group
+ * small enough to stay in the last-level cache runs faster.  The noise counters
+ * are global, so states and statistics are bitwise the same in either
+ * schedule.  A graph captured earlier keeps the schedule it was captured
+ * with.  Host only. */
+flb_status flb_batch_set_pairs(flb_batch* b, uint64_t pair_bytes);
+/* The current pair_bytes and number of groups (0 when off).  Host only. */
+flb_status flb_batch_pairs(const flb_batch* b, uint64_t* pair_bytes, int32_t* ngroups);
 
 /* Text of a status code; last error text (thread-local) with HIP details. */
 const char* flb_strerror(flb_status s);

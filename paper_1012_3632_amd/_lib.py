@@ -95,6 +95,8 @@ PROTOS = {
     "flb_adjoint_run": [vp, P(vp), C.c_int32, C.c_int64, C.c_int64, vp, vp, P(C.c_double), vp],
     "flb_adjoint_run_bytes": [vp, C.c_int64, P(C.c_size_t)],
     "flb_batch_autotune": [vp, C.c_int32, P(C.c_int32), P(C.c_double), vp],
+    "flb_batch_set_pairs": [vp, C.c_uint64],
+    "flb_batch_pairs": [vp, P(C.c_uint64), P(C.c_int32)],
 }
 
 for _name, _args in PROTOS.items():

@@ -10,11 +10,21 @@
 // nothing beyond the last partial wave.  Replica r has its own box, Philox
 // key seeds[r] and counter word 3 = r, and its populations start at element
 // Q * sum_{s<r} V_s of each buffer.
+// In-place pairs (optional, flb_batch_set_pairs): consecutive replicas are
+// grouped up to a byte budget and each group is taken through all the steps of
+// a call before the next, pairs of steps in one buffer (the first step of a
+// pair stores S*_i(x) in plane opp(i) at x + c_i, the second reads plane
+// opp(i) at x and stores plane i at x; every location a thread writes is one
+// only it reads, just before), so that a group's working set can stay in the
+// last-level cache.  The noise counters hold the global step, so the result
+// is the same bits in either schedule.
 // Statistics: a thread sums the moments of its CH sites in registers; a
-// sampled step stores each chunk's 2Q FP64 block sums in a value-major table
-// partial[k][chunk] (plain stores, one block reduction per chunk), and
-// k_batch_accumulate then adds, per replica and value, the sum over the
-// replica's chunks (fixed order) to an FP64 accumulator.
+// sampled step adds each chunk's 2Q FP64 block sums to a value-major table
+// partial[k][chunk] (one block reduction per chunk, the chunk's own slots),
+// and at the end of a call k_batch_fold adds, per replica and value, the sum
+// over the replica's chunks (fixed order) to an FP64 accumulator and clears
+// the slots.  Either schedule adds the same chunk sums in the same step
+// order, so the statistics are bitwise the same.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -109,21 +119,111 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
         if constexpr (STATS) {
             double* lds = lds_stats + (it & 1) * LDS1;
             rows_to_lds<2 * Q>(v, lds);
-            lds_rows_finish<2 * Q, BT, false>(lds, partial + c, nchunks);
+            lds_rows_finish<2 * Q, BT, true>(lds, partial + c, nchunks);
         }
     }
 }
 
-// acc[r][k] += sum over replica r's chunks (fixed order) of partial[k][chunk].
-__global__ void k_batch_accumulate(const double* __restrict__ partial,
-                                   const RepInfo* __restrict__ reps, uint32_t nchunks, int nvals,
-                                   double* __restrict__ acc_out) {
+// One step of an in-place pair on the chunks [c0, c1) of the single buffer f
+// (not restrict: a thread's stores alias its own earlier loads).  PH 0 pulls
+// from the ordinary layout and stores S*_i(x) in plane opp(i) at x + c_i; PH 1
+// reads plane opp(i) at x and stores plane i at x.  The per-site arithmetic
+// and the statistics are those of k_batch_step.
+template <int LAT, typename Real, bool STATS, int PH>
+__global__ __launch_bounds__(BT) void k_batch_step_ip(Real* f, const RepInfo* __restrict__ reps,
+                                                      const uint32_t* __restrict__ chunk_rep,
+                                                      uint32_t c0, uint32_t c1, uint32_t nchunks,
+                                                      CollideParams<Real> P, StepIndex st,
+                                                      double* __restrict__ partial) {
+    using L = Lattice<LAT>;
+    using M = Moments<LAT, Real>;
+    constexpr int Q = L::Q, D = L::D;
+    constexpr int LDS1 = 4 * (BT / 64) * 2 * Q;
+    __shared__ double lds_stats[STATS ? 2 * LDS1 : 1];
+    const uint32_t step = st.get();
+    uint32_t it = 0;
+    for (uint32_t c = c0 + blockIdx.x; c < c1; c += gridDim.x, ++it) {
+        const uint32_t r = chunk_rep[c];
+        const RepInfo R = reps[r];
+        Geom g;
+        g.nx = R.nx;
+        g.ny = R.ny;
+        g.nz = R.nz;
+        g.V = R.V;
+        const uint32_t s0 = (c - R.chunk0) * (uint32_t)BT;
+        const uint32_t ds = R.nchunks * (uint32_t)BT;
+        Real* base = f + R.off;
+        Real v[STATS ? 2 * Q : 1];
+        if constexpr (STATS) {
+#pragma unroll
+            for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
+        }
+#pragma unroll 1
+        for (int tt = 0; tt < CH; ++tt) {
+            if (s0 + (uint32_t)tt * ds >= R.V) break;   // chunk with fewer tiles (uniform)
+            const uint32_t s = s0 + (uint32_t)tt * ds + threadIdx.x;
+            if (s < R.V) {
+                const uint32_t yz = div_small(s, R.inv_nx);
+                const int x = (int)(s - yz * (uint32_t)R.nx);
+                const uint32_t z = div_small(yz, R.inv_ny);
+                const int y = (int)(yz - z * (uint32_t)R.ny);
+                Real fl[Q], m[Q];
+                if constexpr (PH == 0) {
+                    pull<LAT, Real>(base, x, y, (int)z, g, fl);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) fl[i] = base[(size_t)L::opp[i] * R.V + s];
+                }
+                M::forward(fl, m);
+                if constexpr (STATS) {
+#pragma unroll
+                    for (int a = 0; a < Q; ++a) {
+                        v[a] += m[a];
+                        v[Q + a] += m[a] * m[a];
+                    }
+                }
+                Real zn[2 * L::NPAIR];
+                if (P.noise_on) site_normals<L::NPAIR, Real>(s, step, 0u, r, R.key0, R.key1, zn);
+                const Real F[D] = {};
+                collide_moments<LAT, Real, false>(m, F, zn, P);
+                M::inverse(m, fl);
+                if constexpr (PH == 0) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) {
+                        int xx = x + L::cx[i], yy = y + L::cy[i], zz = (int)z + L::cz[i];
+                        xx = xx < 0 ? xx + R.nx : (xx >= R.nx ? xx - R.nx : xx);
+                        yy = yy < 0 ? yy + R.ny : (yy >= R.ny ? yy - R.ny : yy);
+                        zz = zz < 0 ? zz + R.nz : (zz >= R.nz ? zz - R.nz : zz);
+                        const uint32_t t = (uint32_t)xx + (uint32_t)R.nx * ((uint32_t)yy + (uint32_t)R.ny * (uint32_t)zz);
+                        base[(size_t)L::opp[i] * R.V + t] = fl[i];
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) base[(size_t)i * R.V + s] = fl[i];
+                }
+            }
+        }
+        if constexpr (STATS) {
+            double* lds = lds_stats + (it & 1) * LDS1;
+            rows_to_lds<2 * Q>(v, lds);
+            lds_rows_finish<2 * Q, BT, true>(lds, partial + c, nchunks);
+        }
+    }
+}
+
+// acc[r][k] += sum over replica r's chunks (fixed order) of partial[k][chunk],
+// then those slots are cleared.  One block per (value k, replica r).
+__global__ void k_batch_fold(double* __restrict__ partial, const RepInfo* __restrict__ reps,
+                             uint32_t nchunks, int nvals, double* __restrict__ acc_out) {
     __shared__ double red[256];
     const int k = blockIdx.x, r = blockIdx.y;
     const RepInfo R = reps[r];
-    const double* col = partial + (size_t)k * nchunks + R.chunk0;
+    double* col = partial + (size_t)k * nchunks + R.chunk0;
     double acc = 0.0;
-    for (uint32_t t = threadIdx.x; t < R.nchunks; t += 256) acc += col[t];
+    for (uint32_t t = threadIdx.x; t < R.nchunks; t += 256) {
+        acc += col[t];
+        col[t] = 0.0;
+    }
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -242,6 +342,11 @@ flb_status batch_layout(const flb_params* p, int32_t nrep, const int32_t* dims,
 
 }  // namespace
 
+// Consecutive replicas [r0, r1), whose chunks are [c0, c1).
+struct BatchGroup {
+    uint32_t r0, r1, c0, c1;
+};
+
 struct flb_batch {
     flb_params p;
     int q, nrep;
@@ -261,6 +366,9 @@ struct flb_batch {
     int grid_cfg;          // persistent grid of plain steps
     int grid_cfg_stats;    // persistent grid of steps with statistics
     int ncu;
+    uint64_t pair_bytes;   // > 0: in-place pairs, groups of replicas up to this many bytes
+    int pair_cfg;          // persistent grid of the in-place steps
+    std::vector<BatchGroup> groups;
     hipGraph_t graph;
     hipGraphExec_t gexec;
     int64_t graph_steps, graph_samples;
@@ -274,9 +382,7 @@ constexpr int N_GRID_CFG = 4;
 constexpr int GRID_PER_CU[N_GRID_CFG] = {8, 4, 16, 2};
 
 template <int LAT, typename Real>
-void batch_launch(flb_batch* b, int cfg, const void* fin, void* fout,
-                  const unsigned long long* step_dev, unsigned long long step_host,
-                  double* partial, hipStream_t st) {
+CollideParams<Real> batch_collide_params(const flb_batch* b) {
     CollideParams<Real> P;
     const flb_params& p = b->p;
     P.rho0 = (Real)p.rho0;
@@ -296,6 +402,14 @@ void batch_launch(flb_batch* b, int cfg, const void* fin, void* fout,
     P.noise_local = p.noise_rho_local ? 1 : 0;
     P.key0 = P.key1 = 0;   // per replica
     P.replica = 0;
+    return P;
+}
+
+template <int LAT, typename Real>
+void batch_launch(flb_batch* b, int cfg, const void* fin, void* fout,
+                  const unsigned long long* step_dev, unsigned long long step_host,
+                  double* partial, hipStream_t st) {
+    const CollideParams<Real> P = batch_collide_params<LAT, Real>(b);
     StepIndex si{step_dev, step_host};
     const uint32_t grid = std::min<uint32_t>(b->nchunks, (uint32_t)(b->ncu * GRID_PER_CU[cfg]));
     if (partial)
@@ -306,6 +420,59 @@ void batch_launch(flb_batch* b, int cfg, const void* fin, void* fout,
         hipLaunchKernelGGL((k_batch_step<LAT, Real, false>), dim3(grid), dim3(BT), 0, st,
                            (const Real*)fin, (Real*)fout, b->reps_dev, b->tiles_dev, b->nchunks, P,
                            si, partial);
+}
+
+template <int LAT, typename Real>
+void batch_ip_launch(flb_batch* b, int cfg, int phase, const BatchGroup& G, void* f,
+                     const unsigned long long* step_dev, unsigned long long step_host,
+                     double* partial, hipStream_t st) {
+    const CollideParams<Real> P = batch_collide_params<LAT, Real>(b);
+    StepIndex si{step_dev, step_host};
+    const uint32_t n = G.c1 - G.c0;
+    const uint32_t grid = std::min<uint32_t>(n, (uint32_t)(b->ncu * GRID_PER_CU[cfg]));
+    Real* fr = (Real*)f;
+#define FLB_BATCH_IP(S, PH)                                                                   \
+    hipLaunchKernelGGL((k_batch_step_ip<LAT, Real, S, PH>), dim3(grid), dim3(BT), 0, st, fr,  \
+                       b->reps_dev, b->tiles_dev, G.c0, G.c1, b->nchunks, P, si, partial)
+    if (partial) {
+        if (phase == 0) FLB_BATCH_IP(true, 0);
+        else FLB_BATCH_IP(true, 1);
+    } else {
+        if (phase == 0) FLB_BATCH_IP(false, 0);
+        else FLB_BATCH_IP(false, 1);
+    }
+#undef FLB_BATCH_IP
+}
+
+hipError_t batch_ip_one(flb_batch* b, int cfg, int phase, const BatchGroup& G, void* f,
+                        const unsigned long long* step_dev, unsigned long long step_host,
+                        double* partial, hipStream_t st) {
+    const int lat = b->p.lattice, prec = b->p.precision;
+    if (lat == 0 && prec == 0) batch_ip_launch<0, float>(b, cfg, phase, G, f, step_dev, step_host, partial, st);
+    else if (lat == 0) batch_ip_launch<0, double>(b, cfg, phase, G, f, step_dev, step_host, partial, st);
+    else if (prec == 0) batch_ip_launch<1, float>(b, cfg, phase, G, f, step_dev, step_host, partial, st);
+    else batch_ip_launch<1, double>(b, cfg, phase, G, f, step_dev, step_host, partial, st);
+    return hipGetLastError();
+}
+
+// Consecutive replicas up to `bytes` of populations per group (a replica
+// larger than that forms a group of its own).
+std::vector<BatchGroup> batch_groups(const flb_batch* b, uint64_t bytes) {
+    std::vector<BatchGroup> out;
+    const std::vector<RepInfo>& R = b->L.reps;
+    uint32_t r0 = 0;
+    uint64_t acc = 0;
+    for (uint32_t r = 0; r < (uint32_t)R.size(); ++r) {
+        const uint64_t rb = (uint64_t)b->q * R[r].V * b->rb;
+        if (r > r0 && acc + rb > bytes) {
+            out.push_back({r0, r, R[r0].chunk0, R[r].chunk0});
+            r0 = r;
+            acc = 0;
+        }
+        acc += rb;
+    }
+    out.push_back({r0, (uint32_t)R.size(), R[r0].chunk0, b->nchunks});
+    return out;
 }
 
 hipError_t batch_one(flb_batch* b, int cfg, const void* fin, void* fout,
@@ -325,19 +492,36 @@ flb_status batch_run(flb_batch* b, int64_t nsteps, int32_t stride, bool graph_mo
                      hipStream_t st, int64_t* samples) {
     int64_t ns = 0;
     const int nv = 2 * b->q;
-    for (int64_t k = 0; k < nsteps; ++k) {
-        const bool sample = stride > 0 && ((k + 1) % stride) == 0;
-        BHIP(batch_one(b, sample ? b->grid_cfg_stats : b->grid_cfg, b->cur(), b->other(),
-                       graph_mode ? b->ctr_dev : nullptr,
-                       graph_mode ? (unsigned long long)k : (unsigned long long)(b->step + k),
-                       sample ? b->stats : nullptr, st));
-        if (sample) {
-            hipLaunchKernelGGL(k_batch_accumulate, dim3(nv, b->nrep), dim3(256), 0, st, b->stats,
-                               b->reps_dev, b->nchunks, nv, batch_acc(b));
-            BHIP(hipGetLastError());
+    auto sampled = [stride](int64_t k) { return stride > 0 && ((k + 1) % stride) == 0; };
+    auto index = [&](int64_t k) {
+        return graph_mode ? (unsigned long long)k : (unsigned long long)(b->step + k);
+    };
+    const unsigned long long* sd = graph_mode ? b->ctr_dev : nullptr;
+    int64_t k = 0;
+    if (b->pair_bytes > 0 && nsteps >= 2) {
+        // group by group, pairs of steps in place in the current buffer
+        const int64_t np = nsteps & ~(int64_t)1;
+        for (const BatchGroup& G : b->groups) {
+            for (int64_t j = 0; j < np; ++j) {
+                const bool sample = sampled(j);
+                BHIP(batch_ip_one(b, b->pair_cfg, (int)(j & 1), G, b->cur(), sd, index(j),
+                                  sample ? b->stats : nullptr, st));
+            }
         }
+        for (int64_t j = 0; j < np; ++j) ns += sampled(j);
+        k = np;
+    }
+    for (; k < nsteps; ++k) {
+        const bool sample = sampled(k);
+        BHIP(batch_one(b, sample ? b->grid_cfg_stats : b->grid_cfg, b->cur(), b->other(), sd,
+                       index(k), sample ? b->stats : nullptr, st));
         b->cur_a = !b->cur_a;
         ns += sample;
+    }
+    if (ns > 0) {
+        hipLaunchKernelGGL(k_batch_fold, dim3(nv, b->nrep), dim3(256), 0, st, b->stats,
+                           b->reps_dev, b->nchunks, nv, batch_acc(b));
+        BHIP(hipGetLastError());
     }
     if (graph_mode) BHIP(launch_add_u64(b->ctr_dev, (unsigned long long)nsteps, st));
     *samples = ns;
@@ -393,6 +577,8 @@ flb_status flb_batch_init(const flb_params* base, int32_t nrep, const int32_t* d
     b->nsamples = 0;
     b->grid_cfg = 0;
     b->grid_cfg_stats = 0;
+    b->pair_bytes = 0;
+    b->pair_cfg = 2;
     b->graph = nullptr;
     b->gexec = nullptr;
     int dev = 0;
@@ -520,8 +706,8 @@ flb_status flb_batch_autotune(flb_batch* b, int32_t repeats, int32_t* best, doub
     BHIP(hipEventCreate(&e1));
     int bi[2] = {b->grid_cfg, b->grid_cfg_stats};
     float bt[2] = {1e30f, 1e30f};
-    // statistics trials only write the per-tile table, which every sampled
-    // step overwrites before it is read; the accumulators are not touched
+    // statistics trials only add to the per-chunk table, cleared below; the
+    // accumulators are not touched
     for (int mode = 0; mode < 2; ++mode) {
         double* part = mode ? b->stats : nullptr;
         for (int c = 0; c < N_GRID_CFG; ++c) {
@@ -540,10 +726,47 @@ flb_status flb_batch_autotune(flb_batch* b, int32_t repeats, int32_t* best, doub
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     b->grid_cfg = bi[0];
     b->grid_cfg_stats = bi[1];
+    // in-place pairs group by group, with statistics: the trials run in place
+    // on a copy of the state in the other buffer (the next ordinary step
+    // overwrites it), so the state is untouched
+    if (b->nrep > 0) {
+        BHIP(hipMemcpyAsync(b->other(), b->cur(), b->L.elems * b->rb, hipMemcpyDeviceToDevice,
+                            st));
+        uint64_t best_bytes = 0;
+        int best_cfg = b->pair_cfg;
+        float best_pair = bt[1];
+        for (uint64_t mib : {64ull, 128ull, 192ull}) {
+            const std::vector<BatchGroup> groups = batch_groups(b, mib << 20);
+            for (int c = 0; c < N_GRID_CFG; ++c) {
+                BHIP(hipEventRecord(e0, st));
+                for (const BatchGroup& G : groups)
+                    for (int j = 0; j < 2 * repeats; ++j)
+                        BHIP(batch_ip_one(b, c, j & 1, G, b->other(), nullptr, b->step + j,
+                                          b->stats, st));
+                BHIP(hipEventRecord(e1, st));
+                BHIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                BHIP(hipEventElapsedTime(&ms, e0, e1));
+                ms /= 2 * repeats;
+                if (ms < best_pair) {
+                    best_pair = ms;
+                    best_bytes = mib << 20;
+                    best_cfg = c;
+                }
+            }
+        }
+        b->pair_bytes = best_bytes;
+        b->pair_cfg = best_cfg;
+        // the statistics trials added to the per-chunk slots, which are clear
+        // between calls: clear them again
+        BHIP(launch_fill_zero(b->stats, (size_t)b->nchunks * 2 * b->q * sizeof(double), st));
+        BHIP(hipStreamSynchronize(st));
+        b->groups = best_bytes ? batch_groups(b, best_bytes) : std::vector<BatchGroup>();
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     for (int m = 0; m < 2; ++m) {
         if (best) best[m] = bi[m];
         if (best_ms) best_ms[m] = bt[m];
@@ -551,6 +774,18 @@ flb_status flb_batch_autotune(flb_batch* b, int32_t repeats, int32_t* best, doub
     return FLB_OK;
 }
 
+flb_status flb_batch_set_pairs(flb_batch* b, uint64_t pair_bytes) {
+    if (!b) return bfail(FLB_ERR_INVALID_ARG, "batch is NULL");
+    b->pair_bytes = pair_bytes;
+    b->groups = pair_bytes ? batch_groups(b, pair_bytes) : std::vector<BatchGroup>();
+    return FLB_OK;
+}
+flb_status flb_batch_pairs(const flb_batch* b, uint64_t* pair_bytes, int32_t* ngroups) {
+    if (!b) return bfail(FLB_ERR_INVALID_ARG, "batch is NULL");
+    if (pair_bytes) *pair_bytes = b->pair_bytes;
+    if (ngroups) *ngroups = (int32_t)b->groups.size();
+    return FLB_OK;
+}
 flb_status flb_batch_destroy(flb_batch* b) {
     if (!b) return FLB_OK;
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);

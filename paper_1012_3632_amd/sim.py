@@ -439,6 +439,18 @@ class Batch:
         call("flb_batch_autotune", self._h, int(repeats), best, ms, _stream(stream))
         return tuple(best[:]), tuple(ms[:])
 
+    def set_pairs(self, pair_bytes):
+        """0: all replicas every step (alternating buffers); > 0: groups of
+        replicas up to pair_bytes, each taken through all steps of a call in
+        place, pairs of steps in one buffer (the same bits either way)."""
+        call("flb_batch_set_pairs", self._h, int(pair_bytes))
+
+    def pairs(self):
+        """(pair_bytes, number of groups) of the current schedule."""
+        nb, ng = C.c_uint64(), C.c_int32()
+        call("flb_batch_pairs", self._h, C.byref(nb), C.byref(ng))
+        return nb.value, ng.value
+
     def moments(self, stream=None):
         q = self.params.q
         s = (C.c_double * (q * self.nrep))()

@@ -64,6 +64,54 @@ def test_batch_graph_replay_matches_eager():
     np.testing.assert_array_equal(qa, qc)
 
 
+@pytest.mark.parametrize("pair_bytes", [1, 60000, 1 << 40])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("lattice", ["D3Q19", "D2Q9"])
+def test_batch_pairs_bit_identical(lattice, precision, pair_bytes):
+    """Group-by-group in-place pairs (each replica its own group, several per
+    group, one group) give the ordinary schedule's states and statistics bit
+    for bit, over odd and even step counts."""
+    from paper_1012_3632_amd import Batch
+    dims = DIMS if lattice == "D3Q19" else [(nx, ny, 1) for (nx, ny, _) in DIMS]
+    kw = dict(C2, lattice=lattice, precision=precision)
+    a = Batch(gpu_params(**kw), dims)
+    c = Batch(gpu_params(**kw), dims)
+    c.set_pairs(pair_bytes)
+    nb, ng = c.pairs()
+    assert nb == pair_bytes and 1 <= ng <= len(dims)
+    if pair_bytes == 1:
+        assert ng == len(dims)
+    if pair_bytes == 1 << 40:
+        assert ng == 1
+    for n, stride in ((7, 2), (6, 3), (1, 1), (4, 0)):
+        a.step(n, stats_stride=stride)
+        c.step(n, stats_stride=stride)
+    torch.cuda.synchronize()
+    for r in range(len(dims)):
+        assert torch.equal(a.replica_state(r), c.replica_state(r)), r
+    for x, y in zip(a.moments(), c.moments()):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_batch_pairs_graph_replay():
+    from paper_1012_3632_amd import Batch
+    kw = dict(C2, precision="fp32")
+    a = Batch(gpu_params(**kw), DIMS)
+    c = Batch(gpu_params(**kw), DIMS)
+    c.set_pairs(60000)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        c.graph_capture(8, stats_stride=1)
+        for k in range(3):
+            a.step(8, stats_stride=1)
+            c.graph_launch()
+            torch.cuda.synchronize()
+            for r in range(len(DIMS)):
+                assert torch.equal(a.replica_state(r), c.replica_state(r)), (k, r)
+    for x, y in zip(a.moments(), c.moments()):
+        np.testing.assert_array_equal(x, y)
+
+
 def test_batch_autotune_keeps_state():
     from paper_1012_3632_amd import Batch
     b = Batch(gpu_params(**C2, precision="fp32"), DIMS)
@@ -72,6 +120,8 @@ def test_batch_autotune_keeps_state():
     m_before = b.moments()
     best, ms = b.autotune(repeats=2)
     assert all(t > 0 for t in ms) and all(0 <= c < 4 for c in best)
+    nb, ng = b.pairs()
+    assert nb in (0, 64 << 20, 128 << 20, 192 << 20) and (ng == 0) == (nb == 0)
     for r in range(len(DIMS)):
         assert torch.equal(before[r], b.replica_state(r))
     m_after = b.moments()
