@@ -425,6 +425,71 @@ def test_full_size_landau_256_windows():
     sim.close()
 
 
+@pytest.mark.parametrize("precision,dims", [("fp32", (1024, 1024, 1023)),
+                                            ("fp64", (1024, 1024, 511))])
+def test_maximum_size_windows(precision, dims):
+    """The largest lattice 32-bit offsets within a population plane allow (a
+    plane just below 4 GiB; the two buffers take ~163 GB of the 288 GB): the
+    last sites of every plane are addressed like the first.  In the 128 x 2
+    in-place shape, a lone (ordinary) step and then an in-place pair are
+    compared on 8^3 windows (at the origin, across the periodic wrap of the
+    far corner, at the last sites, and at random places) advanced by the
+    oracle with the noise of their global site indices: one step with the
+    inner 6^3, two steps with the inner 4^3."""
+    from oracle import flb, philox
+    from paper_1012_3632_amd import Simulation, lattice_tables
+    nx, ny, nz = dims
+    rb = 4 if precision == "fp32" else 8
+    assert nx * ny * nz * rb < 2 ** 32 <= nx * ny * (nz + 1) * rb
+    kw = dict(lattice="D3Q19", precision=precision, nx=nx, ny=ny, nz=nz, rho0=1.0, kT=1e-5,
+              rate_bulk=1.2, rate_shear=1.6, rate_ghost=1.0, seed=7)
+    sim = Simulation(gpu_params(**kw))
+    sim.set_launch(10)
+    sim.step(3, stats_stride=1)          # a pair in place, then a lone ordinary step
+    w = torch.as_tensor(lattice_tables("D3Q19")["w"]).view(-1, 1, 1, 1)
+    rng = np.random.default_rng(5)
+    Wd = 8
+    starts = [(0, 0, 0), (nz - 4, ny - 4, nx - 4), (nz - Wd, ny - Wd, nx - Wd)] + \
+             [(int(rng.integers(0, nz)), int(rng.integers(0, ny)), int(rng.integers(0, nx)))
+              for _ in range(2)]
+    ids = [tuple(torch.as_tensor(_window_ids(n, s0, Wd), device="cuda")
+                 for n, s0 in zip((nz, ny, nx), st)) for st in starts]
+
+    def windows():
+        S = sim.state()
+        return [S[:, iz[:, None, None], iy[None, :, None], ix[None, None, :]]
+                .to("cpu", torch.float64) + w * kw["rho0"] for iz, iy, ix in ids]
+
+    pw = oracle_params(**dict(kw, nx=Wd, ny=Wd, nz=Wd))
+    lat = flb.lattice_of(pw)
+    K = len(lat.noncons())
+
+    def advance(S, n0, steps, win):
+        iz, iy, ix = (t.cpu().numpy().astype(np.int64) for t in win)
+        sites = ((iz[:, None, None] * ny + iy[None, :, None]) * nx + ix[None, None, :]).reshape(-1)
+        for k in range(steps):
+            z = torch.as_tensor(philox.normals(None, n0 + k, K, kw["seed"], sites=sites))
+            S = flb.collide(flb.pull(S, lat), None, n0 + k, pw, lat, z=z.reshape(K, Wd, Wd, Wd))
+        return S
+
+    tol = 1e-5 if precision == "fp32" else 1e-12
+    for steps in (1, 2):                 # a lone step, then a pair in place
+        before = windows()
+        n0 = sim.step_index
+        sim.step(steps, stats_stride=1)
+        after = windows()
+        M = steps
+        inner = (slice(None),) + (slice(M, Wd - M),) * 3
+        for win, S0, S1 in zip(ids, before, after):
+            ref = advance(S0, n0, steps, win)
+            assert rel_err(S1[inner].numpy(), ref[inner].numpy()) < tol, (steps, win[0][0].item())
+    s1, s2, ns = sim.moments()
+    assert ns == 6 and np.all(np.isfinite(s1)) and np.all(np.isfinite(s2))
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+
 def test_full_size_batch64_replicas():
     """d3q19_batch64 at full size (64 replicas, 21.6 M sites) with the grid the
     autotuner picks, stepped through a captured graph as in the benchmark;
