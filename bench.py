@@ -90,7 +90,7 @@ def fdt_check(sim):
 def profile_key(shape):
     """Name(s) of a stats-on D3Q19 FP32 step launch in the committed counter
     table (an in-place shape has one entry per phase of a pair)."""
-    tx, ty, tz, spt, nt, _, ip = shape
+    tx, ty, tz, spt, nt, _, ip, _ = shape
     if ip:
         return ["k_step_ip_d3q19_fp32_stats_%dx%d_ph%d" % (tx, ty, ph) for ph in (0, 1)]
     return ["k_step_d3q19_fp32_stats_%dx%dx%dx%d%s" % (tx, ty, tz, spt, "_nt" if nt else "")]

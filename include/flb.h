@@ -351,6 +351,8 @@ flb_status flb_batch_destroy(flb_batch* b);
  * best_ms[3]: ms per step of the first three (either pointer may be NULL).
  * The statistics trials run on the handle's own slots, saved to host memory
  * before and restored after; the call synchronizes the stream.
+ * Until then a handle uses shape 0, except D2Q9 force steps, which use
+ * shape 4 (32 x 8, forming its own density tile).
  * flb_set_launch sets every shape to `config` (an in-place shape then serves
  * pairs and, as an ordinary kernel of its tile, lone steps);
  * flb_launch_configs writes the number of shapes and current[3] (plain, with
@@ -359,10 +361,11 @@ flb_status flb_autotune(flb_handle* h, int32_t repeats, int32_t* best, double* b
                         void* stream);
 flb_status flb_set_launch(flb_handle* h, int32_t config);
 flb_status flb_launch_configs(const flb_handle* h, int32_t* count, int32_t* current);
-/* shape[7] = threads per block in x, y, z, sites per thread (stacked in y),
+/* shape[8] = threads per block in x, y, z, sites per thread (stacked in y),
  * 1 if populations are stored with non-temporal hints, the number of z planes
- * a block sweeps (z-marching force step; 0 otherwise), and 1 for an in-place
- * shape. */
+ * a block sweeps (z-marching force step; 0 otherwise), 1 for an in-place
+ * shape, and 1 for a force step that forms its density tile from the
+ * populations itself (no density pass before it; D2Q9). */
 flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape);
 /* The same for a batch: the candidates are persistent grids of 8, 4, 16 or 2
  * blocks per compute unit; best[2] / best_ms[2] as for flb_autotune.  It then

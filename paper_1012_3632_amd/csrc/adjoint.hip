@@ -103,19 +103,112 @@ __device__ __forceinline__ void collide_adjoint(const Real (&m)[Lattice<LAT>::Q]
     mb[0] += rho_b;
 }
 
+// The density adjoint of the force on a tile (P2's arithmetic, shared by
+// k_adj_force and the fused collision adjoint).  With rs, ms the density and
+// mu staged by ForceTile<TX, TY, TZ>::stage (tile plus halos 2 and 1) and fbs
+// the force adjoint staged on the same region as rs:
+//   mubar(y) = -3 sum_i w_i c_i . (rho Fbar)(y - c_i)  on the tile plus halo 1,
+//   rhobar   = -Fbar . 3 grad_h mu + eta grad_h^T Fbar + psi''(rho) mubar - kappa lap_h mubar.
+template <int LAT, typename Real, int TX, int TY, int TZ>
+struct ForceAdjointTile {
+    using L = Lattice<LAT>;
+    using FT = ForceTile<LAT, Real, TX, TY, TZ>;
+    static constexpr int Q = L::Q, D = L::D, HZ = FT::HZ;
+    static constexpr int RX = FT::RX, RY = FT::RY, NR = FT::NR, MX = FT::MX, MY = FT::MY,
+                         NM = FT::NM;
+
+    // fbs[a NR + l] = Fbar_a at the staged site l (tile origin x0, y0, z0)
+    static __device__ __forceinline__ void load_fbar(const Real* __restrict__ Fbar, const Geom& g,
+                                                     int x0, int y0, int z0, Real* fbs,
+                                                     int nthreads) {
+        for (int l = threadIdx.x; l < NR; l += nthreads) {
+            const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
+            const int gx = wrap_any(x0 + lx - 2, g.nx);
+            const int gy = wrap_any(y0 + ly - 2, g.ny);
+            const int gz = wrap_any(z0 + lz - 2 * HZ, g.nz);
+            const uint32_t s = (uint32_t)((gz * g.ny + gy) * g.nx + gx);
+#pragma unroll
+            for (int a = 0; a < D; ++a) fbs[a * NR + l] = Fbar[(size_t)a * g.V + s];
+        }
+    }
+
+    static __device__ __forceinline__ void mubar(const Real* rs, const Real* fbs, Real* mubs,
+                                                 Real rho0, int nthreads) {
+        for (int l = threadIdx.x; l < NM; l += nthreads) {
+            const int mx = l % MX, my = (l / MX) % MY, mz = l / (MX * MY);
+            const int c = ((mz + HZ) * RY + (my + 1)) * RX + (mx + 1);
+            Real acc = Real(0);
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int n = c - (L::cz[i] * RY + L::cy[i]) * RX - L::cx[i];
+                const Real rn = rho0 + rs[n];
+                const int c3[3] = {L::cx[i], L::cy[i], L::cz[i]};
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    if (c3[a] == 0) continue;
+                    acc += Real(L::w[i] * c3[a]) * rn * fbs[a * NR + n];
+                }
+            }
+            mubs[l] = Real(-3) * acc;
+        }
+    }
+
+    // rhobar at tile-local site (tx, ty, tz)
+    static __device__ __forceinline__ Real rhobar(const Real* rs, const Real* ms, const Real* fbs,
+                                                  const Real* mubs, const ForceParams<Real>& fp,
+                                                  int tx, int ty, int tz) {
+        const int cm = ((tz + HZ) * MY + (ty + 1)) * MX + (tx + 1);
+        const int cr = ((tz + 2 * HZ) * RY + (ty + 2)) * RX + (tx + 2);
+        Real gmu[D], eterm = Real(0), lap = Real(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) gmu[a] = Real(0);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int om = (L::cz[i] * MY + L::cy[i]) * MX + L::cx[i];
+            const int orr = (L::cz[i] * RY + L::cy[i]) * RX + L::cx[i];
+            lap += Real(L::w[i]) * (mubs[cm + om] - mubs[cm]);
+            const int c3[3] = {L::cx[i], L::cy[i], L::cz[i]};
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                if (c3[a] == 0) continue;
+                const Real wc = Real(L::w[i] * c3[a]);
+                gmu[a] += wc * ms[cm + om];
+                eterm += wc * fbs[a * NR + cr - orr];
+            }
+        }
+        Real t1 = Real(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) t1 -= fbs[a * NR + cr] * Real(3) * gmu[a];
+        const Real d = rs[cr] + fp.shift;
+        const Real psi2 = Real(2) * fp.a + Real(12) * fp.b * d * d;
+        // eta cs2 grad_h rho = eta sum_i w_i c_i rho(x + c_i): its transpose carries no factor 3
+        return t1 + fp.eta * eterm + psi2 * mubs[cm] - fp.kappa * Real(6) * lap;
+    }
+};
+
 // Collision adjoint + transposed transforms + push (P1).
-template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ>
+// FUSE (D2Q9 force only): instead of reading the later step's rhobar (rb_prev),
+// form it here on the tile plus one site from that step's force adjoint
+// Fbar_next and density drho_next (the arithmetic of k_adj_force on a tile
+// two sites wider), so the reverse sweep needs no separate P2 per step.
+template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ, bool FUSE = false>
 __global__ __launch_bounds__(TX* TY* TZ) void k_adj_collide(
     const Real* __restrict__ s_n, const Real* __restrict__ abar, const Real* __restrict__ rb_prev,
     Real* __restrict__ abar_out, const Real* __restrict__ drho, Real* __restrict__ Fbar, Geom g,
     CollideParams<Real> P, ForceParams<Real> fp, Real inv2kT, uint32_t step,
-    double* __restrict__ gpartial) {
+    double* __restrict__ gpartial, const Real* __restrict__ drho_next,
+    const Real* __restrict__ Fbar_next) {
     using L = Lattice<LAT>;
     using M = Moments<LAT, Real>;
     using FT = ForceTile<LAT, Real, TX, TY, TZ>;
+    using FA = ForceAdjointTile<LAT, Real, TX + 2, TY + 2, TZ>;
     constexpr int Q = L::Q, D = L::D, NT = TX * TY * TZ;
+    static_assert(!FUSE || (FORCE && LAT == 0), "the fused sweep is the D2Q9 force path");
     constexpr int LDS_F = FORCE ? (FT::NR + FT::NM) : 1;
+    constexpr int NRB = (TX + 2) * (TY + 2);
+    constexpr int LDS_A = FUSE ? ((D + 1) * FA::NR + 2 * FA::NM + NRB) : 1;
     __shared__ Real lds_force[LDS_F];
+    __shared__ Real lds_adj[LDS_A];
     __shared__ double lds_red[4 * ((NT + 63) / 64) * 4];
 
     int x0, y0, z0;
@@ -133,7 +226,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_adj_collide(
         pull<LAT, Real>(s_n, x, y, z, g, f);
 #pragma unroll
         for (int i = 0; i < Q; ++i) ab[i] = abar[(size_t)i * g.V + site];
-        if (FORCE && rb_prev) {
+        if (FORCE && !FUSE && rb_prev) {
             // the density adjoint of the later step not yet spread over the
             // populations: abar_i(y) += rhobar(y + c_i)
 #pragma unroll
@@ -142,6 +235,27 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_adj_collide(
                 const int sy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? yp : ym);
                 const int sz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zp : zm);
                 ab[i] += rb_prev[(uint32_t)((sz * g.ny + sy) * g.nx + sx)];
+            }
+        }
+    }
+    if constexpr (FUSE) {
+        if (Fbar_next) {   // uniform over the grid
+            Real* rs2 = lds_adj;
+            Real* fbs2 = rs2 + FA::NR;
+            Real* ms2 = fbs2 + D * FA::NR;
+            Real* mubs2 = ms2 + FA::NM;
+            Real* rbs = mubs2 + FA::NM;
+            FA::load_fbar(Fbar_next, g, x0 - 1, y0 - 1, z0, fbs2, NT);
+            FA::FT::stage(drho_next, g, fp, x0 - 1, y0 - 1, z0, rs2, ms2, NT);   // synchronizes
+            FA::mubar(rs2, fbs2, mubs2, P.rho0, NT);
+            __syncthreads();
+            for (int l = threadIdx.x; l < NRB; l += NT)
+                rbs[l] = FA::rhobar(rs2, ms2, fbs2, mubs2, fp, l % (TX + 2), l / (TX + 2), 0);
+            __syncthreads();
+            if (inside) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    ab[i] += rbs[(ty + 1 + L::cy[i]) * (TX + 2) + (tx + 1 + L::cx[i])];
             }
         }
     }
@@ -190,76 +304,22 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_adj_force(const Real* __restrict
                                                            const Real* __restrict__ Fbar,
                                                            Real* __restrict__ rhobar, Geom g,
                                                            Real rho0, ForceParams<Real> fp) {
-    using L = Lattice<LAT>;
-    using FT = ForceTile<LAT, Real, TX, TY, TZ>;
-    constexpr int Q = L::Q, D = L::D, NT = TX * TY * TZ, HZ = FT::HZ;
-    constexpr int RX = FT::RX, RY = FT::RY, NR = FT::NR, MX = FT::MX, MY = FT::MY, NM = FT::NM;
-    __shared__ Real rs[NR];
-    __shared__ Real ms[NM];
-    __shared__ Real fbs[D * NR];
-    __shared__ Real mubs[NM];
+    using FA = ForceAdjointTile<LAT, Real, TX, TY, TZ>;
+    constexpr int D = FA::D, NT = TX * TY * TZ;
+    __shared__ Real rs[FA::NR];
+    __shared__ Real ms[FA::NM];
+    __shared__ Real fbs[D * FA::NR];
+    __shared__ Real mubs[FA::NM];
     int x0, y0, z0;
     tile_origin<LAT, TX, TY, TZ>(g, x0, y0, z0);
-    FT::stage(drho, g, fp, x0, y0, z0, rs, ms);
-    for (int l = threadIdx.x; l < NR; l += NT) {
-        const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
-        const int gx = wrap_any(x0 + lx - 2, g.nx);
-        const int gy = wrap_any(y0 + ly - 2, g.ny);
-        const int gz = wrap_any(z0 + lz - 2 * HZ, g.nz);
-        const uint32_t s = (uint32_t)((gz * g.ny + gy) * g.nx + gx);
-#pragma unroll
-        for (int a = 0; a < D; ++a) fbs[a * NR + l] = Fbar[(size_t)a * g.V + s];
-    }
-    __syncthreads();
-    // mubar(y) = -3 sum_i w_i c_i . (rho Fbar)(y - c_i) on the tile plus one halo
-    for (int l = threadIdx.x; l < NM; l += NT) {
-        const int mx = l % MX, my = (l / MX) % MY, mz = l / (MX * MY);
-        const int c = ((mz + HZ) * RY + (my + 1)) * RX + (mx + 1);
-        Real acc = Real(0);
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const int n = c - (L::cz[i] * RY + L::cy[i]) * RX - L::cx[i];
-            const Real rn = rho0 + rs[n];
-            const int c3[3] = {L::cx[i], L::cy[i], L::cz[i]};
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                if (c3[a] == 0) continue;
-                acc += Real(L::w[i] * c3[a]) * rn * fbs[a * NR + n];
-            }
-        }
-        mubs[l] = Real(-3) * acc;
-    }
+    FA::load_fbar(Fbar, g, x0, y0, z0, fbs, NT);
+    FA::FT::stage(drho, g, fp, x0, y0, z0, rs, ms);   // synchronizes
+    FA::mubar(rs, fbs, mubs, rho0, NT);
     __syncthreads();
     const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
     const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
     if (x >= g.nx || y >= g.ny || z >= g.nz) return;
-    const int cm = ((tz + HZ) * MY + (ty + 1)) * MX + (tx + 1);
-    const int cr = ((tz + 2 * HZ) * RY + (ty + 2)) * RX + (tx + 2);
-    Real gmu[D], eterm = Real(0), lap = Real(0);
-#pragma unroll
-    for (int a = 0; a < D; ++a) gmu[a] = Real(0);
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const int om = (L::cz[i] * MY + L::cy[i]) * MX + L::cx[i];
-        const int orr = (L::cz[i] * RY + L::cy[i]) * RX + L::cx[i];
-        lap += Real(L::w[i]) * (mubs[cm + om] - mubs[cm]);
-        const int c3[3] = {L::cx[i], L::cy[i], L::cz[i]};
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            if (c3[a] == 0) continue;
-            const Real wc = Real(L::w[i] * c3[a]);
-            gmu[a] += wc * ms[cm + om];
-            eterm += wc * fbs[a * NR + cr - orr];
-        }
-    }
-    Real t1 = Real(0);
-#pragma unroll
-    for (int a = 0; a < D; ++a) t1 -= fbs[a * NR + cr] * Real(3) * gmu[a];
-    const Real d = rs[cr] + fp.shift;
-    const Real psi2 = Real(2) * fp.a + Real(12) * fp.b * d * d;
-    // eta cs2 grad_h rho = eta sum_i w_i c_i rho(x + c_i): its transpose carries no factor 3
-    const Real out = t1 + fp.eta * eterm + psi2 * mubs[cm] - fp.kappa * Real(6) * lap;
-    rhobar[(uint32_t)((z * g.ny + y) * g.nx + x)] = out;
+    rhobar[(uint32_t)((z * g.ny + y) * g.nx + x)] = FA::rhobar(rs, ms, fbs, mubs, fp, tx, ty, tz);
 }
 
 // out_i(y) (+)= r(y + c_i) for every population (P3 and the density seed).
@@ -333,13 +393,19 @@ static ForceParams<Real> adj_force_params(const StepSpec& s) {
     return f;
 }
 
-// Force adjoint work space: D planes of Fbar, then two rhobar planes (a step
-// of a reverse sweep reads the later step's rhobar while writing its own).
+// Force adjoint work space.  D3Q19: D planes of Fbar, then two rhobar planes
+// (a step of a reverse sweep reads the later step's rhobar while writing its
+// own).  D2Q9 (fused sweep): two sets of D Fbar planes (a step reads the later
+// step's Fbar while writing its own), then one rhobar plane for a spread at
+// the end of a sweep or of a single step.
+static bool adj_fused(const StepSpec& s) { return s.force && s.lat == 0; }
+
 size_t adjoint_work_bytes(const StepSpec& s) {
     if (!s.force) return 0;
     const size_t rb = s.prec ? 8 : 4;
     const size_t D = s.lat == 1 ? 3 : 2;
-    return (D + 2) * (size_t)s.nx * s.ny * s.nz * rb;
+    const size_t planes = adj_fused(s) ? 2 * D + 1 : D + 2;
+    return planes * (size_t)s.nx * s.ny * s.nz * rb;
 }
 
 uint32_t adjoint_slots(const StepSpec& s) {
@@ -356,17 +422,36 @@ static void adj_launch(const StepSpec& s, const AdjointStepArgs& a, hipStream_t 
     const CollideParams<Real> P = adj_collide_params<Real>(s);
     const ForceParams<Real> fp = adj_force_params<Real>(s);
     const Real inv2kT = s.kT > 0.0 ? (Real)(0.5 / s.kT) : Real(0);
-    Real* Fbar = (Real*)a.work;
+    const dim3 grid(g.nblocks), block(T::X * T::Y * T::Z);
+    Real* base = (Real*)a.work;
+    if constexpr (FORCE && LAT == 0) {
+        // fused sweep: Fbar sets alternate; the later step's rhobar is formed
+        // inside the collision adjoint
+        Real* Fb_out = base + (size_t)a.rb_out * D * g.V;
+        const Real* Fb_next = a.rb_in >= 0 ? base + (size_t)a.rb_in * D * g.V : nullptr;
+        hipLaunchKernelGGL((k_adj_collide<LAT, Real, true, T::X, T::Y, T::Z, true>), grid, block,
+                           0, st, (const Real*)a.s_n, (const Real*)a.abar_np1, (const Real*)nullptr,
+                           (Real*)a.abar_n, (const Real*)a.drho, Fb_out, g, P, fp, inv2kT,
+                           (uint32_t)a.step, a.gpartial, (const Real*)a.drho_next, Fb_next);
+        if (a.spread) {
+            Real* rbar = base + (size_t)2 * D * g.V;
+            hipLaunchKernelGGL((k_adj_force<LAT, Real, T::X, T::Y, T::Z>), grid, block, 0, st,
+                               (const Real*)a.drho, (const Real*)Fb_out, rbar, g, (Real)s.rho0, fp);
+            hipLaunchKernelGGL((k_adj_spread<LAT, Real, true>), dim3((g.V + 255) / 256), dim3(256),
+                               0, st, (const Real*)rbar, (Real*)a.abar_n, g);
+        }
+        return;
+    }
+    Real* Fbar = base;
     Real* rb_in = (FORCE && a.rb_in >= 0) ? Fbar + (size_t)(D + a.rb_in) * g.V : nullptr;
     Real* rb_out = FORCE ? Fbar + (size_t)(D + a.rb_out) * g.V : nullptr;
-    hipLaunchKernelGGL((k_adj_collide<LAT, Real, FORCE, T::X, T::Y, T::Z>), dim3(g.nblocks),
-                       dim3(T::X * T::Y * T::Z), 0, st, (const Real*)a.s_n,
-                       (const Real*)a.abar_np1, (const Real*)rb_in, (Real*)a.abar_n,
-                       (const Real*)a.drho, Fbar, g, P, fp, inv2kT, (uint32_t)a.step, a.gpartial);
+    hipLaunchKernelGGL((k_adj_collide<LAT, Real, FORCE, T::X, T::Y, T::Z>), grid, block, 0, st,
+                       (const Real*)a.s_n, (const Real*)a.abar_np1, (const Real*)rb_in,
+                       (Real*)a.abar_n, (const Real*)a.drho, Fbar, g, P, fp, inv2kT,
+                       (uint32_t)a.step, a.gpartial, (const Real*)nullptr, (const Real*)nullptr);
     if constexpr (FORCE) {
-        hipLaunchKernelGGL((k_adj_force<LAT, Real, T::X, T::Y, T::Z>), dim3(g.nblocks),
-                           dim3(T::X * T::Y * T::Z), 0, st, (const Real*)a.drho, (const Real*)Fbar,
-                           rb_out, g, (Real)s.rho0, fp);
+        hipLaunchKernelGGL((k_adj_force<LAT, Real, T::X, T::Y, T::Z>), grid, block, 0, st,
+                           (const Real*)a.drho, (const Real*)Fbar, rb_out, g, (Real)s.rho0, fp);
         if (a.spread)
             hipLaunchKernelGGL((k_adj_spread<LAT, Real, true>), dim3((g.V + 255) / 256),
                                dim3(256), 0, st, (const Real*)rb_out, (Real*)a.abar_n, g);
@@ -376,6 +461,7 @@ static void adj_launch(const StepSpec& s, const AdjointStepArgs& a, hipStream_t 
 hipError_t launch_adjoint_step(const StepSpec& s, const AdjointStepArgs& a, hipStream_t st) {
     if (s.force && (a.rb_out < 0 || a.rb_out > 1 || a.rb_in > 1 || a.rb_in == a.rb_out))
         return hipErrorInvalidValue;
+    if (adj_fused(s) && a.rb_in >= 0 && !a.drho_next) return hipErrorInvalidValue;
     if (s.lat == 0 && s.prec == 0) {
         if (s.force) adj_launch<0, float, true>(s, a, st);
         else adj_launch<0, float, false>(s, a, st);
@@ -392,13 +478,37 @@ hipError_t launch_adjoint_step(const StepSpec& s, const AdjointStepArgs& a, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_spread(const StepSpec& s, void* work, int rb, void* abar,
-                                 hipStream_t st) {
+hipError_t launch_adjoint_spread(const StepSpec& s, void* work, int rb, const void* drho,
+                                 void* abar, hipStream_t st) {
     if (!s.force) return hipSuccess;
     if (rb < 0 || rb > 1) return hipErrorInvalidValue;
     const Geom g = adj_geom(s, 1, 1, 1);
-    const size_t off = (size_t)((s.lat == 1 ? 3 : 2) + rb) * g.V;
     const dim3 grid((g.V + 255) / 256), blk(256);
+    if (adj_fused(s)) {
+        // rhobar of the last step of the sweep from its Fbar set, then spread
+        if (!drho) return hipErrorInvalidValue;
+        using T = AdjTile<0, true>;
+        const Geom gt = adj_geom(s, T::X, T::Y, T::Z);
+        const dim3 tg(gt.nblocks), tb(T::X * T::Y * T::Z);
+        const size_t fb = (size_t)rb * 2 * g.V, rr = (size_t)4 * g.V;
+        if (s.prec == 0) {
+            float* w = (float*)work;
+            hipLaunchKernelGGL((k_adj_force<0, float, T::X, T::Y, T::Z>), tg, tb, 0, st,
+                               (const float*)drho, (const float*)(w + fb), w + rr, gt,
+                               (float)s.rho0, adj_force_params<float>(s));
+            hipLaunchKernelGGL((k_adj_spread<0, float, true>), grid, blk, 0, st,
+                               (const float*)(w + rr), (float*)abar, g);
+        } else {
+            double* w = (double*)work;
+            hipLaunchKernelGGL((k_adj_force<0, double, T::X, T::Y, T::Z>), tg, tb, 0, st,
+                               (const double*)drho, (const double*)(w + fb), w + rr, gt, s.rho0,
+                               adj_force_params<double>(s));
+            hipLaunchKernelGGL((k_adj_spread<0, double, true>), grid, blk, 0, st,
+                               (const double*)(w + rr), (double*)abar, g);
+        }
+        return hipGetLastError();
+    }
+    const size_t off = (size_t)((s.lat == 1 ? 3 : 2) + rb) * g.V;
     if (s.lat == 0 && s.prec == 0)
         hipLaunchKernelGGL((k_adj_spread<0, float, true>), grid, blk, 0, st, (const float*)work + off, (float*)abar, g);
     else if (s.lat == 0)

@@ -183,9 +183,11 @@ void scratch_layout(const StepSpec& s, size_t V, size_t rb, size_t* drho_off, si
 // One forward step of the handle: cur -> other, then swap.
 flb_status do_step(flb_handle* h, bool sample, const unsigned long long* step_dev,
                    unsigned long long step_host, hipStream_t st) {
-    if (h->spec.force) HIP_TRY(launch_density(h->spec, h->cur(), h->drho, st));
-    HIP_TRY(launch_step(h->spec, sample ? h->cfg_stats : h->cfg, h->cur(), h->other(), h->drho,
-                        step_dev, step_host, sample ? h->stats : nullptr, st));
+    const int cfg = sample ? h->cfg_stats : h->cfg;
+    if (h->spec.force && !config_fused(h->spec, cfg))
+        HIP_TRY(launch_density(h->spec, h->cur(), h->drho, st));
+    HIP_TRY(launch_step(h->spec, cfg, h->cur(), h->other(), h->drho, step_dev, step_host,
+                        sample ? h->stats : nullptr, st));
     h->cur_a = !h->cur_a;
     return FLB_OK;
 }
@@ -304,8 +306,9 @@ flb_status flb_init(const flb_params* p, void* f_a, void* f_b, void* scratch, vo
     h->slots = max_slots(h->spec);
     h->step = p->step0;
     h->nsamples = 0;
-    h->cfg = 0;
-    h->cfg_stats = 0;
+    // D2Q9 force steps default to the 32 x 8 tile that forms its own density
+    // tile (no density pass); every other kind to shape 0
+    h->cfg = h->cfg_stats = (h->spec.force && h->spec.lat == 0) ? 4 : 0;
     h->pair_cfg = -1;
     h->graph = nullptr;
     h->gexec = nullptr;
@@ -590,9 +593,16 @@ flb_status flb_autotune(flb_handle* h, int32_t repeats, int32_t* best, double* b
         for (int c = 0; c < ncfg && e == hipSuccess; ++c) {
             if (config_in_place(h->spec, c)) continue;   // timed as pairs below
             float ms = 0.f;
+            // a force step that reads a density field pays for its pass
+            const bool pass = h->spec.force && !config_fused(h->spec, c);
             e = timed([&](int k) {
-                return launch_step(h->spec, c, (k & 1) ? B : A, (k & 1) ? A : B, h->drho, nullptr,
-                                   h->step, part, st);
+                void* in = (k & 1) ? B : A;
+                if (pass) {
+                    hipError_t r = launch_density(h->spec, in, h->drho, st);
+                    if (r != hipSuccess) return r;
+                }
+                return launch_step(h->spec, c, in, (k & 1) ? A : B, h->drho, nullptr, h->step,
+                                   part, st);
             }, 1, &ms);
             if (e == hipSuccess && ms < bt[mode]) {
                 bt[mode] = ms;
@@ -676,6 +686,7 @@ flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape)
     shape[4] = t.nt;
     shape[5] = t.zc;
     shape[6] = t.ip;
+    shape[7] = t.fd;
     return FLB_OK;
 }
 
@@ -694,7 +705,7 @@ flb_status flb_adjoint_step(flb_handle* h, const void* s_n, const void* abar_np1
     hipStream_t st = (hipStream_t)stream;
     if (h->spec.force) HIP_TRY(launch_density(h->spec, s_n, h->drho, st));
     AdjointStepArgs a{s_n, h->drho, abar_np1, abar_n, h->adj_work, -1, 0, true,
-                      (unsigned long long)n, h->gpartial};
+                      (unsigned long long)n, h->gpartial, nullptr};
     HIP_TRY(launch_adjoint_step(h->spec, a, st));
     if (grad) {
         double* out = h->gpartial + (size_t)h->gslots * 4;
@@ -762,12 +773,14 @@ flb_status seg_reverse(const SegWork& sw, void* abar, uint64_t k0, hipStream_t s
     for (size_t j = sw.k; j-- > 0;) {
         const int rb_out = (int)(j & 1);
         AdjointStepArgs a{sw.state(j), sw.density(j), cur, nxt, h->adj_work, rb_in, rb_out, false,
-                          (unsigned long long)(k0 + j), h->gpartial};
+                          (unsigned long long)(k0 + j), h->gpartial,
+                          j + 1 < sw.k ? sw.density(j + 1) : nullptr};
         HIP_TRY(launch_adjoint_step(h->spec, a, st));
         rb_in = rb_out;
         std::swap(cur, nxt);
     }
-    if (h->spec.force) HIP_TRY(launch_adjoint_spread(h->spec, h->adj_work, rb_in, cur, st));
+    if (h->spec.force)
+        HIP_TRY(launch_adjoint_spread(h->spec, h->adj_work, rb_in, sw.density(0), cur, st));
     if (cur != abar)
         HIP_TRY(hipMemcpyAsync(abar, cur, (size_t)h->q * h->V * h->real_bytes,
                                hipMemcpyDeviceToDevice, st));

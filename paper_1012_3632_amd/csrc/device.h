@@ -210,11 +210,13 @@ struct ForceTile {
     static constexpr int NR = RX * RY * RZ, NM = MX * MY * MZ;
     static constexpr int NT = TX * TY * TZ;
 
+    // nthreads: the block's thread count (NT unless a wider tile is staged by
+    // a smaller block)
     static __device__ __forceinline__ void stage(const Real* __restrict__ drho, const Geom& g,
                                                  const ForceParams<Real>& fp, int x0, int y0,
-                                                 int z0, Real* rs, Real* ms) {
+                                                 int z0, Real* rs, Real* ms, int nthreads = NT) {
         const int tid = threadIdx.x;
-        for (int l = tid; l < NR; l += NT) {
+        for (int l = tid; l < NR; l += nthreads) {
             const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
             const int gx = wrap_any(x0 + lx - 2, g.nx);
             const int gy = wrap_any(y0 + ly - 2, g.ny);
@@ -222,7 +224,36 @@ struct ForceTile {
             rs[l] = drho[(uint32_t)((gz * g.ny + gy) * g.nx + gx)];
         }
         __syncthreads();
-        for (int l = tid; l < NM; l += NT) {
+        mu_from_rho(fp, rs, ms, nthreads);
+    }
+
+    // The same, with the density of every staged site formed here from the
+    // populations of fin (pulled and summed in the order of k_density, so the
+    // staged values are the same bits): no separate density pass.
+    static __device__ __forceinline__ void stage_pop(const Real* __restrict__ fin, const Geom& g,
+                                                     const ForceParams<Real>& fp, int x0, int y0,
+                                                     int z0, Real* rs, Real* ms) {
+        const int tid = threadIdx.x;
+        for (int l = tid; l < NR; l += NT) {
+            const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
+            const int gx = wrap_any(x0 + lx - 2, g.nx);
+            const int gy = wrap_any(y0 + ly - 2, g.ny);
+            const int gz = wrap_any(z0 + lz - 2 * HZ, g.nz);
+            Real f[L::Q];
+            pull<LAT, Real>(fin, gx, gy, gz, g, f);
+            Real acc = Real(0);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) acc += f[i];
+            rs[l] = acc;
+        }
+        __syncthreads();
+        mu_from_rho(fp, rs, ms, NT);
+    }
+
+    static __device__ __forceinline__ void mu_from_rho(const ForceParams<Real>& fp, const Real* rs,
+                                                       Real* ms, int nthreads) {
+        const int tid = threadIdx.x;
+        for (int l = tid; l < NM; l += nthreads) {
             const int mx = l % MX, my = (l / MX) % MY, mz = l / (MX * MY);
             const int c = ((mz + HZ) * RY + (my + 1)) * RX + (mx + 1);
             const Real rc = rs[c];

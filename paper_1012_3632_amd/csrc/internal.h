@@ -13,6 +13,8 @@ struct TileShape {
     int zc;           // > 0: the block sweeps zc planes in z (D3Q19 force step), tz = 1
     int ip;           // 1: in-place step pairs in one buffer (ideal gas); a lone
                       //    step runs the ordinary kernel of the same tile
+    int fd;           // 1: the force step forms the staged density tile from the
+                      //    populations itself (no density pass; D2Q9)
 };
 
 // Candidate tiles (the autotuner picks one per handle).
@@ -26,8 +28,10 @@ constexpr int N_FORCE3_CFG = 8;
 constexpr TileShape FORCE3_CFG[N_FORCE3_CFG] = {
     {32, 4, 2, 1, 0}, {16, 4, 4, 1, 0}, {64, 2, 2, 1, 0}, {64, 4, 1, 1, 0, 16},
     {64, 4, 1, 1, 0, 32}, {32, 8, 1, 1, 0, 16}, {64, 8, 1, 1, 0, 16}, {128, 2, 1, 1, 0, 16}};
-constexpr int N_FORCE2_CFG = 3;
-constexpr TileShape FORCE2_CFG[N_FORCE2_CFG] = {{64, 4, 1, 1, 0}, {32, 8, 1, 1, 0}, {128, 2, 1, 1, 0}};
+constexpr int N_FORCE2_CFG = 6;
+constexpr TileShape FORCE2_CFG[N_FORCE2_CFG] = {
+    {64, 4, 1, 1, 0},          {32, 8, 1, 1, 0},          {128, 2, 1, 1, 0},
+    {64, 4, 1, 1, 0, 0, 0, 1}, {32, 8, 1, 1, 0, 0, 0, 1}, {128, 2, 1, 1, 0, 0, 0, 1}};
 
 // Everything a forward launch needs, in FP64 on the host (converted per precision).
 struct StepSpec {
@@ -59,6 +63,8 @@ hipError_t launch_step(const StepSpec& s, int cfg, const void* fin, void* fout, 
 // In-place shapes: one step of a pair on the single buffer f (phase 0 then 1;
 // see push_rows_opp).  The state is in the ordinary layout after phase 1.
 bool config_in_place(const StepSpec& s, int cfg);
+// Force shapes whose step needs no density pass before it.
+bool config_fused(const StepSpec& s, int cfg);
 hipError_t launch_step_in_place(const StepSpec& s, int cfg, int phase, void* f,
                                 const unsigned long long* step_dev, unsigned long long step_host,
                                 double* partial, hipStream_t st);
@@ -111,11 +117,14 @@ struct AdjointStepArgs {
     bool spread;             // spread rb_out into abar_n now
     unsigned long long step;
     double* gpartial;        // per-block parameter-derivative slots (added to)
+    const void* drho_next;   // D2Q9 force: density of S_{n+1} when rb_in >= 0 (the
+                             //   pending rhobar is formed from its Fbar set rb_in)
 };
 hipError_t launch_adjoint_step(const StepSpec& s, const AdjointStepArgs& a, hipStream_t st);
-// abar_i(y) += rhobar(y + c_i) from rhobar plane rb of the work space.
-hipError_t launch_adjoint_spread(const StepSpec& s, void* work, int rb, void* abar,
-                                 hipStream_t st);
+// abar_i(y) += rhobar(y + c_i) from rhobar plane rb of the work space (D2Q9
+// force: rhobar formed first from Fbar set rb and the density drho).
+hipError_t launch_adjoint_spread(const StepSpec& s, void* work, int rb, const void* drho,
+                                 void* abar, hipStream_t st);
 size_t adjoint_work_bytes(const StepSpec& s);
 uint32_t adjoint_slots(const StepSpec& s);
 

@@ -50,7 +50,7 @@ __global__ void k_density(const Real* __restrict__ fin, Real* __restrict__ out, 
 }
 
 template <int LAT, typename Real, bool FORCE, bool STATS, int TX, int TY, int TZ, int SPT,
-          bool NTS>
+          bool NTS, bool FUSED = false>
 __global__ __launch_bounds__(TX* TY* TZ) void k_step(
     const Real* __restrict__ fin, Real* __restrict__ fout, const Real* __restrict__ drho, Geom g,
     CollideParams<Real> P, ForceParams<Real> fp, StepIndex st, double* __restrict__ partial) {
@@ -87,7 +87,8 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
             if constexpr (ROWS) pull_rows<LAT, Real>(fin, x, y0 + ty, z, g, fpre);
             else pull<LAT, Real>(fin, x, y0 + ty, z, g, fpre);
         }
-        FT::stage(drho, g, fp, x0, y0, z0, lds_force, lds_force + FT::NR);
+        if constexpr (FUSED) FT::stage_pop(fin, g, fp, x0, y0, z0, lds_force, lds_force + FT::NR);
+        else FT::stage(drho, g, fp, x0, y0, z0, lds_force, lds_force + FT::NR);
         if (in0) FT::force(lds_force, lds_force + FT::NR, fp, P.rho0, tx, ty, tz, F);
     }
 
@@ -477,7 +478,8 @@ hipError_t launch_density(const StepSpec& s, const void* fin, void* out, hipStre
     return hipGetLastError();
 }
 
-template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ, int SPT = 1, bool NTS = false>
+template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ, int SPT = 1, bool NTS = false,
+          bool FUSED = false>
 static void step_tile(const StepSpec& s, const void* fin, void* fout, const void* drho,
                       StepIndex si, double* partial, hipStream_t st) {
     const Geom g = make_geom(s, TileShape{TX, TY, TZ, SPT, NTS, 0, 0});
@@ -485,10 +487,10 @@ static void step_tile(const StepSpec& s, const void* fin, void* fout, const void
     const CollideParams<Real> P = collide_params<Real>(s);
     const ForceParams<Real> fp = force_params<Real>(s);
     if (partial)
-        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, true, TX, TY, TZ, SPT, NTS>), grid, block, 0, st,
+        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, true, TX, TY, TZ, SPT, NTS, FUSED>), grid, block, 0, st,
                            (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
     else
-        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, false, TX, TY, TZ, SPT, NTS>), grid, block, 0, st,
+        hipLaunchKernelGGL((k_step<LAT, Real, FORCE, false, TX, TY, TZ, SPT, NTS, FUSED>), grid, block, 0, st,
                            (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
 }
 
@@ -542,7 +544,10 @@ static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fou
         switch (cfg) {
             case 0: step_tile<LAT, Real, true, 64, 4, 1>(s, fin, fout, drho, si, partial, st); break;
             case 1: step_tile<LAT, Real, true, 32, 8, 1>(s, fin, fout, drho, si, partial, st); break;
-            default: step_tile<LAT, Real, true, 128, 2, 1>(s, fin, fout, drho, si, partial, st); break;
+            case 2: step_tile<LAT, Real, true, 128, 2, 1>(s, fin, fout, drho, si, partial, st); break;
+            case 3: step_tile<LAT, Real, true, 64, 4, 1, 1, false, true>(s, fin, fout, drho, si, partial, st); break;
+            case 4: step_tile<LAT, Real, true, 32, 8, 1, 1, false, true>(s, fin, fout, drho, si, partial, st); break;
+            default: step_tile<LAT, Real, true, 128, 2, 1, 1, false, true>(s, fin, fout, drho, si, partial, st); break;
         }
     }
 }
@@ -570,6 +575,11 @@ static void ip_dispatch(const StepSpec& s, int cfg, int phase, void* f, StepInde
         case 11: step_ip<LAT, Real, 64, 4>(s, phase, f, si, partial, st); break;
         default: step_ip<LAT, Real, 256, 1>(s, phase, f, si, partial, st); break;
     }
+}
+
+bool config_fused(const StepSpec& s, int cfg) {
+    return s.force && cfg >= 0 && cfg < n_configs(s.lat, s.force) &&
+           config_shape(s.lat, s.force, cfg).fd;
 }
 
 bool config_in_place(const StepSpec& s, int cfg) {

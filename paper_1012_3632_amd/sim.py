@@ -323,8 +323,8 @@ class Simulation:
 
     def launch_shape(self, config):
         """(tx, ty, tz, sites_per_thread, nontemporal, z_planes_per_block,
-        in_place) of a launch configuration."""
-        sh = (C.c_int32 * 7)()
+        in_place, fused_density) of a launch configuration."""
+        sh = (C.c_int32 * 8)()
         call("flb_launch_shape", self.handle, int(config), sh)
         return tuple(sh[:])
 

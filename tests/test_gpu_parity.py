@@ -425,6 +425,38 @@ def test_full_size_landau_256_windows():
     sim.close()
 
 
+@pytest.mark.parametrize("eta", [0, 1])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(13, 37), (64, 64), (1, 1), (3, 200)])
+def test_fused_density_bit_identical(shape, precision, eta):
+    """D2Q9 force steps that form the density tile from the populations
+    themselves (no density pass) give the bits of the same tile after a
+    density pass: states and statistics, over ragged, tiny and thin boxes."""
+    from paper_1012_3632_amd import Simulation
+    ny, nx = shape
+    kw = dict(C2, lattice="D2Q9", precision=precision, nx=nx, ny=ny, nz=1, kT=1e-5,
+              rho0=1.0, eta=eta, **LANDAU)
+    drho = W.initial_drho((1, ny, nx), 4, 0.01)
+    probe = Simulation(gpu_params(**kw))
+    shapes = [probe.launch_shape(c) for c in range(probe.launch_configs()[0])]
+    probe.close()
+    fused = [c for c, sh in enumerate(shapes) if sh[7]]
+    assert len(fused) == 3
+    for c in fused:
+        plain = next(u for u, sh in enumerate(shapes) if sh[:7] == shapes[c][:7] and not sh[7])
+        a = Simulation(gpu_params(**kw), drho_init=drho)
+        b = Simulation(gpu_params(**kw), drho_init=drho)
+        a.set_launch(plain)
+        b.set_launch(c)
+        for n, stride in ((3, 1), (4, 2), (1, 0)):
+            a.step(n, stats_stride=stride)
+            b.step(n, stats_stride=stride)
+        torch.cuda.synchronize()
+        assert torch.equal(a.state(), b.state()), (c, plain)
+        for x, y in zip(a.moments(), b.moments()):
+            np.testing.assert_array_equal(x, y)
+
+
 @pytest.mark.parametrize("precision,dims", [("fp32", (1024, 1024, 1023)),
                                             ("fp64", (1024, 1024, 511))])
 def test_maximum_size_windows(precision, dims):
