@@ -20,6 +20,9 @@
 // to every population of the site: abar_n,i(y) += rhobar(y + c_i).  In a
 // reverse sweep that last spread is deferred: the next (earlier) step's
 // collision adjoint adds rhobar(y + c_i) as it reads abar, which saves a pass.
+// For the D2Q9 force that rhobar is not stored either: the collision adjoint
+// forms it on its tile plus a one-site halo from the later step's Fbar and
+// density, staged in LDS, so a reverse step is a single launch.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
