@@ -29,6 +29,11 @@ fluctuations in the discrete Boltzmann equation"):
   heights by fitting the mean-field profile (eqs. height-def, denprof), their
   spectrum, eq. surf-tension and the capillary structure factor
   (eq. capill-static), and the effective tension of this lattice scheme.
+* ``modeq``    -- the modified-equilibrium (Swift) model of Sec. IV.B,
+  linearized about rest on D2Q9: equilibrium moments of eq. meq-yeo, the
+  correlations of eq. f-correl-yeo, the noise covariance fixed by the lattice
+  FDT (its DBE limit against eq. noise-yeo), white normals filtered in
+  Fourier space for the k-dependent (e, eps) block.
 * ``grad``     -- reference gradients of a scalar loss of the final density
   w.r.t. the initial populations, the shear rate and kT, by reverse-mode
   automatic differentiation of ``flb`` (plain definition of the derivative).
