@@ -88,6 +88,26 @@ PARAM_KEYS = ("lattice", "nx", "ny", "nz", "rho0", "kT", "rate_bulk", "rate_shea
               "rate_ghost", "force_model", "a", "b", "rho_c", "kappa", "eta", "seed")
 
 
+# The modified-equilibrium model (Sec. IV.B) at the equilibration parameters
+# of Sec. VI: D2Q9 128^2, rho0 1, c_s(0) 0.265, kappa 0.08, kT 1e-7, all
+# rates 1 (tau = 1), FP32 deviations from rest, seed 1012; the run starts
+# at rest, and after a burn-in of 20000 steps takes 400 snapshots 250 steps apart.
+MODEQ_WORKLOADS = {
+    "d2q9_128_modeq": dict(nx=128, ny=128, precision="fp32", rho0=1.0, kT=1e-7,
+                           cs2_0=0.265 ** 2, kappa=0.08, rate_bulk=1.0, rate_shear=1.0,
+                           rate_ghost=1.0, seed=1012, burn_in=20000, snapshots=400,
+                           interval=250),
+}
+MODEQ_PARAM_KEYS = ("nx", "ny", "precision", "rho0", "kT", "cs2_0", "kappa", "rate_bulk",
+                    "rate_shear", "rate_ghost", "seed")
+
+
+def modeq_params_of(name, **override):
+    d = {k: v for k, v in MODEQ_WORKLOADS[name].items() if k in MODEQ_PARAM_KEYS}
+    d.update(override)
+    return d
+
+
 def params_of(name, **override):
     """The FLB parameters of a workload as a plain dict (keys of PARAM_KEYS)."""
     w = dict(WORKLOADS[name])

@@ -201,6 +201,68 @@ flb_status flb_interface_heights(flb_handle* h, const flb_interface* ifs, int32_
                                  double rho_L, double rho_V, double width, double* heights,
                                  void* stream);
 
+/* ----------------------------------------------------------------------
+ * Modified-equilibrium (Swift) model, linearized about rest, D2Q9
+ * (Sec. IV.B, subsection on the modified-equilibrium model).
+ *
+ * State: deviations delta f_i from the uniform rest state, f[i * V + x + nx y]
+ * (V = nx ny), reals of `precision`.  One step with index n:
+ *   pull f_i(x) = S_i(x - c_i); m = T f (App. B basis: rho, j_x, j_y, e, p_xx,
+ *   p_xy, q_x, q_y, eps); linearized equilibrium of eq. meq-yeo
+ *     m^eq = {rho, j_x, j_y, D, 0, 0, 0, 0, -D},
+ *     D = 6 (cs2_0 - 1/3) rho - 6 kappa rho0 lap_h rho   (= d(k) rho,
+ *     d(k) = 6 (c_s^2(k) - 1/3), c_s^2(k) = cs2_0 + kappa rho0 Lambda(k),
+ *     Lambda the symbol of -lap_h; S(k) = rho0 kT / c_s^2(k), eq. s-nonideal);
+ *   m*_a = m_a - lam_a (m_a - m^eq_a) + xi_a;  S_{n+1} = w_i sum_a T_ai m*_a / N_a.
+ * Noise: covariance Xi(k) = G - C G C^T, G the equal-time correlations of
+ * eq. f-correl-yeo, C the collision matrix: white on p_xx, p_xy, q_x, q_y
+ * (rho0 kT N_a lam (2 - lam) / cs2, normals z_1..z_4 of the site), and for
+ * (e, eps), with c2 = c_s^2(k), lam_e = rate_bulk, lam_g = rate_ghost,
+ *   Xi_ee = 12 rho0 kT lam_e (2 - lam_e)(2 - 3 c2),
+ *   Xi_eE = 12 rho0 kT (3 c2 - 1)(lam_e + lam_g - lam_e lam_g),
+ *   Xi_EE = 12 rho0 kT lam_g (2 - lam_g)(5 - 3 c2),
+ * drawn as xi = IDFT[L(k) DFT[z_0, z_5]], L the lower Cholesky factor, z the
+ * site normals of the force-based step (Philox counter (site, n, block, 0),
+ * tag 0, replica 0).  Its small-rate limit is eq. noise-yeo with the (e, eps)
+ * entry at half its printed value (the value for which Xi is a covariance
+ * wherever the equilibrium populations are non-negative).
+ * --------------------------------------------------------------------- */
+typedef struct flb_modeq_params {
+    int32_t nx, ny;       /* periodic lattice, each in [1, 1024]                        */
+    int32_t precision;    /* FLB_FP32 or FLB_FP64 (state and step arithmetic; the noise
+                             transforms are FP64)                                        */
+    int32_t reserved;     /* 0                                                          */
+    double rho0;          /* > 0                                                        */
+    double kT;            /* >= 0; 0 runs the deterministic step and needs no work      */
+    double cs2_0;         /* c_s^2 at k = 0, > 0                                        */
+    double kappa;         /* >= 0, with cs2_0 + kappa rho0 16/3 <= 0.6                  */
+    double rate_bulk, rate_shear, rate_ghost;   /* lam^LB in (0, 2); ghost = q and eps  */
+    uint64_t seed;        /* Philox key                                                 */
+} flb_modeq_params;
+
+/* Device work bytes of flb_modeq_step / _run / _noise: 48 V (the complex
+ * noise spectra, then the filtered fields).  Rejects invalid parameters
+ * (FLB_ERR_INVALID_ARG), including rates for which the (e, eps) covariance
+ * is not positive semidefinite somewhere on [cs2_0, cs2_0 + kappa rho0 16/3]. */
+flb_status flb_modeq_work_bytes(const flb_modeq_params* p, size_t* bytes);
+
+/* One step with index `step` from fin to fout (distinct, device, 256-byte
+ * aligned, 9 V reals each).  `work` (device, 256-byte aligned, at least
+ * flb_modeq_work_bytes) is overwritten; it may be NULL when kT = 0.
+ * Asynchronous on `stream`. */
+flb_status flb_modeq_step(const flb_modeq_params* p, const void* fin, void* fout, uint64_t step,
+                          void* work, size_t work_bytes, void* stream);
+
+/* nsteps steps with indices step0 .. step0 + nsteps - 1; the result is in f,
+ * tmp (device, 9 V reals) is overwritten. */
+flb_status flb_modeq_run(const flb_modeq_params* p, void* f, void* tmp, uint64_t step0,
+                         int32_t nsteps, void* work, size_t work_bytes, void* stream);
+
+/* Verification: the filtered (e, eps) noise of step `step`, xi[0 .. V) = xi_e,
+ * xi[V .. 2V) = xi_eps (device, FP64). */
+flb_status flb_modeq_noise(const flb_modeq_params* p, uint64_t step, double* xi, void* work,
+                           size_t work_bytes, void* stream);
+
 /* Verification: the raw Philox4x32-10 words the step draws for noise block
  * `block` (tag `tag`) at step `step` for sites site0 .. site0 + nsites - 1,
  * written to out_dev[4 * s + k] (device, uint32).  Uses p->seed and

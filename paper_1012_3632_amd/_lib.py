@@ -42,6 +42,15 @@ class flb_interface(C.Structure):
     _fields_ = [("y_ref", C.c_double), ("sign", C.c_int32), ("half_window", C.c_int32)]
 
 
+class flb_modeq_params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32),
+        ("rho0", C.c_double), ("kT", C.c_double), ("cs2_0", C.c_double), ("kappa", C.c_double),
+        ("rate_bulk", C.c_double), ("rate_shear", C.c_double), ("rate_ghost", C.c_double),
+        ("seed", C.c_uint64),
+    ]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
                       "(python -m paper_1012_3632_amd.build)")
@@ -97,6 +106,10 @@ PROTOS = {
     "flb_batch_autotune": [vp, C.c_int32, P(C.c_int32), P(C.c_double), vp],
     "flb_batch_set_pairs": [vp, C.c_uint64],
     "flb_batch_pairs": [vp, P(C.c_uint64), P(C.c_int32)],
+    "flb_modeq_work_bytes": [P(flb_modeq_params), P(C.c_size_t)],
+    "flb_modeq_step": [P(flb_modeq_params), vp, vp, C.c_uint64, vp, C.c_size_t, vp],
+    "flb_modeq_run": [P(flb_modeq_params), vp, vp, C.c_uint64, C.c_int32, vp, C.c_size_t, vp],
+    "flb_modeq_noise": [P(flb_modeq_params), C.c_uint64, vp, vp, C.c_size_t, vp],
 }
 
 for _name, _args in PROTOS.items():

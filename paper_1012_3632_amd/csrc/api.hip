@@ -889,6 +889,137 @@ flb_status flb_adjoint_run(flb_handle* h, const void* const* ckpts, int32_t nseg
     return r;
 }
 
+// ------------------------------------------------ modified-equilibrium model
+
+namespace {
+
+// Xi_(e,eps) block at c_s^2 = c2 (per rho0 kT); see modeq.hip.
+void modeq_block(double c2, double le, double lg, double& see, double& sep, double& spp) {
+    see = 12.0 * le * (2.0 - le) * (2.0 - 3.0 * c2);
+    sep = 12.0 * (3.0 * c2 - 1.0) * (le + lg - le * lg);
+    spp = 12.0 * lg * (2.0 - lg) * (5.0 - 3.0 * c2);
+}
+
+flb_status modeq_args(const flb_modeq_params* p, ModEqArgs* a) {
+    if (!p) return fail(FLB_ERR_INVALID_ARG, "NULL params");
+    if (p->nx < 1 || p->ny < 1 || p->nx > SPECTRUM_MAX_N || p->ny > SPECTRUM_MAX_N)
+        return fail(FLB_ERR_INVALID_ARG, "modified-equilibrium extents must be in [1, 1024]");
+    if (p->precision != FLB_FP32 && p->precision != FLB_FP64)
+        return fail(FLB_ERR_INVALID_ARG, "precision must be FLB_FP32 or FLB_FP64");
+    if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0) || !(p->kT >= 0.0) || !std::isfinite(p->kT))
+        return fail(FLB_ERR_INVALID_ARG, "rho0 must be positive and kT >= 0");
+    const double rates[3] = {p->rate_bulk, p->rate_shear, p->rate_ghost};
+    for (double r : rates)
+        if (!(r > 0.0 && r < 2.0)) return fail(FLB_ERR_INVALID_ARG, "rates must lie in (0, 2)");
+    if (!(p->cs2_0 > 0.0) || !(p->kappa >= 0.0) || !std::isfinite(p->kappa))
+        return fail(FLB_ERR_INVALID_ARG, "cs2_0 must be positive and kappa >= 0");
+    // c_s^2(k) spans [cs2_0, cs2_0 + kappa rho0 16/3]; the equilibrium
+    // populations stay non-negative up to 0.6
+    const double c2max = p->cs2_0 + p->kappa * p->rho0 * 16.0 / 3.0;
+    if (!(c2max <= 0.6))
+        return fail(FLB_ERR_INVALID_ARG,
+                    "c_s^2(k) = cs2_0 + kappa rho0 Lambda(k) must stay <= 0.6 (max %g)", c2max);
+    for (int s = 0; s <= 256; ++s) {
+        const double c2 = p->cs2_0 + (c2max - p->cs2_0) * s / 256.0;
+        double see, sep, spp;
+        modeq_block(c2, p->rate_bulk, p->rate_ghost, see, sep, spp);
+        if (see < 0.0 || spp < 0.0 || see * spp - sep * sep < -1e-12 * (see * spp + 1e-300))
+            return fail(FLB_ERR_INVALID_ARG,
+                        "the (e, eps) noise covariance is not positive semidefinite at c_s^2 = %g "
+                        "for these rates",
+                        c2);
+    }
+    a->nx = p->nx;
+    a->ny = p->ny;
+    a->rho0 = p->rho0;
+    a->kT = p->kT;
+    a->cs2_0 = p->cs2_0;
+    a->kappa = p->kappa;
+    a->rate_bulk = p->rate_bulk;
+    a->rate_shear = p->rate_shear;
+    a->rate_ghost = p->rate_ghost;
+    a->k0 = (uint32_t)(p->seed & 0xffffffffu);
+    a->k1 = (uint32_t)(p->seed >> 32);
+    using L = Lattice<0>;
+    const double lam[4] = {p->rate_shear, p->rate_shear, p->rate_ghost, p->rate_ghost};
+    for (int k = 0; k < 4; ++k)
+        a->amp[k] = std::sqrt(p->rho0 * p->kT * L::N[4 + k] * lam[k] * (2.0 - lam[k]) / CS2);
+    return FLB_OK;
+}
+
+flb_status modeq_work_ok(const ModEqArgs& a, const void* work, size_t work_bytes) {
+    if (a.kT == 0.0) return FLB_OK;
+    if (!work) return fail(FLB_ERR_INVALID_ARG, "work is NULL");
+    if (!aligned(work)) return fail(FLB_ERR_INVALID_ARG, "work must be 256-byte aligned");
+    if (work_bytes < modeq_work_bytes(a.nx, a.ny))
+        return fail(FLB_ERR_INVALID_ARG, "work holds %zu bytes, %zu needed", work_bytes,
+                    modeq_work_bytes(a.nx, a.ny));
+    return FLB_OK;
+}
+
+}  // namespace
+
+flb_status flb_modeq_work_bytes(const flb_modeq_params* p, size_t* bytes) {
+    ModEqArgs a{};
+    if (!bytes) return fail(FLB_ERR_INVALID_ARG, "NULL bytes");
+    const flb_status r = modeq_args(p, &a);
+    if (r != FLB_OK) return r;
+    *bytes = modeq_work_bytes(a.nx, a.ny);
+    return FLB_OK;
+}
+
+flb_status flb_modeq_noise(const flb_modeq_params* p, uint64_t step, double* xi, void* work,
+                           size_t work_bytes, void* stream) {
+    ModEqArgs a{};
+    flb_status r = modeq_args(p, &a);
+    if (r != FLB_OK) return r;
+    if (!xi || !work) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    if (!aligned(work)) return fail(FLB_ERR_INVALID_ARG, "work must be 256-byte aligned");
+    if ((uintptr_t)xi % sizeof(double)) return fail(FLB_ERR_INVALID_ARG, "xi must be 8-byte aligned");
+    if (work_bytes < modeq_work_bytes(a.nx, a.ny))
+        return fail(FLB_ERR_INVALID_ARG, "work too small");
+    HIP_TRY(launch_modeq_noise(a, p->precision, (uint32_t)step, work, xi, (hipStream_t)stream));
+    return FLB_OK;
+}
+
+flb_status flb_modeq_step(const flb_modeq_params* p, const void* fin, void* fout, uint64_t step,
+                          void* work, size_t work_bytes, void* stream) {
+    ModEqArgs a{};
+    flb_status r = modeq_args(p, &a);
+    if (r != FLB_OK) return r;
+    if (!fin || !fout) return fail(FLB_ERR_INVALID_ARG, "NULL populations");
+    if (fin == fout) return fail(FLB_ERR_INVALID_ARG, "fin and fout must differ");
+    if (!aligned(fin) || !aligned(fout))
+        return fail(FLB_ERR_INVALID_ARG, "populations must be 256-byte aligned");
+    if ((r = modeq_work_ok(a, work, work_bytes)) != FLB_OK) return r;
+    HIP_TRY(launch_modeq_step(a, p->precision, fin, fout, (uint32_t)step, work,
+                              (hipStream_t)stream));
+    return FLB_OK;
+}
+
+flb_status flb_modeq_run(const flb_modeq_params* p, void* f, void* tmp, uint64_t step0,
+                         int32_t nsteps, void* work, size_t work_bytes, void* stream) {
+    ModEqArgs a{};
+    flb_status r = modeq_args(p, &a);
+    if (r != FLB_OK) return r;
+    if (!f || !tmp || f == tmp) return fail(FLB_ERR_INVALID_ARG, "f and tmp must be distinct");
+    if (!aligned(f) || !aligned(tmp))
+        return fail(FLB_ERR_INVALID_ARG, "populations must be 256-byte aligned");
+    if (nsteps < 0) return fail(FLB_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if ((r = modeq_work_ok(a, work, work_bytes)) != FLB_OK) return r;
+    const hipStream_t st = (hipStream_t)stream;
+    for (int32_t k = 0; k < nsteps; ++k) {
+        const void* in = (k % 2 == 0) ? f : tmp;
+        void* out = (k % 2 == 0) ? tmp : f;
+        HIP_TRY(launch_modeq_step(a, p->precision, in, out, (uint32_t)(step0 + k), work, st));
+    }
+    if (nsteps % 2) {
+        const size_t bytes = (size_t)9 * a.nx * a.ny * (p->precision == FLB_FP64 ? 8 : 4);
+        HIP_TRY(hipMemcpyAsync(f, tmp, bytes, hipMemcpyDeviceToDevice, st));
+    }
+    return FLB_OK;
+}
+
 flb_status flb_destroy(flb_handle* h) {
     if (!h) return FLB_OK;
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);

@@ -104,6 +104,22 @@ hipError_t launch_interface_heights(int prec, const void* drho, double rho0, int
                                     const InterfaceSet& set, double rho_L, double rho_V,
                                     double width, double* out, hipStream_t st);
 
+// Linearized modified-equilibrium model (modeq.hip), D2Q9.
+struct ModEqArgs {
+    int nx, ny;
+    double rho0, kT, cs2_0, kappa;
+    double rate_bulk, rate_shear, rate_ghost;
+    uint32_t k0, k1;     // Philox key
+    double amp[4];       // white-noise amplitudes of p_xx, p_xy, q_x, q_y
+};
+// Work: the two complex noise spectra (2 V double2), then the filtered
+// noise fields xi_e, xi_eps (2 V double).
+size_t modeq_work_bytes(int nx, int ny);
+hipError_t launch_modeq_noise(const ModEqArgs& a, int prec, uint32_t step, void* work,
+                              double* xi, hipStream_t st);
+hipError_t launch_modeq_step(const ModEqArgs& a, int prec, const void* fin, void* fout,
+                             uint32_t step, void* work, hipStream_t st);
+
 // Adjoint launchers (adjoint.hip).
 hipError_t launch_adjoint_seed(const StepSpec& s, const void* rhobar, void* abar, hipStream_t st);
 struct AdjointStepArgs {

@@ -1,0 +1,296 @@
+// Modified-equilibrium (Swift) fluctuating LB, linearized about rest, D2Q9
+// (Sec. IV.B, subsection on the modified-equilibrium model).
+//
+// State: the deviations delta f_i from the uniform rest state, stored
+// f[i * V + x + nx y].  One step with index n:
+//   pull       f_i(x) = S_i(x - c_i)
+//   moments    m_a = sum_i T_ai f_i                        (App. B basis)
+//   equilibrium (eq. meq-yeo, linearized)  m^eq = {rho, j_x, j_y, D, 0, 0, 0, 0, -D},
+//              D = d(k) rho = 6 (cs2_0 - cs2) rho - 6 kappa rho0 lap_h rho,
+//              i.e. d(k) = 6 (c_s^2(k) - cs2) with c_s^2(k) = cs2_0 + kappa rho0 Lambda(k),
+//              Lambda(k) = (4/3)(2 - cos kx - cos ky) + (2/3)(1 - cos kx cos ky)
+//              the symbol of -lap_h (9-point isotropic Laplacian)
+//   relax      m*_a = m_a - lam_a (m_a - m^eq_a) + xi_a
+//   back       S_{n+1,i} = w_i sum_a T_ai m*_a / N_a.
+// Noise: the covariance Xi(k) = G - C G C^T that keeps the equal-time
+// correlations of eq. f-correl-yeo stationary under the step.  p_xx, p_xy,
+// q_x, q_y get white noise rho0 kT N_a lam (2 - lam) / cs2; the (e, eps) pair
+// has the k-dependent block
+//   Xi_ee = 12 rho0 kT lam_e (2 - lam_e)(2 - 3 c2),
+//   Xi_eE = 12 rho0 kT (3 c2 - 1)(lam_e + lam_g - lam_e lam_g),
+//   Xi_EE = 12 rho0 kT lam_g (2 - lam_g)(5 - 3 c2),      c2 = c_s^2(k),
+// whose small-rate limit is eq. noise-yeo (the (e, eps) entry at half its
+// printed value: the value for which Xi is a covariance wherever the
+// equilibrium populations are non-negative).  That pair is drawn as white
+// normals z_e, z_eps (the site's Philox normals 0 and 5), transformed, mixed
+// by the lower Cholesky factor of the block at every k, and transformed back:
+//   k_meq_noise_x    normals of one row, DFT along x          (one block per row)
+//   k_meq_filter_y   DFT along y, Cholesky mix, inverse DFT   (one block per column)
+//   k_meq_noise_ix   inverse DFT along x, real part / V       (one block per row)
+// Each line sits in LDS with its twiddles; outputs are direct sums (the
+// extents are at most 1024).  Then k_meq_step applies the step.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "internal.h"
+#include "philox.h"
+
+namespace flb {
+
+namespace {
+
+constexpr int MQ_THREADS = 256;
+constexpr int MQ_MAXK = SPECTRUM_MAX_N / MQ_THREADS;   // outputs per thread and line
+constexpr int MQ_TX = 64, MQ_TY = 4;
+
+// X(k) = sum_j x(j) exp(-+ 2 pi i j k / n) (sign - forward, + inverse), from a
+// line in LDS and the forward twiddles tw[j] = exp(-2 pi i j / n).
+__device__ __forceinline__ double2 dft_at(const double2* __restrict__ buf,
+                                          const double2* __restrict__ tw, int n, int k,
+                                          bool inverse) {
+    double re = 0.0, im = 0.0;
+    int idx = 0;   // j k mod n
+    for (int j = 0; j < n; ++j) {
+        const double2 x = buf[j];
+        const double2 w = tw[idx];
+        const double wi = inverse ? -w.y : w.y;
+        re = fma(x.x, w.x, fma(-x.y, wi, re));
+        im = fma(x.x, wi, fma(x.y, w.x, im));
+        idx += k;
+        if (idx >= n) idx -= n;
+    }
+    return make_double2(re, im);
+}
+
+__device__ __forceinline__ void twiddles(double2* tw, int n) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        double s, c;
+        sincospi(2.0 * (double)j / (double)n, &s, &c);
+        tw[j] = make_double2(c, -s);
+    }
+}
+
+template <typename Real>
+__global__ __launch_bounds__(MQ_THREADS) void k_meq_noise_x(ModEqArgs a, uint32_t step,
+                                                            double2* __restrict__ W) {
+    extern __shared__ double2 lds_mq[];
+    const int n = a.nx, y = blockIdx.x;
+    const size_t V = (size_t)a.nx * a.ny;
+    double2* tw = lds_mq;
+    double2* be = lds_mq + n;
+    double2* bp = lds_mq + 2 * n;
+    twiddles(tw, n);
+    for (int x = threadIdx.x; x < n; x += blockDim.x) {
+        Real z[6];
+        site_normals<3, Real>((uint32_t)(x + n * y), step, 0u, 0u, a.k0, a.k1, z);
+        be[x] = make_double2((double)z[0], 0.0);
+        bp[x] = make_double2((double)z[5], 0.0);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        W[(size_t)y * n + k] = dft_at(be, tw, n, k, false);
+        W[V + (size_t)y * n + k] = dft_at(bp, tw, n, k, false);
+    }
+}
+
+__global__ __launch_bounds__(MQ_THREADS) void k_meq_filter_y(ModEqArgs a,
+                                                             double2* __restrict__ W) {
+    extern __shared__ double2 lds_mq[];
+    const int n = a.ny, nx = a.nx, kx = blockIdx.x;
+    const size_t V = (size_t)a.nx * a.ny;
+    double2* tw = lds_mq;
+    double2* be = lds_mq + n;
+    double2* bp = lds_mq + 2 * n;
+    twiddles(tw, n);
+    for (int y = threadIdx.x; y < n; y += blockDim.x) {
+        be[y] = W[(size_t)y * nx + kx];
+        bp[y] = W[V + (size_t)y * nx + kx];
+    }
+    __syncthreads();
+    double sx, cx;
+    sincospi(2.0 * (double)kx / (double)nx, &sx, &cx);
+    const double pre = 12.0 * a.rho0 * a.kT;
+    const double le = a.rate_bulk, lg = a.rate_ghost;
+    double2 oe[MQ_MAXK], op[MQ_MAXK];
+#pragma unroll
+    for (int r = 0; r < MQ_MAXK; ++r) {
+        const int ky = threadIdx.x + r * MQ_THREADS;
+        if (ky < n) {
+            const double2 ze = dft_at(be, tw, n, ky, false);
+            const double2 zp = dft_at(bp, tw, n, ky, false);
+            const double cy = tw[ky].x;
+            const double lap = (4.0 / 3.0) * (2.0 - cx - cy) + (2.0 / 3.0) * (1.0 - cx * cy);
+            const double c2 = a.cs2_0 + a.kappa * a.rho0 * lap;
+            const double see = pre * le * (2.0 - le) * (2.0 - 3.0 * c2);
+            const double sep = pre * (3.0 * c2 - 1.0) * (le + lg - le * lg);
+            const double spp = pre * lg * (2.0 - lg) * (5.0 - 3.0 * c2);
+            const double l11 = sqrt(fmax(see, 0.0));
+            const double l21 = l11 > 0.0 ? sep / l11 : 0.0;
+            const double l22 = sqrt(fmax(spp - l21 * l21, 0.0));
+            oe[r] = make_double2(l11 * ze.x, l11 * ze.y);
+            op[r] = make_double2(l21 * ze.x + l22 * zp.x, l21 * ze.y + l22 * zp.y);
+        }
+    }
+    __syncthreads();   // every forward sum has read be, bp
+#pragma unroll
+    for (int r = 0; r < MQ_MAXK; ++r) {
+        const int ky = threadIdx.x + r * MQ_THREADS;
+        if (ky < n) {
+            be[ky] = oe[r];
+            bp[ky] = op[r];
+        }
+    }
+    __syncthreads();
+    for (int y = threadIdx.x; y < n; y += blockDim.x) {
+        W[(size_t)y * nx + kx] = dft_at(be, tw, n, y, true);
+        W[V + (size_t)y * nx + kx] = dft_at(bp, tw, n, y, true);
+    }
+}
+
+__global__ __launch_bounds__(MQ_THREADS) void k_meq_noise_ix(ModEqArgs a,
+                                                             const double2* __restrict__ W,
+                                                             double* __restrict__ xi) {
+    extern __shared__ double2 lds_mq[];
+    const int n = a.nx, y = blockIdx.x;
+    const size_t V = (size_t)a.nx * a.ny;
+    const double inv_v = 1.0 / (double)V;
+    double2* tw = lds_mq;
+    double2* be = lds_mq + n;
+    double2* bp = lds_mq + 2 * n;
+    twiddles(tw, n);
+    for (int x = threadIdx.x; x < n; x += blockDim.x) {
+        be[x] = W[(size_t)y * n + x];
+        bp[x] = W[V + (size_t)y * n + x];
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < n; x += blockDim.x) {
+        xi[(size_t)y * n + x] = dft_at(be, tw, n, x, true).x * inv_v;
+        xi[V + (size_t)y * n + x] = dft_at(bp, tw, n, x, true).x * inv_v;
+    }
+}
+
+__device__ __forceinline__ int wrap(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(MQ_TX * MQ_TY) void k_meq_step(ModEqArgs a, Geom g,
+                                                            const Real* __restrict__ fin,
+                                                            Real* __restrict__ fout,
+                                                            uint32_t step,
+                                                            const double* __restrict__ xi) {
+    using L = Lattice<0>;
+    constexpr int SX = MQ_TX + 2, NS = SX * (MQ_TY + 2);
+    __shared__ Real rs[NS];
+    const int x0 = blockIdx.x * MQ_TX, y0 = blockIdx.y * MQ_TY;
+    // density of the pulled populations on the tile and a one-site halo
+    for (int l = threadIdx.x; l < NS; l += MQ_TX * MQ_TY) {
+        const int gx = wrap(x0 - 1 + l % SX, g.nx), gy = wrap(y0 - 1 + l / SX, g.ny);
+        Real f[L::Q];
+        pull<0, Real>(fin, gx, gy, 0, g, f);
+        Real s = Real(0);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) s += f[i];
+        rs[l] = s;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % MQ_TX, ty = threadIdx.x / MQ_TX;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= g.nx || y >= g.ny) return;
+    Real f[L::Q];
+    pull<0, Real>(fin, x, y, 0, g, f);
+    Real m[L::Q];
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        Real s = Real(0);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            if (L::T[q][i] != 0) s += Real(L::T[q][i]) * f[i];
+        m[q] = s;
+    }
+    const int c = (ty + 1) * SX + tx + 1;
+    Real lap = Real(0);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) lap += Real(L::w[i]) * (rs[c + L::cy[i] * SX + L::cx[i]] - rs[c]);
+    lap *= Real(6);
+    const Real D = Real(6.0 * (a.cs2_0 - 1.0 / 3.0)) * m[0] - Real(6.0 * a.kappa * a.rho0) * lap;
+    const Real le = Real(a.rate_bulk), ls = Real(a.rate_shear), lg = Real(a.rate_ghost);
+    m[3] -= le * (m[3] - D);
+    m[4] -= ls * m[4];
+    m[5] -= ls * m[5];
+    m[6] -= lg * m[6];
+    m[7] -= lg * m[7];
+    m[8] -= lg * (m[8] + D);
+    const uint32_t site = (uint32_t)(x + g.nx * y);
+    if (xi) {
+        Real z[6];
+        site_normals<3, Real>(site, step, 0u, 0u, a.k0, a.k1, z);
+        m[3] += Real(xi[site]);
+        m[4] += Real(a.amp[0]) * z[1];
+        m[5] += Real(a.amp[1]) * z[2];
+        m[6] += Real(a.amp[2]) * z[3];
+        m[7] += Real(a.amp[3]) * z[4];
+        m[8] += Real(xi[g.V + site]);
+    }
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        Real s = Real(0);
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q)
+            if (L::T[q][i] != 0) s += Real(L::T[q][i] / L::N[q]) * m[q];
+        plane_st(fout + (size_t)i * g.V, site, Real(L::w[i]) * s);
+    }
+}
+
+}  // namespace
+
+size_t modeq_work_bytes(int nx, int ny) {
+    const size_t V = (size_t)nx * ny;
+    return 2 * V * sizeof(double2) + 2 * V * sizeof(double);
+}
+
+hipError_t launch_modeq_noise(const ModEqArgs& a, int prec, uint32_t step, void* work,
+                              double* xi, hipStream_t st) {
+    double2* W = (double2*)work;
+    const size_t lx = 3 * (size_t)a.nx * sizeof(double2), ly = 3 * (size_t)a.ny * sizeof(double2);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_meq_noise_x<float>, dim3(a.ny), dim3(MQ_THREADS), lx, st, a, step, W);
+    else
+        hipLaunchKernelGGL(k_meq_noise_x<double>, dim3(a.ny), dim3(MQ_THREADS), lx, st, a, step, W);
+    hipLaunchKernelGGL(k_meq_filter_y, dim3(a.nx), dim3(MQ_THREADS), ly, st, a, W);
+    hipLaunchKernelGGL(k_meq_noise_ix, dim3(a.ny), dim3(MQ_THREADS), lx, st, a,
+                       (const double2*)W, xi);
+    return hipGetLastError();
+}
+
+hipError_t launch_modeq_step(const ModEqArgs& a, int prec, const void* fin, void* fout,
+                             uint32_t step, void* work, hipStream_t st) {
+    const size_t V = (size_t)a.nx * a.ny;
+    double* xi = nullptr;
+    if (a.kT > 0.0) {
+        xi = (double*)((char*)work + 2 * V * sizeof(double2));
+        const hipError_t e = launch_modeq_noise(a, prec, step, work, xi, st);
+        if (e != hipSuccess) return e;
+    }
+    Geom g{};
+    g.nx = a.nx;
+    g.ny = a.ny;
+    g.nz = 1;
+    g.nbx = (a.nx + MQ_TX - 1) / MQ_TX;
+    g.nby = (a.ny + MQ_TY - 1) / MQ_TY;
+    g.nbz = 1;
+    g.nblocks = (uint32_t)(g.nbx * g.nby);
+    g.V = (uint32_t)V;
+    g.zc = 0;
+    const dim3 grid((unsigned)g.nbx, (unsigned)g.nby);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_meq_step<float>, grid, dim3(MQ_TX * MQ_TY), 0, st, a, g,
+                           (const float*)fin, (float*)fout, step, xi);
+    else
+        hipLaunchKernelGGL(k_meq_step<double>, grid, dim3(MQ_TX * MQ_TY), 0, st, a, g,
+                           (const double*)fin, (double*)fout, step, xi);
+    return hipGetLastError();
+}
+
+}  // namespace flb

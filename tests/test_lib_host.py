@@ -116,3 +116,21 @@ def test_capillary_theory_equals_oracle():
     np.testing.assert_allclose(C.stripe(p, 10.0, 30.0, 1.0, 0.5, w),
                                W.stripe_drho(p.shape, 10.0, 30.0, 1.0, 0.5, w, p.rho0),
                                atol=1e-15)
+
+
+def test_modeq_validation_and_sizes():
+    """flb_modeq_work_bytes: 48 V bytes; invalid extents, rates, kT, c_s^2(k)
+    above 0.6 and rates that leave the (e, eps) covariance indefinite are
+    rejected on the host."""
+    from paper_1012_3632_amd._lib import FLBError
+    from paper_1012_3632_amd.modeq import ModEqParams, paper_params, work_bytes
+    ok = ModEqParams(nx=8, ny=8, kT=1e-5, cs2_0=0.07, kappa=0.08, rate_bulk=1.2, rate_shear=1.6,
+                     rate_ghost=0.9)
+    assert work_bytes(ok) == 48 * 64
+    assert work_bytes(paper_params()) == 48 * 128 * 128
+    bad = [ok.with_(nx=1025), ok.with_(ny=0), ok.with_(rate_shear=2.0), ok.with_(kT=-1.0),
+           ok.with_(cs2_0=0.0), ok.with_(kappa=0.2),
+           ok.with_(cs2_0=0.55, kappa=0.0, rate_bulk=1.0, rate_ghost=1.9)]
+    for p in bad:
+        with pytest.raises(FLBError):
+            work_bytes(p)
