@@ -321,6 +321,35 @@ def extras(args, stream):
         "momentum_max_dev_k_lt_2.5": round(dev(range(1, 3)), 4),
         "nonconserved_max_dev_k_lt_2.5": round(dev(range(3, 9)), 4)}
 
+    # the modified-equilibrium (Swift) model at the same parameters (Sec. IV.B)
+    from paper_1012_3632_amd import modeq as MQ
+    wl = W.MODEQ_WORKLOADS["d2q9_128_modeq"]
+    pm = MQ.ModEqParams(**W.modeq_params_of("d2q9_128_modeq"))
+    sm = MQ.ModEq(pm)
+    with torch.cuda.stream(stream):
+        sm.step(200, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        nms = 2000
+        e0.record(stream)
+        sm.step(nms, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+    ms_step = e0.elapsed_time(e1) / nms
+    del sm
+    t0 = time.perf_counter()
+    spec_m, sm = MQ.run_spectra(pm, wl["burn_in"], wl["snapshots"], wl["interval"], stream=stream)
+    run_s = time.perf_counter() - t0
+    Vm = pm.nx * pm.ny
+    rm = spec_m.cpu().numpy() / (wl["snapshots"] * Vm * MQ.equal_time_variances(pm))
+    rm[:, 0, 0] = np.nan
+    res["d2q9_128_modeq"] = {
+        "ms_per_step": round(ms_step, 5), "MLUPS": round(Vm / (ms_step * 1e-3) / 1e6, 1),
+        "run_s": round(run_s, 3), "steps": wl["burn_in"] + wl["snapshots"] * wl["interval"],
+        "snapshots": wl["snapshots"],
+        "ratio_to_G_by_mode": [round(float(x), 4) for x in np.nanmean(rm.reshape(9, -1), 1)]}
+    del sm, spec_m
+
     # the capillary-fluctuation test of Sec. VI: 1024 x 400 stripe, 10^6 steps
     from paper_1012_3632_amd import capillary as CAP
     from paper_1012_3632_amd import field_spectrum

@@ -27,8 +27,11 @@
 //   k_meq_noise_x    normals of one row, DFT along x          (one block per row)
 //   k_meq_filter_y   DFT along y, Cholesky mix, inverse DFT   (one block per column)
 //   k_meq_noise_ix   inverse DFT along x, real part / V       (one block per row)
-// Each line sits in LDS with its twiddles; outputs are direct sums (the
-// extents are at most 1024).  Then k_meq_step applies the step.
+// Each line sits in LDS with its twiddles.  Power-of-two extents use an
+// in-place radix-2 FFT (input in bit-reversed order, log2 n butterfly stages
+// with a barrier each, the e and eps lines of a block sharing the stages);
+// other extents (at most 1024) use direct sums.  Then k_meq_step applies the
+// step.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -70,6 +73,41 @@ __device__ __forceinline__ void twiddles(double2* tw, int n) {
     }
 }
 
+__device__ __forceinline__ bool pow2(int n) { return (n & (n - 1)) == 0; }
+
+__device__ __forceinline__ int log2i(int n) { return 31 - __clz(n); }
+
+// Position of element j in the bit-reversed order of a 2^logn line.
+__device__ __forceinline__ int brev(int j, int logn) {
+    return logn == 0 ? 0 : (int)(__brev((unsigned)j) >> (32 - logn));
+}
+
+// In place, the two lines b[0 .. n) and b[n .. 2n) (n = 2^logn), each loaded
+// in bit-reversed order, become their transforms in natural order
+// (exp(-+ 2 pi i j k / n), sign - forward, + inverse).  Ends with a barrier.
+__device__ __forceinline__ void fft2_lines(double2* b, const double2* __restrict__ tw, int n,
+                                           int logn, bool inverse) {
+    const int nh = n >> 1;
+    for (int s = 1; s <= logn; ++s) {
+        const int half = 1 << (s - 1);
+        const int step = n >> s;   // exp(-2 pi i pos / 2 half) = tw[pos * step]
+        for (int t = threadIdx.x; t < 2 * nh; t += blockDim.x) {
+            const int f = t >= nh ? 1 : 0;
+            const int bt = t - f * nh;
+            const int pos = bt & (half - 1);
+            const int i0 = f * n + ((bt >> (s - 1)) << s) + pos;
+            const int i1 = i0 + half;
+            const double2 w = tw[pos * step];
+            const double wi = inverse ? -w.y : w.y;
+            const double2 u = b[i0], x = b[i1];
+            const double vr = x.x * w.x - x.y * wi, vi = x.x * wi + x.y * w.x;
+            b[i0] = make_double2(u.x + vr, u.y + vi);
+            b[i1] = make_double2(u.x - vr, u.y - vi);
+        }
+        __syncthreads();
+    }
+}
+
 template <typename Real>
 __global__ __launch_bounds__(MQ_THREADS) void k_meq_noise_x(ModEqArgs a, uint32_t step,
                                                             double2* __restrict__ W) {
@@ -79,14 +117,25 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_noise_x(ModEqArgs a, uint32_
     double2* tw = lds_mq;
     double2* be = lds_mq + n;
     double2* bp = lds_mq + 2 * n;
+    const bool fft = pow2(n);
+    const int logn = log2i(n);
     twiddles(tw, n);
     for (int x = threadIdx.x; x < n; x += blockDim.x) {
         Real z[6];
         site_normals<3, Real>((uint32_t)(x + n * y), step, 0u, 0u, a.k0, a.k1, z);
-        be[x] = make_double2((double)z[0], 0.0);
-        bp[x] = make_double2((double)z[5], 0.0);
+        const int j = fft ? brev(x, logn) : x;
+        be[j] = make_double2((double)z[0], 0.0);
+        bp[j] = make_double2((double)z[5], 0.0);
     }
     __syncthreads();
+    if (fft) {
+        fft2_lines(be, tw, n, logn, false);
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            W[(size_t)y * n + k] = be[k];
+            W[V + (size_t)y * n + k] = bp[k];
+        }
+        return;
+    }
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
         W[(size_t)y * n + k] = dft_at(be, tw, n, k, false);
         W[V + (size_t)y * n + k] = dft_at(bp, tw, n, k, false);
@@ -101,12 +150,16 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_filter_y(ModEqArgs a,
     double2* tw = lds_mq;
     double2* be = lds_mq + n;
     double2* bp = lds_mq + 2 * n;
+    const bool fft = pow2(n);
+    const int logn = log2i(n);
     twiddles(tw, n);
     for (int y = threadIdx.x; y < n; y += blockDim.x) {
-        be[y] = W[(size_t)y * nx + kx];
-        bp[y] = W[V + (size_t)y * nx + kx];
+        const int j = fft ? brev(y, logn) : y;
+        be[j] = W[(size_t)y * nx + kx];
+        bp[j] = W[V + (size_t)y * nx + kx];
     }
     __syncthreads();
+    if (fft) fft2_lines(be, tw, n, logn, false);
     double sx, cx;
     sincospi(2.0 * (double)kx / (double)nx, &sx, &cx);
     const double pre = 12.0 * a.rho0 * a.kT;
@@ -116,8 +169,8 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_filter_y(ModEqArgs a,
     for (int r = 0; r < MQ_MAXK; ++r) {
         const int ky = threadIdx.x + r * MQ_THREADS;
         if (ky < n) {
-            const double2 ze = dft_at(be, tw, n, ky, false);
-            const double2 zp = dft_at(bp, tw, n, ky, false);
+            const double2 ze = fft ? be[ky] : dft_at(be, tw, n, ky, false);
+            const double2 zp = fft ? bp[ky] : dft_at(bp, tw, n, ky, false);
             const double cy = tw[ky].x;
             const double lap = (4.0 / 3.0) * (2.0 - cx - cy) + (2.0 / 3.0) * (1.0 - cx * cy);
             const double c2 = a.cs2_0 + a.kappa * a.rho0 * lap;
@@ -131,16 +184,25 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_filter_y(ModEqArgs a,
             op[r] = make_double2(l21 * ze.x + l22 * zp.x, l21 * ze.y + l22 * zp.y);
         }
     }
-    __syncthreads();   // every forward sum has read be, bp
+    __syncthreads();   // every forward value has been read from be, bp
 #pragma unroll
     for (int r = 0; r < MQ_MAXK; ++r) {
         const int ky = threadIdx.x + r * MQ_THREADS;
         if (ky < n) {
-            be[ky] = oe[r];
-            bp[ky] = op[r];
+            const int j = fft ? brev(ky, logn) : ky;
+            be[j] = oe[r];
+            bp[j] = op[r];
         }
     }
     __syncthreads();
+    if (fft) {
+        fft2_lines(be, tw, n, logn, true);
+        for (int y = threadIdx.x; y < n; y += blockDim.x) {
+            W[(size_t)y * nx + kx] = be[y];
+            W[V + (size_t)y * nx + kx] = bp[y];
+        }
+        return;
+    }
     for (int y = threadIdx.x; y < n; y += blockDim.x) {
         W[(size_t)y * nx + kx] = dft_at(be, tw, n, y, true);
         W[V + (size_t)y * nx + kx] = dft_at(bp, tw, n, y, true);
@@ -157,12 +219,23 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_noise_ix(ModEqArgs a,
     double2* tw = lds_mq;
     double2* be = lds_mq + n;
     double2* bp = lds_mq + 2 * n;
+    const bool fft = pow2(n);
+    const int logn = log2i(n);
     twiddles(tw, n);
     for (int x = threadIdx.x; x < n; x += blockDim.x) {
-        be[x] = W[(size_t)y * n + x];
-        bp[x] = W[V + (size_t)y * n + x];
+        const int j = fft ? brev(x, logn) : x;
+        be[j] = W[(size_t)y * n + x];
+        bp[j] = W[V + (size_t)y * n + x];
     }
     __syncthreads();
+    if (fft) {
+        fft2_lines(be, tw, n, logn, true);
+        for (int x = threadIdx.x; x < n; x += blockDim.x) {
+            xi[(size_t)y * n + x] = be[x].x * inv_v;
+            xi[V + (size_t)y * n + x] = bp[x].x * inv_v;
+        }
+        return;
+    }
     for (int x = threadIdx.x; x < n; x += blockDim.x) {
         xi[(size_t)y * n + x] = dft_at(be, tw, n, x, true).x * inv_v;
         xi[V + (size_t)y * n + x] = dft_at(bp, tw, n, x, true).x * inv_v;

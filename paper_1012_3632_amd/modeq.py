@@ -97,3 +97,47 @@ class ModEq:
         call("flb_modeq_noise", C.byref(self.c), int(n), _ptr(out), _ptr(self.work),
              int(self.nbytes), _stream(stream))
         return out
+
+
+def equal_time_variances(p):
+    """G_aa(k) of eq. f-correl-yeo projected as in eq. g-correl, in closed
+    form for the D2Q9 basis: (9, ny, nx) float64 numpy.  With c2 = c_s^2(k):
+    rho kT / c2, rho kT (j_x, j_y), 4 rho kT / c2 (e), 4/3, 1/3 rho kT (p_xx,
+    p_xy), 2 rho kT (q_x, q_y), 4 rho kT (9 c2 + 1) / c2 (eps)."""
+    import numpy as np
+    kx = 2 * np.pi * np.arange(p.nx) / p.nx
+    ky = 2 * np.pi * np.arange(p.ny) / p.ny
+    cx, cy = np.cos(kx)[None, :], np.cos(ky)[:, None]
+    lap = (4.0 / 3.0) * (2.0 - cx - cy) + (2.0 / 3.0) * (1.0 - cx * cy)
+    c2 = p.cs2_0 + p.kappa * p.rho0 * lap
+    g = p.rho0 * p.kT
+    one = np.ones_like(c2)
+    return np.stack([g / c2, g * one, g * one, 4 * g / c2, 4 / 3 * g * one, g / 3 * one,
+                     2 * g * one, 2 * g * one, 4 * g * (9 * c2 + 1) / c2])
+
+
+def run_spectra(p, burn_in, snapshots, interval, stream=None):
+    """From rest: burn_in steps, then ``snapshots`` snapshots ``interval``
+    steps apart, each adding |m_a(k)|^2 of the pulled moments (the
+    equilibration measure of Sec. VI) to a (9, ny, nx) FP64 sum.  The snapshot
+    projection onto the moments is a torch contraction; the transforms are
+    the library's field spectra.  Returns (spectrum sum, the ModEq)."""
+    from .sim import field_spectrum, lattice_tables
+    t = lattice_tables("D2Q9")
+    T = torch.as_tensor(t["T"], dtype=torch.float64, device="cuda")
+    c = t["c"]
+    sim = ModEq(p)
+    spec = torch.zeros((9, 1, p.ny, p.nx), dtype=torch.float64, device="cuda")
+    work = torch.empty(16 * spec.numel(), dtype=torch.uint8, device="cuda")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(s):
+        sim.step(burn_in, stream=s)
+        for _ in range(snapshots):
+            sim.step(interval, stream=s)
+            f = sim.f.double()
+            fp = torch.stack([torch.roll(f[i], (int(c[i, 1]), int(c[i, 0])), (0, 1))
+                              for i in range(9)])
+            m = torch.tensordot(T, fp, dims=([1], [0])).reshape(9, 1, p.ny, p.nx)
+            field_spectrum(m, spec, work=work, stream=s)
+    s.synchronize()
+    return spec.reshape(9, p.ny, p.nx), sim
