@@ -240,8 +240,9 @@ typedef struct flb_modeq_params {
     uint64_t seed;        /* Philox key                                                 */
 } flb_modeq_params;
 
-/* Device work bytes of flb_modeq_step / _run / _noise: 48 V (the complex
- * noise spectra, then the filtered fields).  Rejects invalid parameters
+/* Minimum device work bytes of flb_modeq_step / _run / _noise: 48 V per
+ * step of a noise batch (the complex noise spectra, then the filtered
+ * fields).  Rejects invalid parameters
  * (FLB_ERR_INVALID_ARG), including rates for which the (e, eps) covariance
  * is not positive semidefinite somewhere on [cs2_0, cs2_0 + kappa rho0 16/3]. */
 flb_status flb_modeq_work_bytes(const flb_modeq_params* p, size_t* bytes);
@@ -254,7 +255,10 @@ flb_status flb_modeq_step(const flb_modeq_params* p, const void* fin, void* fout
                           void* work, size_t work_bytes, void* stream);
 
 /* nsteps steps with indices step0 .. step0 + nsteps - 1; the result is in f,
- * tmp (device, 9 V reals) is overwritten. */
+ * tmp (device, 9 V reals) is overwritten.  The noise of consecutive steps is
+ * drawn and filtered in batches of b = min(16, work_bytes / (48 V)) steps
+ * (one launch set per batch; a larger work buffer fills more of the chip at
+ * small lattices).  The result does not depend on b. */
 flb_status flb_modeq_run(const flb_modeq_params* p, void* f, void* tmp, uint64_t step0,
                          int32_t nsteps, void* work, size_t work_bytes, void* stream);
 

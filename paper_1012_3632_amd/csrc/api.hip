@@ -978,7 +978,7 @@ flb_status flb_modeq_noise(const flb_modeq_params* p, uint64_t step, double* xi,
     if ((uintptr_t)xi % sizeof(double)) return fail(FLB_ERR_INVALID_ARG, "xi must be 8-byte aligned");
     if (work_bytes < modeq_work_bytes(a.nx, a.ny))
         return fail(FLB_ERR_INVALID_ARG, "work too small");
-    HIP_TRY(launch_modeq_noise(a, p->precision, (uint32_t)step, work, xi, (hipStream_t)stream));
+    HIP_TRY(launch_modeq_noise(a, p->precision, (uint32_t)step, 1, work, xi, (hipStream_t)stream));
     return FLB_OK;
 }
 
@@ -992,8 +992,14 @@ flb_status flb_modeq_step(const flb_modeq_params* p, const void* fin, void* fout
     if (!aligned(fin) || !aligned(fout))
         return fail(FLB_ERR_INVALID_ARG, "populations must be 256-byte aligned");
     if ((r = modeq_work_ok(a, work, work_bytes)) != FLB_OK) return r;
-    HIP_TRY(launch_modeq_step(a, p->precision, fin, fout, (uint32_t)step, work,
-                              (hipStream_t)stream));
+    const hipStream_t st = (hipStream_t)stream;
+    const size_t V = (size_t)a.nx * a.ny;
+    double* xi = nullptr;
+    if (a.kT > 0.0) {
+        xi = (double*)((char*)work + 2 * V * sizeof(double2));
+        HIP_TRY(launch_modeq_noise(a, p->precision, (uint32_t)step, 1, work, xi, st));
+    }
+    HIP_TRY(launch_modeq_step(a, p->precision, fin, fout, (uint32_t)step, xi, st));
     return FLB_OK;
 }
 
@@ -1008,10 +1014,24 @@ flb_status flb_modeq_run(const flb_modeq_params* p, void* f, void* tmp, uint64_t
     if (nsteps < 0) return fail(FLB_ERR_INVALID_ARG, "nsteps must be >= 0");
     if ((r = modeq_work_ok(a, work, work_bytes)) != FLB_OK) return r;
     const hipStream_t st = (hipStream_t)stream;
-    for (int32_t k = 0; k < nsteps; ++k) {
-        const void* in = (k % 2 == 0) ? f : tmp;
-        void* out = (k % 2 == 0) ? tmp : f;
-        HIP_TRY(launch_modeq_step(a, p->precision, in, out, (uint32_t)(step0 + k), work, st));
+    const size_t V = (size_t)a.nx * a.ny;
+    // noise batches of up to MODEQ_MAX_BATCH steps, as many as work holds
+    size_t fit = a.kT > 0.0 ? work_bytes / modeq_work_bytes(a.nx, a.ny) : 1;
+    const int nb_max = (int)(fit < (size_t)MODEQ_MAX_BATCH ? fit : MODEQ_MAX_BATCH);
+    for (int32_t k0 = 0; k0 < nsteps; k0 += nb_max) {
+        const int nb = nsteps - k0 < nb_max ? nsteps - k0 : nb_max;
+        double* xi = nullptr;
+        if (a.kT > 0.0) {
+            xi = (double*)((char*)work + (size_t)nb * 2 * V * sizeof(double2));
+            HIP_TRY(launch_modeq_noise(a, p->precision, (uint32_t)(step0 + k0), nb, work, xi, st));
+        }
+        for (int b = 0; b < nb; ++b) {
+            const int32_t k = k0 + b;
+            const void* in = (k % 2 == 0) ? f : tmp;
+            void* out = (k % 2 == 0) ? tmp : f;
+            HIP_TRY(launch_modeq_step(a, p->precision, in, out, (uint32_t)(step0 + k),
+                                      xi ? xi + (size_t)b * 2 * V : nullptr, st));
+        }
     }
     if (nsteps % 2) {
         const size_t bytes = (size_t)9 * a.nx * a.ny * (p->precision == FLB_FP64 ? 8 : 4);

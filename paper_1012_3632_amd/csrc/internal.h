@@ -112,13 +112,17 @@ struct ModEqArgs {
     uint32_t k0, k1;     // Philox key
     double amp[4];       // white-noise amplitudes of p_xx, p_xy, q_x, q_y
 };
-// Work: the two complex noise spectra (2 V double2), then the filtered
-// noise fields xi_e, xi_eps (2 V double).
+// Work per step of a noise batch: the two complex noise spectra (2 V
+// double2) and the filtered noise fields xi_e, xi_eps (2 V double).
+constexpr int MODEQ_MAX_BATCH = 16;
 size_t modeq_work_bytes(int nx, int ny);
-hipError_t launch_modeq_noise(const ModEqArgs& a, int prec, uint32_t step, void* work,
+// The noise of steps step0 .. step0 + nb - 1: spectra of step b at
+// W + 2 V b (double2), filtered fields at xi + 2 V b.
+hipError_t launch_modeq_noise(const ModEqArgs& a, int prec, uint32_t step0, int nb, void* W,
                               double* xi, hipStream_t st);
+// One step; xi = that step's filtered fields, or null for kT = 0.
 hipError_t launch_modeq_step(const ModEqArgs& a, int prec, const void* fin, void* fout,
-                             uint32_t step, void* work, hipStream_t st);
+                             uint32_t step, const double* xi, hipStream_t st);
 
 // Adjoint launchers (adjoint.hip).
 hipError_t launch_adjoint_seed(const StepSpec& s, const void* rhobar, void* abar, hipStream_t st);

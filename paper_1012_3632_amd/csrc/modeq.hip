@@ -27,6 +27,10 @@
 //   k_meq_noise_x    normals of one row, DFT along x          (one block per row)
 //   k_meq_filter_y   DFT along y, Cholesky mix, inverse DFT   (one block per column)
 //   k_meq_noise_ix   inverse DFT along x, real part / V       (one block per row)
+// The noise does not depend on the state, so a launch of these three
+// kernels draws and filters the noise of a batch of consecutive steps
+// (blockIdx.y = step within the batch): at small lattices a single step's
+// lines are far fewer blocks than the chip has CUs.
 // Each line sits in LDS with its twiddles.  Power-of-two extents use an
 // in-place radix-2 FFT (input in bit-reversed order, log2 n butterfly stages
 // with a barrier each, the e and eps lines of a block sharing the stages);
@@ -109,11 +113,13 @@ __device__ __forceinline__ void fft2_lines(double2* b, const double2* __restrict
 }
 
 template <typename Real>
-__global__ __launch_bounds__(MQ_THREADS) void k_meq_noise_x(ModEqArgs a, uint32_t step,
+__global__ __launch_bounds__(MQ_THREADS) void k_meq_noise_x(ModEqArgs a, uint32_t step0,
                                                             double2* __restrict__ W) {
     extern __shared__ double2 lds_mq[];
     const int n = a.nx, y = blockIdx.x;
     const size_t V = (size_t)a.nx * a.ny;
+    const uint32_t step = step0 + blockIdx.y;
+    W += (size_t)blockIdx.y * 2 * V;
     double2* tw = lds_mq;
     double2* be = lds_mq + n;
     double2* bp = lds_mq + 2 * n;
@@ -147,6 +153,7 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_filter_y(ModEqArgs a,
     extern __shared__ double2 lds_mq[];
     const int n = a.ny, nx = a.nx, kx = blockIdx.x;
     const size_t V = (size_t)a.nx * a.ny;
+    W += (size_t)blockIdx.y * 2 * V;
     double2* tw = lds_mq;
     double2* be = lds_mq + n;
     double2* bp = lds_mq + 2 * n;
@@ -216,6 +223,8 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_noise_ix(ModEqArgs a,
     const int n = a.nx, y = blockIdx.x;
     const size_t V = (size_t)a.nx * a.ny;
     const double inv_v = 1.0 / (double)V;
+    W += (size_t)blockIdx.y * 2 * V;
+    xi += (size_t)blockIdx.y * 2 * V;
     double2* tw = lds_mq;
     double2* be = lds_mq + n;
     double2* bp = lds_mq + 2 * n;
@@ -323,29 +332,23 @@ size_t modeq_work_bytes(int nx, int ny) {
     return 2 * V * sizeof(double2) + 2 * V * sizeof(double);
 }
 
-hipError_t launch_modeq_noise(const ModEqArgs& a, int prec, uint32_t step, void* work,
+hipError_t launch_modeq_noise(const ModEqArgs& a, int prec, uint32_t step0, int nb, void* W,
                               double* xi, hipStream_t st) {
-    double2* W = (double2*)work;
+    double2* Wc = (double2*)W;
     const size_t lx = 3 * (size_t)a.nx * sizeof(double2), ly = 3 * (size_t)a.ny * sizeof(double2);
+    const dim3 gx((unsigned)a.ny, (unsigned)nb), gy((unsigned)a.nx, (unsigned)nb);
     if (prec == 0)
-        hipLaunchKernelGGL(k_meq_noise_x<float>, dim3(a.ny), dim3(MQ_THREADS), lx, st, a, step, W);
+        hipLaunchKernelGGL(k_meq_noise_x<float>, gx, dim3(MQ_THREADS), lx, st, a, step0, Wc);
     else
-        hipLaunchKernelGGL(k_meq_noise_x<double>, dim3(a.ny), dim3(MQ_THREADS), lx, st, a, step, W);
-    hipLaunchKernelGGL(k_meq_filter_y, dim3(a.nx), dim3(MQ_THREADS), ly, st, a, W);
-    hipLaunchKernelGGL(k_meq_noise_ix, dim3(a.ny), dim3(MQ_THREADS), lx, st, a,
-                       (const double2*)W, xi);
+        hipLaunchKernelGGL(k_meq_noise_x<double>, gx, dim3(MQ_THREADS), lx, st, a, step0, Wc);
+    hipLaunchKernelGGL(k_meq_filter_y, gy, dim3(MQ_THREADS), ly, st, a, Wc);
+    hipLaunchKernelGGL(k_meq_noise_ix, gx, dim3(MQ_THREADS), lx, st, a, (const double2*)Wc, xi);
     return hipGetLastError();
 }
 
 hipError_t launch_modeq_step(const ModEqArgs& a, int prec, const void* fin, void* fout,
-                             uint32_t step, void* work, hipStream_t st) {
+                             uint32_t step, const double* xi, hipStream_t st) {
     const size_t V = (size_t)a.nx * a.ny;
-    double* xi = nullptr;
-    if (a.kT > 0.0) {
-        xi = (double*)((char*)work + 2 * V * sizeof(double2));
-        const hipError_t e = launch_modeq_noise(a, prec, step, work, xi, st);
-        if (e != hipSuccess) return e;
-    }
     Geom g{};
     g.nx = a.nx;
     g.ny = a.ny;

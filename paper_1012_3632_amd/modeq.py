@@ -70,14 +70,16 @@ class ModEq:
     """Two population buffers (9, ny, nx) of the deviations from rest, and
     the noise work space, on the current device."""
 
-    def __init__(self, p, f0=None, device="cuda"):
+    def __init__(self, p, f0=None, device="cuda", batch=16):
+        """``batch``: steps whose noise ``step`` draws and filters together
+        (the work buffer holds that many; results do not depend on it)."""
         self.p = p
         self.c = p.to_c()
         self.f = torch.zeros((9, p.ny, p.nx), dtype=p.dtype, device=device)
         if f0 is not None:
             self.f.copy_(torch.as_tensor(f0).reshape(9, p.ny, p.nx))
         self.tmp = torch.empty_like(self.f)
-        self.nbytes = work_bytes(p)
+        self.nbytes = work_bytes(p) * max(1, int(batch))
         self.work = torch.empty(max(self.nbytes, 1), dtype=torch.uint8, device=device)
         self.n = 0
 

@@ -64,6 +64,28 @@ def test_steps_match_oracle(prec, shape):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_noise_batch_does_not_change_the_run(prec):
+    """Runs whose noise is drawn in batches of 1, 5 and 16 steps are
+    bit-identical, and equal to single flb_modeq_step calls."""
+    from paper_1012_3632_amd.modeq import ModEq
+    pg, _ = _pair(prec, 48, 20)
+    f0 = W.random_populations(9, (20, 48), 17, 1e-3)
+    out = []
+    for batch in (1, 5, 16):
+        sim = ModEq(pg, f0=f0, batch=batch)
+        sim.step(23)
+        out.append(sim.f.clone())
+    sim = ModEq(pg, f0=f0, batch=1)
+    a, b = sim.f.clone(), torch.empty_like(sim.f)
+    for n in range(23):
+        sim.step_into(a, b, n)
+        a, b = b, a
+    out.append(a)
+    for o in out[1:]:
+        assert torch.equal(o, out[0])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_deterministic_step_matches_oracle(prec):
     from oracle import modeq as OM
     from paper_1012_3632_amd.modeq import ModEq
