@@ -110,10 +110,8 @@ __device__ __forceinline__ void store_rows(Real* f, int x, int y, int z, const G
     for (int i = 0; i < L::Q; ++i) plane_st(f + ((size_t)i * g.V + row), (uint32_t)x, v[i]);
 }
 
-// Row sums with DPP lane shifts (no LDS traffic): four row_shr steps leave the
-// sum of each 16-lane row in its lane 15.  Out-of-row source lanes read 0 (old
-// operand 0).  Stage-outer over NV independent values, so consecutive DPP reads
-// never depend on the instruction just before them.  Fixed order.
+// A DPP lane move within 16-lane rows (pattern CTRL; a source outside the
+// row would read 0, the old operand).
 template <int CTRL>
 __device__ __forceinline__ float dpp_shift(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
@@ -126,33 +124,55 @@ __device__ __forceinline__ double dpp_shift(double v) {
     return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
-template <int NV, typename Acc>
-__device__ __forceinline__ void row_sums_to_lane15(Acc (&v)[NV]) {
+// One butterfly stage of a 16-lane row reduction of N values per lane: the
+// lane pairs given by the DPP pattern CTRL (partners differ in lane bit
+// `hi`'s position and hold the same value indices) swap halves of their
+// lists, so each lane keeps H = ceil(N/2) partial sums: of its lower half
+// (hi = 0) or of its upper half (hi = 1, padded with a zero when N is odd).
+// base and len track the original index of the lane's first entry and how
+// many of its entries are real.
+template <int CTRL, int N, int H, typename Acc>
+__device__ __forceinline__ void row_fold(const Acc (&v)[N], Acc (&o)[H], int hi, int& base,
+                                         int& len) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x111>(v[k]);   // row_shr:1
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x112>(v[k]);   // row_shr:2
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x114>(v[k]);   // row_shr:4
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += dpp_shift<0x118>(v[k]);   // row_shr:8
+    for (int k = 0; k < H; ++k) {
+        const Acc lo_v = v[k];
+        const Acc hi_v = (k + H < N) ? v[k + H] : Acc(0);
+        const Acc keep = hi ? hi_v : lo_v;
+        const Acc send = hi ? lo_v : hi_v;
+        o[k] = keep + dpp_shift<CTRL>(send);
+    }
+    if (hi) {
+        base += H;
+        len = len > H ? len - H : 0;
+    } else {
+        len = len < H ? len : H;
+    }
 }
 
 // Block reductions in two phases, in a fixed order.  Phase 1 (rows_to_lds):
-// 16-lane row sums by DPP, then lane 15 of every row stores its NV sums in
-// FP64 to its own LDS row; no barrier.  Phase 2 (lds_rows_finish): a barrier,
-// then thread k < NV sums the rows and adds (ADD) or stores its value at
-// out[k * stride].  lds holds 4 * NW * NV doubles (NW wavefronts).  All lanes
-// must be active in phase 1 (the DPP reads neighbouring lanes).
+// 16-lane row sums of NV values by four DPP butterfly stages (row_ror:8,
+// row_half_mirror, quad_perm [2,3,0,1], quad_perm [1,0,3,2]); partners swap
+// halves of their lists, so the row's 16 lanes end holding its NV sums
+// between them, and every lane stores its sums in FP64 to its row's LDS
+// slots; no barrier.  Phase 2 (lds_rows_finish): a barrier, then thread
+// k < NV sums the rows and adds (ADD) or stores its value at out[k * stride].
+// lds holds 4 * NW * NV doubles (NW wavefronts).  All lanes must be active in
+// phase 1 (the DPP reads neighbouring lanes).
 template <int NV, typename Acc>
 __device__ __forceinline__ void rows_to_lds(Acc (&v)[NV], double* lds) {
     const int lane = threadIdx.x & 63;
     const int row = threadIdx.x >> 4;
-    row_sums_to_lane15<NV, Acc>(v);
-    if ((lane & 15) == 15) {
+    constexpr int H1 = (NV + 1) / 2, H2 = (H1 + 1) / 2, H3 = (H2 + 1) / 2, H4 = (H3 + 1) / 2;
+    Acc a1[H1], a2[H2], a3[H3], a4[H4];
+    int base = 0, len = NV;
+    row_fold<0x128, NV, H1, Acc>(v, a1, (lane >> 3) & 1, base, len);    // row_ror:8
+    row_fold<0x141, H1, H2, Acc>(a1, a2, (lane >> 2) & 1, base, len);   // row_half_mirror
+    row_fold<0x4E, H2, H3, Acc>(a2, a3, (lane >> 1) & 1, base, len);    // quad_perm 2,3,0,1
+    row_fold<0xB1, H3, H4, Acc>(a3, a4, lane & 1, base, len);           // quad_perm 1,0,3,2
 #pragma unroll
-        for (int k = 0; k < NV; ++k) lds[row * NV + k] = (double)v[k];
-    }
+    for (int p = 0; p < H4; ++p)
+        if (p < len) lds[row * NV + base + p] = (double)a4[p];
 }
 template <int NV, int NT, bool ADD>
 __device__ __forceinline__ void lds_rows_finish(const double* lds, double* __restrict__ out,
