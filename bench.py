@@ -464,6 +464,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--inplace-probe", action="store_true",
+                    help="only time a plain in-place elementwise pass over buffers of 32 MB to 1 GiB")
     ap.add_argument("--profile-step", choices=["fp32", "fp64"],
                     help="only run the d3q19_128 step (fixed launch shape, statistics on)")
     args = ap.parse_args()
@@ -473,6 +475,8 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+    elif args.inplace_probe:
+        inplace_probe()
     elif args.profile_step:
         profile_step(args)
     else:
@@ -488,6 +492,29 @@ def copy_probe():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4}))
+
+
+def inplace_probe():
+    """Read-and-write rate of a plain in-place pass (x *= 1) over one buffer,
+    by buffer size: the ceiling a one-buffer in-place step can reach when its
+    working set does or does not fit the last-level cache."""
+    import torch
+    out = {}
+    for mb in (32, 64, 128, 159, 200, 256, 320, 512, 1024):
+        n = mb * 2 ** 20 // 4
+        a = torch.ones(n, device="cuda")
+        for _ in range(30):
+            a.mul_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(200):
+            a.mul_(1.0)
+        e1.record()
+        e1.synchronize()
+        out[f"{mb}MB"] = round(2 * n * 4 / (e0.elapsed_time(e1) / 200 * 1e-3) / 1e12, 3)
+        del a
+    print(json.dumps({"inplace_probe_TBps": out}))
 
 
 def profile_step(args):
