@@ -262,6 +262,11 @@ flb_status flb_modeq_step(const flb_modeq_params* p, const void* fin, void* fout
 flb_status flb_modeq_run(const flb_modeq_params* p, void* f, void* tmp, uint64_t step0,
                          int32_t nsteps, void* work, size_t work_bytes, void* stream);
 
+/* Analysis: the moment fields of the pulled populations of state f,
+ * m[a * V + site] = sum_i T_ai f_i(x - c_i) (device, FP64, 9 V), the modes
+ * whose equal-time spectra eq. f-correl-yeo fixes.  Asynchronous. */
+flb_status flb_modeq_moments(const flb_modeq_params* p, const void* f, double* m, void* stream);
+
 /* Verification: the filtered (e, eps) noise of step `step`, xi[0 .. V) = xi_e,
  * xi[V .. 2V) = xi_eps (device, FP64). */
 flb_status flb_modeq_noise(const flb_modeq_params* p, uint64_t step, double* xi, void* work,

@@ -2,7 +2,7 @@
 
 Every call goes straight to the C ABI declared in include/flb.h; no step of the
 method runs in Python.  Importing this module fails loudly if the library has
-not been built (``python -m paper_1012_3632_amd.build``).
+not been built (``python paper_1012_3632_amd/build.py``).
 """
 
 import ctypes as C
@@ -53,7 +53,7 @@ class flb_modeq_params(C.Structure):
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
-                      "(python -m paper_1012_3632_amd.build)")
+                      "(python paper_1012_3632_amd/build.py)")
 
 lib = C.CDLL(LIB_PATH)
 
@@ -110,6 +110,7 @@ PROTOS = {
     "flb_modeq_step": [P(flb_modeq_params), vp, vp, C.c_uint64, vp, C.c_size_t, vp],
     "flb_modeq_run": [P(flb_modeq_params), vp, vp, C.c_uint64, C.c_int32, vp, C.c_size_t, vp],
     "flb_modeq_noise": [P(flb_modeq_params), C.c_uint64, vp, vp, C.c_size_t, vp],
+    "flb_modeq_moments": [P(flb_modeq_params), vp, vp, vp],
 }
 
 for _name, _args in PROTOS.items():

@@ -982,6 +982,17 @@ flb_status flb_modeq_noise(const flb_modeq_params* p, uint64_t step, double* xi,
     return FLB_OK;
 }
 
+flb_status flb_modeq_moments(const flb_modeq_params* p, const void* f, double* m, void* stream) {
+    ModEqArgs a{};
+    flb_status r = modeq_args(p, &a);
+    if (r != FLB_OK) return r;
+    if (!f || !m) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
+    if (!aligned(f)) return fail(FLB_ERR_INVALID_ARG, "populations must be 256-byte aligned");
+    if ((uintptr_t)m % sizeof(double)) return fail(FLB_ERR_INVALID_ARG, "m must be 8-byte aligned");
+    HIP_TRY(launch_modeq_moments(a, p->precision, f, m, (hipStream_t)stream));
+    return FLB_OK;
+}
+
 flb_status flb_modeq_step(const flb_modeq_params* p, const void* fin, void* fout, uint64_t step,
                           void* work, size_t work_bytes, void* stream) {
     ModEqArgs a{};

@@ -120,6 +120,9 @@ size_t modeq_work_bytes(int nx, int ny);
 // W + 2 V b (double2), filtered fields at xi + 2 V b.
 hipError_t launch_modeq_noise(const ModEqArgs& a, int prec, uint32_t step0, int nb, void* W,
                               double* xi, hipStream_t st);
+// Moment fields of the pulled populations, FP64, m[a * V + site].
+hipError_t launch_modeq_moments(const ModEqArgs& a, int prec, const void* fin, double* m,
+                                hipStream_t st);
 // One step; xi = that step's filtered fields, or null for kT = 0.
 hipError_t launch_modeq_step(const ModEqArgs& a, int prec, const void* fin, void* fout,
                              uint32_t step, const double* xi, hipStream_t st);

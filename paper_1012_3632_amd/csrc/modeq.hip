@@ -325,7 +325,43 @@ __global__ __launch_bounds__(MQ_TX * MQ_TY) void k_meq_step(ModEqArgs a, Geom g,
     }
 }
 
+// Analysis: the nine moment fields m_a(x) = sum_i T_ai f_i(x) of the pulled
+// populations, in FP64, m[a * V + site].
+template <typename Real>
+__global__ __launch_bounds__(256) void k_meq_moments(Geom g, const Real* __restrict__ fin,
+                                                     double* __restrict__ m) {
+    using L = Lattice<0>;
+    const uint32_t site = blockIdx.x * 256u + threadIdx.x;
+    if (site >= g.V) return;
+    const int x = (int)(site % (uint32_t)g.nx), y = (int)(site / (uint32_t)g.nx);
+    Real f[L::Q];
+    pull<0, Real>(fin, x, y, 0, g, f);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            if (L::T[q][i] != 0) s += (double)L::T[q][i] * (double)f[i];
+        m[(size_t)q * g.V + site] = s;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_modeq_moments(const ModEqArgs& a, int prec, const void* fin, double* m,
+                                hipStream_t st) {
+    Geom g{};
+    g.nx = a.nx;
+    g.ny = a.ny;
+    g.nz = 1;
+    g.V = (uint32_t)((size_t)a.nx * a.ny);
+    const dim3 grid((g.V + 255) / 256);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_meq_moments<float>, grid, dim3(256), 0, st, g, (const float*)fin, m);
+    else
+        hipLaunchKernelGGL(k_meq_moments<double>, grid, dim3(256), 0, st, g, (const double*)fin, m);
+    return hipGetLastError();
+}
 
 size_t modeq_work_bytes(int nx, int ny) {
     const size_t V = (size_t)nx * ny;

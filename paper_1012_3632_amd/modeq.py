@@ -93,6 +93,13 @@ class ModEq:
         call("flb_modeq_step", C.byref(self.c), _ptr(fin), _ptr(fout), int(n), _ptr(self.work),
              int(self.nbytes), _stream(stream))
 
+    def moments(self, out=None, stream=None):
+        """Moment fields of the pulled populations: (9, ny, nx) float64."""
+        if out is None:
+            out = torch.empty((9, self.p.ny, self.p.nx), dtype=torch.float64, device=self.f.device)
+        call("flb_modeq_moments", C.byref(self.c), _ptr(self.f), _ptr(out), _stream(stream))
+        return out
+
     def noise(self, n, stream=None):
         """The filtered (e, eps) noise of step n: (2, ny, nx) float64."""
         out = torch.empty((2, self.p.ny, self.p.nx), dtype=torch.float64, device=self.f.device)
@@ -121,25 +128,20 @@ def equal_time_variances(p):
 def run_spectra(p, burn_in, snapshots, interval, stream=None):
     """From rest: burn_in steps, then ``snapshots`` snapshots ``interval``
     steps apart, each adding |m_a(k)|^2 of the pulled moments (the
-    equilibration measure of Sec. VI) to a (9, ny, nx) FP64 sum.  The snapshot
-    projection onto the moments is a torch contraction; the transforms are
-    the library's field spectra.  Returns (spectrum sum, the ModEq)."""
-    from .sim import field_spectrum, lattice_tables
-    t = lattice_tables("D2Q9")
-    T = torch.as_tensor(t["T"], dtype=torch.float64, device="cuda")
-    c = t["c"]
+    equilibration measure of Sec. VI) to a (9, ny, nx) FP64 sum: the moment
+    fields (flb_modeq_moments) and their spectra (flb_field_spectrum).
+    Returns (spectrum sum, the ModEq)."""
+    from .sim import field_spectrum
     sim = ModEq(p)
     spec = torch.zeros((9, 1, p.ny, p.nx), dtype=torch.float64, device="cuda")
+    m = torch.empty((9, 1, p.ny, p.nx), dtype=torch.float64, device="cuda")
     work = torch.empty(16 * spec.numel(), dtype=torch.uint8, device="cuda")
     s = stream if stream is not None else torch.cuda.current_stream()
     with torch.cuda.stream(s):
         sim.step(burn_in, stream=s)
         for _ in range(snapshots):
             sim.step(interval, stream=s)
-            f = sim.f.double()
-            fp = torch.stack([torch.roll(f[i], (int(c[i, 1]), int(c[i, 0])), (0, 1))
-                              for i in range(9)])
-            m = torch.tensordot(T, fp, dims=([1], [0])).reshape(9, 1, p.ny, p.nx)
+            sim.moments(out=m, stream=s)
             field_spectrum(m, spec, work=work, stream=s)
     s.synchronize()
     return spec.reshape(9, p.ny, p.nx), sim

@@ -112,6 +112,21 @@ def test_full_size_workload_matches_oracle():
     assert rel_err(sim.f.cpu().numpy(), S) < F32_TOL
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(37, 10), (1, 1), (128, 128)], ids=str)
+def test_moment_fields_match_oracle(prec, shape):
+    from oracle import modeq as OM
+    from paper_1012_3632_amd.modeq import ModEq
+    nx, ny = shape
+    pg, _ = _pair(prec, nx, ny)
+    f0 = W.random_populations(9, (ny, nx), 23, 1e-3)
+    sim = ModEq(pg, f0=f0)
+    got = sim.moments().cpu().numpy()
+    f = sim.f.double().cpu().numpy()     # the stored state (FP32 rounding included)
+    ref = np.tensordot(OM.LAT.T, OM.pull(f), axes=([1], [0]))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-15 * np.abs(ref).max() + 1e-300)
+
+
 def test_rejects_bad_arguments():
     from paper_1012_3632_amd._lib import FLBError
     from paper_1012_3632_amd.modeq import ModEq, ModEqParams
