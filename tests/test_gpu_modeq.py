@@ -127,6 +127,25 @@ def test_moment_fields_match_oracle(prec, shape):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-15 * np.abs(ref).max() + 1e-300)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_noisy_run_conserves_mass_and_momentum(prec):
+    """The noise and the equilibrium leave rho, j_x, j_y unchanged at every
+    site-sum (eq. meq-yeo keeps them; the noise has no conserved component):
+    200 noisy steps change the totals only by rounding."""
+    from paper_1012_3632_amd.modeq import ModEq
+    pg, _ = _pair(prec, 48, 36, kT=1e-4)
+    f0 = W.random_populations(9, (36, 48), 31, 1e-3)
+    sim = ModEq(pg, f0=f0)
+    m0 = sim.moments().sum(dim=(1, 2))
+    sim.step(200)
+    m1 = sim.moments().sum(dim=(1, 2))
+    scale = sim.moments().abs().sum(dim=(1, 2))
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    for a in range(3):
+        assert abs(float(m1[a] - m0[a])) <= tol * float(scale[a]) + 1e-14, a
+    assert float(sim.moments()[3].abs().max()) > 0   # the noise is on
+
+
 def test_rejects_bad_arguments():
     from paper_1012_3632_amd._lib import FLBError
     from paper_1012_3632_amd.modeq import ModEq, ModEqParams
