@@ -414,7 +414,9 @@ size_t adjoint_work_bytes(const StepSpec& s) {
 uint32_t adjoint_slots(const StepSpec& s) {
     if (s.lat == 1 && s.force)
         return adj_geom(s, AdjTile<1, true>::X, AdjTile<1, true>::Y, AdjTile<1, true>::Z).nblocks;
-    return adj_geom(s, 64, 4, 1).nblocks;
+    if (s.lat == 0 && s.force)
+        return adj_geom(s, AdjTile<0, true>::X, AdjTile<0, true>::Y, AdjTile<0, true>::Z).nblocks;
+    return adj_geom(s, AdjTile<0, false>::X, AdjTile<0, false>::Y, AdjTile<0, false>::Z).nblocks;
 }
 
 template <int LAT, typename Real, bool FORCE>
