@@ -264,24 +264,46 @@ __global__ __launch_bounds__(MQ_TX * MQ_TY) void k_meq_step(ModEqArgs a, Geom g,
                                                             const double* __restrict__ xi) {
     using L = Lattice<0>;
     constexpr int SX = MQ_TX + 2, NS = SX * (MQ_TY + 2);
+    constexpr int NRING = NS - MQ_TX * MQ_TY;   // halo sites: two rows of SX, two columns of TY
+    static_assert(NRING <= MQ_TX * MQ_TY, "one halo site per thread at most");
     __shared__ Real rs[NS];
     const int x0 = blockIdx.x * MQ_TX, y0 = blockIdx.y * MQ_TY;
-    // density of the pulled populations on the tile and a one-site halo
-    for (int l = threadIdx.x; l < NS; l += MQ_TX * MQ_TY) {
-        const int gx = wrap(x0 - 1 + l % SX, g.nx), gy = wrap(y0 - 1 + l / SX, g.ny);
-        Real f[L::Q];
-        pull<0, Real>(fin, gx, gy, 0, g, f);
+    const int tx = threadIdx.x % MQ_TX, ty = threadIdx.x / MQ_TX;
+    const int x = x0 + tx, y = y0 + ty;
+    // density of the pulled populations on the tile and a one-site halo: each
+    // thread pulls its own site (periodic image for a ragged edge) and keeps
+    // the populations, the first NRING threads pull the halo ring
+    Real f[L::Q];
+    pull<0, Real>(fin, wrap(x, g.nx), wrap(y, g.ny), 0, g, f);
+    {
         Real s = Real(0);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) s += f[i];
-        rs[l] = s;
+        rs[(ty + 1) * SX + tx + 1] = s;
+    }
+    if (threadIdx.x < NRING) {
+        const int r = threadIdx.x;
+        int lx, ly;
+        if (r < SX) {
+            lx = r;
+            ly = 0;
+        } else if (r < 2 * SX) {
+            lx = r - SX;
+            ly = MQ_TY + 1;
+        } else {
+            const int c = r - 2 * SX;   // 0 .. 2 TY - 1
+            lx = c < MQ_TY ? 0 : SX - 1;
+            ly = 1 + (c < MQ_TY ? c : c - MQ_TY);
+        }
+        Real h[L::Q];
+        pull<0, Real>(fin, wrap(x0 - 1 + lx, g.nx), wrap(y0 - 1 + ly, g.ny), 0, g, h);
+        Real s = Real(0);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) s += h[i];
+        rs[ly * SX + lx] = s;
     }
     __syncthreads();
-    const int tx = threadIdx.x % MQ_TX, ty = threadIdx.x / MQ_TX;
-    const int x = x0 + tx, y = y0 + ty;
     if (x >= g.nx || y >= g.ny) return;
-    Real f[L::Q];
-    pull<0, Real>(fin, x, y, 0, g, f);
     Real m[L::Q];
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
