@@ -249,22 +249,42 @@ struct ForceTile {
 
     // The same, with the density of every staged site formed here from the
     // populations of fin (pulled and summed in the order of k_density, so the
-    // staged values are the same bits): no separate density pass.
+    // staged values are the same bits): no separate density pass.  2-D tiles
+    // only.  own: the populations the calling thread pulled for its own site
+    // (tx, ty) of the tile, or for that site's periodic image when it lies
+    // past a ragged edge; the tile's own sites take their density from them,
+    // and only the two-site ring around the tile is pulled here.
     static __device__ __forceinline__ void stage_pop(const Real* __restrict__ fin, const Geom& g,
                                                      const ForceParams<Real>& fp, int x0, int y0,
-                                                     int z0, Real* rs, Real* ms) {
+                                                     int tx, int ty, const Real (&own)[L::Q],
+                                                     Real* rs, Real* ms) {
+        static_assert(LAT == 0 && TZ == 1, "the ring staging is written for 2-D tiles");
+        constexpr int NRING = 4 * RX + 4 * TY;   // rows 0, 1, RY-2, RY-1 and columns 0, 1, RX-2, RX-1
         const int tid = threadIdx.x;
-        for (int l = tid; l < NR; l += NT) {
-            const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
-            const int gx = wrap_any(x0 + lx - 2, g.nx);
-            const int gy = wrap_any(y0 + ly - 2, g.ny);
-            const int gz = wrap_any(z0 + lz - 2 * HZ, g.nz);
+        {
+            Real acc = Real(0);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) acc += own[i];
+            rs[(ty + 2) * RX + tx + 2] = acc;
+        }
+        for (int r = tid; r < NRING; r += NT) {
+            int lx, ly;
+            if (r < 4 * RX) {
+                const int k = r / RX;   // 0, 1, 2, 3 -> rows 0, 1, RY - 2, RY - 1
+                lx = r - k * RX;
+                ly = k < 2 ? k : RY - 4 + k;
+            } else {
+                const int c = r - 4 * RX;   // 0 .. 4 TY - 1
+                const int k = c / TY;       // 0, 1, 2, 3 -> columns 0, 1, RX - 2, RX - 1
+                lx = k < 2 ? k : RX - 4 + k;
+                ly = 2 + (c - k * TY);
+            }
             Real f[L::Q];
-            pull<LAT, Real>(fin, gx, gy, gz, g, f);
+            pull<LAT, Real>(fin, wrap_any(x0 + lx - 2, g.nx), wrap_any(y0 + ly - 2, g.ny), 0, g, f);
             Real acc = Real(0);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) acc += f[i];
-            rs[l] = acc;
+            rs[ly * RX + lx] = acc;
         }
         __syncthreads();
         mu_from_rho(fp, rs, ms, NT);

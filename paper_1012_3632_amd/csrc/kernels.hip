@@ -83,12 +83,19 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
         // the populations are pulled before the density tile is staged, so
         // that the two sets of loads are in flight together
         const bool in0 = x < g.nx && y0 + ty < g.ny && z < g.nz;
-        if (in0) {
-            if constexpr (ROWS) pull_rows<LAT, Real>(fin, x, y0 + ty, z, g, fpre);
-            else pull<LAT, Real>(fin, x, y0 + ty, z, g, fpre);
+        if constexpr (FUSED) {
+            // every thread pulls its site (a periodic image past a ragged
+            // edge): the staged density of the tile's own sites comes from it
+            if (in0 && ROWS) pull_rows<LAT, Real>(fin, x, y0 + ty, z, g, fpre);
+            else pull<LAT, Real>(fin, wrap_any(x, g.nx), wrap_any(y0 + ty, g.ny), z, g, fpre);
+            FT::stage_pop(fin, g, fp, x0, y0, tx, ty, fpre, lds_force, lds_force + FT::NR);
+        } else {
+            if (in0) {
+                if constexpr (ROWS) pull_rows<LAT, Real>(fin, x, y0 + ty, z, g, fpre);
+                else pull<LAT, Real>(fin, x, y0 + ty, z, g, fpre);
+            }
+            FT::stage(drho, g, fp, x0, y0, z0, lds_force, lds_force + FT::NR);
         }
-        if constexpr (FUSED) FT::stage_pop(fin, g, fp, x0, y0, z0, lds_force, lds_force + FT::NR);
-        else FT::stage(drho, g, fp, x0, y0, z0, lds_force, lds_force + FT::NR);
         if (in0) FT::force(lds_force, lds_force + FT::NR, fp, P.rho0, tx, ty, tz, F);
     }
 
