@@ -241,17 +241,31 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_adj_collide(
             }
         }
     }
+    Real F[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) F[a] = Real(0);
     if constexpr (FUSE) {
-        if (Fbar_next) {   // uniform over the grid
-            Real* rs2 = lds_adj;
-            Real* fbs2 = rs2 + FA::NR;
-            Real* ms2 = fbs2 + D * FA::NR;
-            Real* mubs2 = ms2 + FA::NM;
-            Real* rbs = mubs2 + FA::NM;
+        // every staged field is requested at once: this step's density tile,
+        // and the later step's Fbar and density on the tile two sites wider;
+        // then the chemical potentials and mubar in one phase
+        const bool next = Fbar_next != nullptr;   // uniform over the grid
+        Real* rs2 = lds_adj;
+        Real* fbs2 = rs2 + FA::NR;
+        Real* ms2 = fbs2 + D * FA::NR;
+        Real* mubs2 = ms2 + FA::NM;
+        Real* rbs = mubs2 + FA::NM;
+        FT::load_rho(drho, g, x0, y0, z0, lds_force, NT);
+        if (next) {
             FA::load_fbar(Fbar_next, g, x0 - 1, y0 - 1, z0, fbs2, NT);
-            FA::FT::stage(drho_next, g, fp, x0 - 1, y0 - 1, z0, rs2, ms2, NT);   // synchronizes
+            FA::FT::load_rho(drho_next, g, x0 - 1, y0 - 1, z0, rs2, NT);
+        }
+        __syncthreads();
+        if (next) {
+            FA::FT::mu_rows(fp, rs2, ms2, NT);
             FA::mubar(rs2, fbs2, mubs2, P.rho0, NT);
-            __syncthreads();
+        }
+        FT::mu_from_rho(fp, lds_force, lds_force + FT::NR, NT);   // ends with a barrier
+        if (next) {
             for (int l = threadIdx.x; l < NRB; l += NT)
                 rbs[l] = FA::rhobar(rs2, ms2, fbs2, mubs2, fp, l % (TX + 2), l / (TX + 2), 0);
             __syncthreads();
@@ -261,11 +275,8 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_adj_collide(
                     ab[i] += rbs[(ty + 1 + L::cy[i]) * (TX + 2) + (tx + 1 + L::cx[i])];
             }
         }
-    }
-    Real F[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) F[a] = Real(0);
-    if constexpr (FORCE) {
+        if (inside) FT::force(lds_force, lds_force + FT::NR, fp, P.rho0, tx, ty, tz, F);
+    } else if constexpr (FORCE) {
         FT::stage(drho, g, fp, x0, y0, z0, lds_force, lds_force + FT::NR);
         if (inside) FT::force(lds_force, lds_force + FT::NR, fp, P.rho0, tx, ty, tz, F);
     }

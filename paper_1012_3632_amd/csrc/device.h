@@ -235,16 +235,22 @@ struct ForceTile {
     static __device__ __forceinline__ void stage(const Real* __restrict__ drho, const Geom& g,
                                                  const ForceParams<Real>& fp, int x0, int y0,
                                                  int z0, Real* rs, Real* ms, int nthreads = NT) {
-        const int tid = threadIdx.x;
-        for (int l = tid; l < NR; l += nthreads) {
+        load_rho(drho, g, x0, y0, z0, rs, nthreads);
+        __syncthreads();
+        mu_from_rho(fp, rs, ms, nthreads);
+    }
+
+    // The density loads of stage alone (no barrier).
+    static __device__ __forceinline__ void load_rho(const Real* __restrict__ drho, const Geom& g,
+                                                    int x0, int y0, int z0, Real* rs,
+                                                    int nthreads) {
+        for (int l = threadIdx.x; l < NR; l += nthreads) {
             const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
             const int gx = wrap_any(x0 + lx - 2, g.nx);
             const int gy = wrap_any(y0 + ly - 2, g.ny);
             const int gz = wrap_any(z0 + lz - 2 * HZ, g.nz);
             rs[l] = drho[(uint32_t)((gz * g.ny + gy) * g.nx + gx)];
         }
-        __syncthreads();
-        mu_from_rho(fp, rs, ms, nthreads);
     }
 
     // The same, with the density of every staged site formed here from the
@@ -292,6 +298,13 @@ struct ForceTile {
 
     static __device__ __forceinline__ void mu_from_rho(const ForceParams<Real>& fp, const Real* rs,
                                                        Real* ms, int nthreads) {
+        mu_rows(fp, rs, ms, nthreads);
+        __syncthreads();
+    }
+
+    // The chemical potential of mu_from_rho alone (no barrier).
+    static __device__ __forceinline__ void mu_rows(const ForceParams<Real>& fp, const Real* rs,
+                                                   Real* ms, int nthreads) {
         const int tid = threadIdx.x;
         for (int l = tid; l < NM; l += nthreads) {
             const int mx = l % MX, my = (l / MX) % MY, mz = l / (MX * MY);
@@ -307,7 +320,6 @@ struct ForceTile {
             const Real d = rc + fp.shift;
             ms[l] = Real(2) * fp.a * d + Real(4) * fp.b * d * d * d - fp.kappa * lap;
         }
-        __syncthreads();
     }
 
     // Force at tile-local site (lx, ly, lz); also returns delta rho there.
