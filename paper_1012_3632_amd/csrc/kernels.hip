@@ -214,8 +214,9 @@ __global__ __launch_bounds__(TX* TY) void k_step_ip(Real* f, Geom g, CollidePara
 // and chemical potential live in LDS ring buffers (ForceMarch); the density
 // plane two ahead is loaded into registers one plane early, and the
 // populations of the current plane are requested before the barriers, so
-// global loads overlap the LDS work.
-template <typename Real, bool STATS, int TX, int TY>
+// global loads overlap the LDS work.  NTS: populations stored with
+// non-temporal hints (the state of a large lattice does not stay in the cache).
+template <typename Real, bool STATS, int TX, int TY, bool NTS = false>
 __global__ __launch_bounds__(TX* TY) void k_step_march(
     const Real* __restrict__ fin, Real* __restrict__ fout, const Real* __restrict__ drho, Geom g,
     CollideParams<Real> P, ForceParams<Real> fp, StepIndex st, double* __restrict__ partial) {
@@ -297,7 +298,10 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(
             if constexpr (ROWS) {
                 const size_t row = (size_t)(uint32_t)((z * g.ny + y) * g.nx);
 #pragma unroll
-                for (int i = 0; i < Q; ++i) plane_st(fout + ((size_t)i * g.V + row), (uint32_t)xl, f[i]);
+                for (int i = 0; i < Q; ++i) {
+                    if constexpr (NTS) plane_st_nt(fout + ((size_t)i * g.V + row), (uint32_t)xl, f[i]);
+                    else plane_st(fout + ((size_t)i * g.V + row), (uint32_t)xl, f[i]);
+                }
             } else {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) plane_st(fout + (size_t)i * g.V, site, f[i]);
@@ -501,18 +505,18 @@ static void step_tile(const StepSpec& s, const void* fin, void* fout, const void
                            (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
 }
 
-template <typename Real, int TX, int TY>
+template <typename Real, int TX, int TY, bool NTS = false>
 static void step_march(const StepSpec& s, int zc, const void* fin, void* fout, const void* drho,
                        StepIndex si, double* partial, hipStream_t st) {
-    const Geom g = make_geom(s, TileShape{TX, TY, 1, 1, 0, zc, 0});
+    const Geom g = make_geom(s, TileShape{TX, TY, 1, 1, NTS, zc, 0});
     const dim3 grid(g.nblocks), block(TX * TY);
     const CollideParams<Real> P = collide_params<Real>(s);
     const ForceParams<Real> fp = force_params<Real>(s);
     if (partial)
-        hipLaunchKernelGGL((k_step_march<Real, true, TX, TY>), grid, block, 0, st, (const Real*)fin,
+        hipLaunchKernelGGL((k_step_march<Real, true, TX, TY, NTS>), grid, block, 0, st, (const Real*)fin,
                            (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
     else
-        hipLaunchKernelGGL((k_step_march<Real, false, TX, TY>), grid, block, 0, st, (const Real*)fin,
+        hipLaunchKernelGGL((k_step_march<Real, false, TX, TY, NTS>), grid, block, 0, st, (const Real*)fin,
                            (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
 }
 
@@ -545,7 +549,8 @@ static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fou
             case 4: step_march<Real, 64, 4>(s, 32, fin, fout, drho, si, partial, st); break;
             case 5: step_march<Real, 32, 8>(s, 16, fin, fout, drho, si, partial, st); break;
             case 6: step_march<Real, 64, 8>(s, 16, fin, fout, drho, si, partial, st); break;
-            default: step_march<Real, 128, 2>(s, 16, fin, fout, drho, si, partial, st); break;
+            case 7: step_march<Real, 128, 2>(s, 16, fin, fout, drho, si, partial, st); break;
+            default: step_march<Real, 128, 2, true>(s, 16, fin, fout, drho, si, partial, st); break;
         }
     } else {
         switch (cfg) {
