@@ -349,6 +349,28 @@ def extras(args, stream):
         "snapshots": wl["snapshots"],
         "ratio_to_G_by_mode": [round(float(x), 4) for x in np.nanmean(rm.reshape(9, -1), 1)]}
     del sm, spec_m
+    # the same model at 1024^2, the largest extent of its transforms: one
+    # step moves 232 B per site (noise: 32 B written by the row transforms,
+    # 64 B read and written by the column pass, 48 B by the inverse rows;
+    # step: 36 B of populations in, 36 B out, 16 B of filtered noise)
+    pm2 = pm.with_(nx=1024, ny=1024)
+    sm2 = MQ.ModEq(pm2)
+    with torch.cuda.stream(stream):
+        sm2.step(32, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        nms = 160
+        e0.record(stream)
+        sm2.step(nms, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+    ms2 = e0.elapsed_time(e1) / nms
+    V2 = pm2.nx * pm2.ny
+    res["d2q9_1024_modeq"] = {"ms_per_step": round(ms2, 5), "MLUPS": round(V2 / (ms2 * 1e-3) / 1e6, 1),
+                              "GBps_232B_per_site": round(232 * V2 / (ms2 * 1e-3) / 1e9, 1),
+                              "hbm_frac": round(232 * V2 / (ms2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del sm2
+    torch.cuda.empty_cache()
 
     # the capillary-fluctuation test of Sec. VI: 1024 x 400 stripe, 10^6 steps
     from paper_1012_3632_amd import capillary as CAP
