@@ -486,6 +486,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--profile-modeq", type=int, metavar="N",
+                    help="only run the modified-equilibrium model on an N x N lattice (FP32, "
+                         "the equilibration parameters), 64 steps after 32 warm-up steps")
     ap.add_argument("--inplace-probe", action="store_true",
                     help="only time a plain in-place elementwise pass over buffers of 32 MB to 1 GiB")
     ap.add_argument("--profile-step", choices=["fp32", "fp64"],
@@ -499,6 +502,8 @@ def main():
         copy_probe()
     elif args.inplace_probe:
         inplace_probe()
+    elif args.profile_modeq:
+        profile_modeq(args.profile_modeq)
     elif args.profile_step:
         profile_step(args)
     else:
@@ -514,6 +519,21 @@ def copy_probe():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4}))
+
+
+def profile_modeq(n):
+    """The modified-equilibrium model at n x n for per-kernel profiles."""
+    import torch
+
+    import flb_workloads as W
+    from paper_1012_3632_amd import modeq as MQ
+    pm = MQ.ModEqParams(**W.modeq_params_of("d2q9_128_modeq", nx=n, ny=n))
+    sm = MQ.ModEq(pm)
+    sm.step(32)
+    torch.cuda.synchronize()
+    sm.step(64)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_modeq": n, "steps": 96}))
 
 
 def inplace_probe():
