@@ -146,6 +146,19 @@ def test_noisy_run_conserves_mass_and_momentum(prec):
     assert float(sim.moments()[3].abs().max()) > 0   # the noise is on
 
 
+def test_maximum_size_steps_match_oracle():
+    """1024 x 1024, the largest extent of the noise transforms (a 1024-point
+    FFT along both axes), FP32 in the benchmark's batching: 2 steps."""
+    from oracle import modeq as OM
+    from paper_1012_3632_amd.modeq import ModEq
+    pg, po = _pair("fp32", 1024, 1024)
+    f0 = W.random_populations(9, (1024, 1024), 41, 1e-3)
+    sim = ModEq(pg, f0=f0)
+    sim.step(2)
+    S = OM.run(np.array(f0), po, 2)
+    assert rel_err(sim.f.cpu().numpy(), S) < F32_TOL
+
+
 def test_rejects_bad_arguments():
     from paper_1012_3632_amd._lib import FLBError
     from paper_1012_3632_amd.modeq import ModEq, ModEqParams
