@@ -6,7 +6,9 @@
  * the discrete Boltzmann equation", Sec. V eq. lbe-mom) on periodic D2Q9 or
  * D3Q19 lattices, for the ideal gas (Sec. IV.A) and for the force-based
  * non-ideal fluid (Sec. IV.B.1) with the square-gradient force of App. A
- * (eq. he-force) and the Landau double well of Sec. VI (eq. f0-bulk).
+ * (eq. he-force) and the Landau double well of Sec. VI (eq. f0-bulk); and,
+ * handle-free (flb_modeq_*), the modified-equilibrium model of Sec. IV.B
+ * linearized about rest on D2Q9, with its k-dependent noise.
  *
  * One time step with index n maps the post-collision populations S_n to S_{n+1}:
  *   pull      f_i(x) = S_{n,i}(x - c_i)                         (periodic)
