@@ -32,8 +32,9 @@
 // (blockIdx.y = step within the batch): at small lattices a single step's
 // lines are far fewer blocks than the chip has CUs.
 // Each line sits in LDS with its twiddles.  Power-of-two extents use an
-// in-place radix-2 FFT (input in bit-reversed order, log2 n butterfly stages
-// with a barrier each, the e and eps lines of a block sharing the stages);
+// in-place radix-2 FFT (input in bit-reversed order, the butterfly stages
+// taken two per pass through LDS, the e and eps lines of a block sharing the
+// passes);
 // other extents (at most 1024) use direct sums.  Then k_meq_step applies the
 // step.
 #include <hip/hip_runtime.h>
@@ -86,27 +87,59 @@ __device__ __forceinline__ int brev(int j, int logn) {
     return logn == 0 ? 0 : (int)(__brev((unsigned)j) >> (32 - logn));
 }
 
+// a + w x, a - w x for complex values, w's imaginary part negated for an
+// inverse transform
+__device__ __forceinline__ void bfly(double2& a, double2& x, double2 w, bool inverse) {
+    const double wi = inverse ? -w.y : w.y;
+    const double vr = x.x * w.x - x.y * wi, vi = x.x * wi + x.y * w.x;
+    x = make_double2(a.x - vr, a.y - vi);
+    a = make_double2(a.x + vr, a.y + vi);
+}
+
 // In place, the two lines b[0 .. n) and b[n .. 2n) (n = 2^logn), each loaded
 // in bit-reversed order, become their transforms in natural order
-// (exp(-+ 2 pi i j k / n), sign - forward, + inverse).  Ends with a barrier.
+// (exp(-+ 2 pi i j k / n), sign - forward, + inverse).  Radix-2 stages are
+// taken two at a time: stages s and s + 1 (half h = 2^(s-1)) combine the four
+// elements a, a + h, a + 2h, a + 3h of a group, so a thread loads them once,
+// applies both stages in registers and stores them; the quads of a pass are
+// disjoint.  An odd last stage is a plain radix-2 pass.  Ends with a barrier.
 __device__ __forceinline__ void fft2_lines(double2* b, const double2* __restrict__ tw, int n,
                                            int logn, bool inverse) {
-    const int nh = n >> 1;
-    for (int s = 1; s <= logn; ++s) {
-        const int half = 1 << (s - 1);
-        const int step = n >> s;   // exp(-2 pi i pos / 2 half) = tw[pos * step]
+    const int nq = n >> 2, nh = n >> 1;
+    int s = 1;
+    for (; s + 1 <= logn; s += 2) {
+        const int h = 1 << (s - 1);
+        const int st1 = n >> s, st2 = n >> (s + 1);
+        for (int t = threadIdx.x; t < 2 * nq; t += blockDim.x) {
+            const int f = t >= nq ? 1 : 0;
+            const int q = t - f * nq;
+            const int pos = q & (h - 1);
+            const int a = f * n + ((q >> (s - 1)) << (s + 1)) + pos;
+            double2 x0 = b[a], x1 = b[a + h], x2 = b[a + 2 * h], x3 = b[a + 3 * h];
+            const double2 w1 = tw[pos * st1];
+            bfly(x0, x1, w1, inverse);   // stage s
+            bfly(x2, x3, w1, inverse);
+            bfly(x0, x2, tw[pos * st2], inverse);         // stage s + 1
+            bfly(x1, x3, tw[(pos + h) * st2], inverse);
+            b[a] = x0;
+            b[a + h] = x1;
+            b[a + 2 * h] = x2;
+            b[a + 3 * h] = x3;
+        }
+        __syncthreads();
+    }
+    if (s == logn) {
+        const int h = 1 << (s - 1);
+        const int st1 = n >> s;
         for (int t = threadIdx.x; t < 2 * nh; t += blockDim.x) {
             const int f = t >= nh ? 1 : 0;
             const int bt = t - f * nh;
-            const int pos = bt & (half - 1);
+            const int pos = bt & (h - 1);
             const int i0 = f * n + ((bt >> (s - 1)) << s) + pos;
-            const int i1 = i0 + half;
-            const double2 w = tw[pos * step];
-            const double wi = inverse ? -w.y : w.y;
-            const double2 u = b[i0], x = b[i1];
-            const double vr = x.x * w.x - x.y * wi, vi = x.x * wi + x.y * w.x;
-            b[i0] = make_double2(u.x + vr, u.y + vi);
-            b[i1] = make_double2(u.x - vr, u.y - vi);
+            double2 u = b[i0], x = b[i0 + h];
+            bfly(u, x, tw[pos * st1], inverse);
+            b[i0] = u;
+            b[i0 + h] = x;
         }
         __syncthreads();
     }
