@@ -96,25 +96,26 @@ __device__ __forceinline__ void bfly(double2& a, double2& x, double2 w, bool inv
     a = make_double2(a.x + vr, a.y + vi);
 }
 
-// In place, the two lines b[0 .. n) and b[n .. 2n) (n = 2^logn), each loaded
-// in bit-reversed order, become their transforms in natural order
-// (exp(-+ 2 pi i j k / n), sign - forward, + inverse).  Radix-2 stages are
-// taken two at a time: stages s and s + 1 (half h = 2^(s-1)) combine the four
-// elements a, a + h, a + 2h, a + 3h of a group, so a thread loads them once,
-// applies both stages in registers and stores them; the quads of a pass are
-// disjoint.  An odd last stage is a plain radix-2 pass.  Ends with a barrier.
-__device__ __forceinline__ void fft2_lines(double2* b, const double2* __restrict__ tw, int n,
-                                           int logn, bool inverse) {
-    const int nq = n >> 2, nh = n >> 1;
+// In place, the NL lines b[L n .. (L + 1) n) (n = 2^logn), each loaded in
+// bit-reversed order, become their transforms in natural order
+// (exp(-+ 2 pi i j k / n), sign - forward, + inverse): decimation in time.
+// Radix-2 stages are taken two at a time: stages s and s + 1 (half
+// h = 2^(s-1)) combine the four elements a, a + h, a + 2h, a + 3h of a group,
+// so a thread loads them once, applies both stages in registers and stores
+// them; the quads of a pass are disjoint.  An odd last stage is a plain
+// radix-2 pass.  Ends with a barrier.
+__device__ __forceinline__ void fft_lines_dit(double2* b, const double2* __restrict__ tw, int NL,
+                                              int n, int logn, bool inverse) {
     int s = 1;
     for (; s + 1 <= logn; s += 2) {
         const int h = 1 << (s - 1);
         const int st1 = n >> s, st2 = n >> (s + 1);
-        for (int t = threadIdx.x; t < 2 * nq; t += blockDim.x) {
-            const int f = t >= nq ? 1 : 0;
-            const int q = t - f * nq;
+        const int nq = n >> 2;
+        for (int t = threadIdx.x; t < NL * nq; t += blockDim.x) {
+            const int L = t >> (logn - 2);
+            const int q = t - L * nq;
             const int pos = q & (h - 1);
-            const int a = f * n + ((q >> (s - 1)) << (s + 1)) + pos;
+            const int a = L * n + ((q >> (s - 1)) << (s + 1)) + pos;
             double2 x0 = b[a], x1 = b[a + h], x2 = b[a + 2 * h], x3 = b[a + 3 * h];
             const double2 w1 = tw[pos * st1];
             bfly(x0, x1, w1, inverse);   // stage s
@@ -131,15 +132,72 @@ __device__ __forceinline__ void fft2_lines(double2* b, const double2* __restrict
     if (s == logn) {
         const int h = 1 << (s - 1);
         const int st1 = n >> s;
-        for (int t = threadIdx.x; t < 2 * nh; t += blockDim.x) {
-            const int f = t >= nh ? 1 : 0;
-            const int bt = t - f * nh;
+        const int nh = n >> 1;
+        for (int t = threadIdx.x; t < NL * nh; t += blockDim.x) {
+            const int L = t >> (logn - 1);
+            const int bt = t - L * nh;
             const int pos = bt & (h - 1);
-            const int i0 = f * n + ((bt >> (s - 1)) << s) + pos;
+            const int i0 = L * n + ((bt >> (s - 1)) << s) + pos;
             double2 u = b[i0], x = b[i0 + h];
             bfly(u, x, tw[pos * st1], inverse);
             b[i0] = u;
             b[i0 + h] = x;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void fft2_lines(double2* b, const double2* __restrict__ tw, int n,
+                                           int logn, bool inverse) {
+    fft_lines_dit(b, tw, 2, n, logn, inverse);
+}
+
+// (u, v) -> (u + v, (u - v) w): the decimation-in-frequency butterfly
+__device__ __forceinline__ void bfly_dif(double2& u, double2& v, double2 w) {
+    const double dr = u.x - v.x, di = u.y - v.y;
+    u = make_double2(u.x + v.x, u.y + v.y);
+    v = make_double2(dr * w.x - di * w.y, dr * w.y + di * w.x);
+}
+
+// In place, the NL lines of b (natural order) become their forward
+// transforms in bit-reversed order: decimation in frequency, stages from
+// half n/2 down to 1, two per pass (halves 2 q and q combine the elements a,
+// a + q, a + 2q, a + 3q of a group of 4q); an odd last stage (half 1) alone.
+// Ends with a barrier.
+__device__ __forceinline__ void fft_lines_dif(double2* b, const double2* __restrict__ tw, int NL,
+                                              int n, int logn) {
+    int s = logn;
+    for (; s >= 2; s -= 2) {
+        const int q4 = 1 << (s - 2);
+        const int stA = n >> s, stC = n >> (s - 1);
+        const int nq = n >> 2;
+        for (int t = threadIdx.x; t < NL * nq; t += blockDim.x) {
+            const int L = t >> (logn - 2);
+            const int qq = t - L * nq;
+            const int pos = qq & (q4 - 1);
+            const int a = L * n + ((qq >> (s - 2)) << s) + pos;
+            double2 x0 = b[a], x1 = b[a + q4], x2 = b[a + 2 * q4], x3 = b[a + 3 * q4];
+            bfly_dif(x0, x2, tw[pos * stA]);          // half 2 q4
+            bfly_dif(x1, x3, tw[(pos + q4) * stA]);
+            const double2 wC = tw[pos * stC];         // half q4
+            bfly_dif(x0, x1, wC);
+            bfly_dif(x2, x3, wC);
+            b[a] = x0;
+            b[a + q4] = x1;
+            b[a + 2 * q4] = x2;
+            b[a + 3 * q4] = x3;
+        }
+        __syncthreads();
+    }
+    if (s == 1) {
+        const int nh = n >> 1;
+        for (int t = threadIdx.x; t < NL * nh; t += blockDim.x) {
+            const int L = t >> (logn - 1);
+            const int i0 = L * n + 2 * (t - L * nh);
+            double2 u = b[i0], v = b[i0 + 1];
+            bfly_dif(u, v, make_double2(1.0, 0.0));
+            b[i0] = u;
+            b[i0 + 1] = v;
         }
         __syncthreads();
     }
@@ -246,6 +304,64 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_filter_y(ModEqArgs a,
     for (int y = threadIdx.x; y < n; y += blockDim.x) {
         W[(size_t)y * nx + kx] = dft_at(be, tw, n, y, true);
         W[V + (size_t)y * nx + kx] = dft_at(bp, tw, n, y, true);
+    }
+}
+
+// Power-of-two ny: CB adjacent columns per block (loads and stores of a row
+// touch CB consecutive values).  The forward transforms leave the spectra in
+// bit-reversed order (decimation in frequency), the Cholesky mix is
+// pointwise there (position j holds wavenumber ky = brev(j)), and the inverse
+// transforms take that order back to natural order (decimation in time), so
+// no permutation step is needed.  Lines in LDS: e of columns 0 .. CB-1, then
+// eps.  nx must be a multiple of CB.
+template <int CB>
+__global__ __launch_bounds__(MQ_THREADS) void k_meq_filter_cols(ModEqArgs a,
+                                                                double2* __restrict__ W) {
+    extern __shared__ double2 lds_mq[];
+    const int n = a.ny, nx = a.nx, kx0 = blockIdx.x * CB;
+    const int logn = log2i(n);
+    const size_t V = (size_t)a.nx * a.ny;
+    W += (size_t)blockIdx.y * 2 * V;
+    double2* tw = lds_mq;
+    double2* b = lds_mq + n;
+    twiddles(tw, n);
+    for (int idx = threadIdx.x; idx < CB * n; idx += blockDim.x) {
+        const int y = idx / CB, c = idx - y * CB;
+        b[c * n + y] = W[(size_t)y * nx + kx0 + c];
+        b[(CB + c) * n + y] = W[V + (size_t)y * nx + kx0 + c];
+    }
+    __syncthreads();
+    fft_lines_dif(b, tw, 2 * CB, n, logn);
+    double cxs[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        double sx;
+        sincospi(2.0 * (double)(kx0 + c) / (double)nx, &sx, &cxs[c]);
+    }
+    const double pre = 12.0 * a.rho0 * a.kT;
+    const double le = a.rate_bulk, lg = a.rate_ghost;
+    for (int idx = threadIdx.x; idx < CB * n; idx += blockDim.x) {
+        const int c = idx >> logn, j = idx & (n - 1);
+        const double cx = cxs[c];
+        const double cy = tw[brev(j, logn)].x;
+        const double lap = (4.0 / 3.0) * (2.0 - cx - cy) + (2.0 / 3.0) * (1.0 - cx * cy);
+        const double c2 = a.cs2_0 + a.kappa * a.rho0 * lap;
+        const double see = pre * le * (2.0 - le) * (2.0 - 3.0 * c2);
+        const double sep = pre * (3.0 * c2 - 1.0) * (le + lg - le * lg);
+        const double spp = pre * lg * (2.0 - lg) * (5.0 - 3.0 * c2);
+        const double l11 = sqrt(fmax(see, 0.0));
+        const double l21 = l11 > 0.0 ? sep / l11 : 0.0;
+        const double l22 = sqrt(fmax(spp - l21 * l21, 0.0));
+        const double2 ze = b[c * n + j], zp = b[(CB + c) * n + j];
+        b[c * n + j] = make_double2(l11 * ze.x, l11 * ze.y);
+        b[(CB + c) * n + j] = make_double2(l21 * ze.x + l22 * zp.x, l21 * ze.y + l22 * zp.y);
+    }
+    __syncthreads();
+    fft_lines_dit(b, tw, 2 * CB, n, logn, true);
+    for (int idx = threadIdx.x; idx < CB * n; idx += blockDim.x) {
+        const int y = idx / CB, c = idx - y * CB;
+        W[(size_t)y * nx + kx0 + c] = b[c * n + y];
+        W[V + (size_t)y * nx + kx0 + c] = b[(CB + c) * n + y];
     }
 }
 
@@ -432,7 +548,43 @@ hipError_t launch_modeq_noise(const ModEqArgs& a, int prec, uint32_t step0, int 
         hipLaunchKernelGGL(k_meq_noise_x<float>, gx, dim3(MQ_THREADS), lx, st, a, step0, Wc);
     else
         hipLaunchKernelGGL(k_meq_noise_x<double>, gx, dim3(MQ_THREADS), lx, st, a, step0, Wc);
-    hipLaunchKernelGGL(k_meq_filter_y, gy, dim3(MQ_THREADS), ly, st, a, Wc);
+    const bool p2 = (a.ny & (a.ny - 1)) == 0;
+    int cb = 1;
+    if (p2) {
+        int dev = 0, lmax = 65536;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        const size_t per = (size_t)a.ny * sizeof(double2);
+        for (int c : {4, 2}) {
+            if (a.nx % c == 0 && (1 + 2 * (size_t)c) * per <= (size_t)lmax) {
+                cb = c;
+                break;
+            }
+        }
+        const size_t lc = (1 + 2 * (size_t)cb) * per;
+        const dim3 gc((unsigned)(a.nx / cb), (unsigned)nb);
+        hipError_t e = hipSuccess;
+        switch (cb) {
+            case 4:
+                e = hipFuncSetAttribute((const void*)k_meq_filter_cols<4>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc);
+                if (e == hipSuccess)
+                    hipLaunchKernelGGL(k_meq_filter_cols<4>, gc, dim3(MQ_THREADS), lc, st, a, Wc);
+                break;
+            case 2:
+                e = hipFuncSetAttribute((const void*)k_meq_filter_cols<2>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc);
+                if (e == hipSuccess)
+                    hipLaunchKernelGGL(k_meq_filter_cols<2>, gc, dim3(MQ_THREADS), lc, st, a, Wc);
+                break;
+            default:
+                hipLaunchKernelGGL(k_meq_filter_cols<1>, gc, dim3(MQ_THREADS), lc, st, a, Wc);
+                break;
+        }
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(k_meq_filter_y, gy, dim3(MQ_THREADS), ly, st, a, Wc);
+    }
     hipLaunchKernelGGL(k_meq_noise_ix, gx, dim3(MQ_THREADS), lx, st, a, (const double2*)Wc, xi);
     return hipGetLastError();
 }
