@@ -24,18 +24,21 @@
 // equilibrium populations are non-negative).  That pair is drawn as white
 // normals z_e, z_eps (the site's Philox normals 0 and 5), transformed, mixed
 // by the lower Cholesky factor of the block at every k, and transformed back:
-//   k_meq_noise_x    normals of one row, DFT along x          (one block per row)
-//   k_meq_filter_y   DFT along y, Cholesky mix, inverse DFT   (one block per column)
-//   k_meq_noise_ix   inverse DFT along x, real part / V       (one block per row)
+//   k_meq_noise_x      normals of one row, DFT along x         (one block per row)
+//   k_meq_filter_cols  DFT along y, Cholesky mix, inverse DFT  (CB adjacent columns
+//     / k_meq_filter_y                                          per block; one column
+//                                                               when ny is not a power of 2)
+//   k_meq_noise_ix     inverse DFT along x, real part / V      (one block per row)
 // The noise does not depend on the state, so a launch of these three
 // kernels draws and filters the noise of a batch of consecutive steps
 // (blockIdx.y = step within the batch): at small lattices a single step's
 // lines are far fewer blocks than the chip has CUs.
 // Each line sits in LDS with its twiddles.  Power-of-two extents use an
-// in-place radix-2 FFT (input in bit-reversed order, the butterfly stages
-// taken two per pass through LDS, the e and eps lines of a block sharing the
-// passes);
-// other extents (at most 1024) use direct sums.  Then k_meq_step applies the
+// in-place radix-2 FFT, the butterfly stages taken two per pass through LDS
+// and shared by all lines of a block: decimation in time from bit-reversed
+// input for the rows, and for the columns decimation in frequency forward
+// (bit-reversed output), the mix in that order, then decimation in time back.
+// Other extents (at most 1024) use direct sums.  Then k_meq_step applies the
 // step.
 #include <hip/hip_runtime.h>
 
