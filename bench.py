@@ -349,6 +349,18 @@ def extras(args, stream):
         "snapshots": wl["snapshots"],
         "ratio_to_G_by_mode": [round(float(x), 4) for x in np.nanmean(rm.reshape(9, -1), 1)]}
     del sm, spec_m
+    # the same workload with FP64 state and step arithmetic
+    sm64 = MQ.ModEq(pm.with_(precision="fp64"))
+    with torch.cuda.stream(stream):
+        sm64.step(200, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        sm64.step(2000, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+    res["d2q9_128_modeq"]["fp64_ms_per_step"] = round(e0.elapsed_time(e1) / 2000, 5)
+    del sm64
     # the same model at 1024^2, the largest extent of its transforms: one
     # step moves 232 B per site (noise: 32 B written by the row transforms,
     # 64 B read and written by the column pass, 48 B by the inverse rows;
