@@ -134,3 +134,34 @@ def test_modeq_validation_and_sizes():
     for p in bad:
         with pytest.raises(FLBError):
             work_bytes(p)
+
+
+def test_modeq_entry_points_reject_bad_pointers():
+    """flb_modeq_step / _run / _noise / _moments check their pointers on the
+    host before any device work: NULL, aliased or unaligned buffers and a
+    too-small work buffer are errors (no device memory is touched)."""
+    import ctypes as C
+
+    from paper_1012_3632_amd._lib import FLBError, call
+    from paper_1012_3632_amd.modeq import ModEqParams
+    p = ModEqParams(nx=8, ny=8, kT=1e-5, cs2_0=0.07, kappa=0.08).to_c()
+    A, B, Wk = C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20)
+    odd = C.c_void_p((1 << 20) + 8)
+    need = 48 * 64
+    bad_calls = [
+        ("flb_modeq_step", C.byref(p), None, B, 0, Wk, need, None),
+        ("flb_modeq_step", C.byref(p), A, A, 0, Wk, need, None),
+        ("flb_modeq_step", C.byref(p), odd, B, 0, Wk, need, None),
+        ("flb_modeq_step", C.byref(p), A, B, 0, Wk, need - 1, None),
+        ("flb_modeq_step", C.byref(p), A, B, 0, None, need, None),
+        ("flb_modeq_run", C.byref(p), A, A, 0, 4, Wk, need, None),
+        ("flb_modeq_run", C.byref(p), A, B, 0, -1, Wk, need, None),
+        ("flb_modeq_noise", C.byref(p), 0, None, Wk, need, None),
+        ("flb_modeq_noise", C.byref(p), 0, A, Wk, need - 1, None),
+        ("flb_modeq_moments", C.byref(p), None, A, None),
+        ("flb_modeq_moments", C.byref(p), odd, A, None),
+    ]
+    for name, *args in bad_calls:
+        with pytest.raises(FLBError) as e:
+            call(name, *args)
+        assert e.value.status == -1, (name, e.value)   # FLB_ERR_INVALID_ARG: rejected on the host
