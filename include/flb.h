@@ -116,10 +116,16 @@ flb_status flb_query_sizes(const flb_params* p, size_t* pop_bytes, size_t* scrat
 flb_status flb_init(const flb_params* p, void* f_a, void* f_b, void* scratch, void* stats,
                     const double* drho_init, void* stream, flb_handle** out);
 
-/* Advance nsteps time steps.  If stats_stride > 0, the pre-collision moments
- * of every step k (0-based in this call) with (k + 1) % stats_stride == 0 are
- * accumulated into the FP64 statistics (sum and sum of squares per mode over
- * sites, with m_0 taken as rho - rho0).  Asynchronous. */
+/* Advance nsteps time steps of Sec. V eq. lbe-mom (each: pull, moments of
+ * Sec. III eq. moments, relaxation with the forcing moments of Sec. V
+ * eq. lbe-moments and the noise of eq. noise-lbe, back-transform of Sec. III
+ * eq. moments-inv; the force of App. A eq. he-force for force_model 1).  If
+ * stats_stride > 0, the pre-collision moments of every step k (0-based in
+ * this call) with (k + 1) % stats_stride == 0 are accumulated into the FP64
+ * statistics (sum and sum of squares per mode over sites, with m_0 taken as
+ * rho - rho0): the equal-time mode variances that Sec. IV.A eq. G-ideal fixes.
+ * Returns FLB_ERR_INVALID_ARG for nsteps < 0 or stats_stride < 0 (nothing
+ * queued), FLB_ERR_HIP if a launch fails.  Asynchronous. */
 flb_status flb_step(flb_handle* h, int64_t nsteps, int32_t stats_stride, void* stream);
 
 /* Current state: *cur receives the device buffer holding S_n, *other the
@@ -132,8 +138,12 @@ flb_status flb_seek(flb_handle* h, uint64_t step, void* stream);
 
 /* Finalize the statistics in a fixed order and copy them to the host:
  * mode_sum[Q], mode_sumsq[Q] (either may be NULL), *nsamples the number of
- * sampled steps.  Synchronizes the stream.  Returns FLB_ERR_NONFINITE if a
- * sum is not finite. */
+ * sampled steps.  Per mode a, sumsq / (nsamples V) - (sum / (nsamples V))^2
+ * is the equal-time variance that the fluctuation-dissipation theorem fixes
+ * at rho0 kT N_a / cs2 for the ideal gas (Sec. IV.A eq. G-ideal; the
+ * per-mode equilibration ratio of Sec. VI.A).  Host arrays, caller-owned.
+ * Synchronizes the stream.  Returns FLB_ERR_NONFINITE if a sum is not
+ * finite (the outputs are still written). */
 flb_status flb_moments(flb_handle* h, double* mode_sum, double* mode_sumsq, int64_t* nsamples,
                        void* stream);
 
@@ -299,12 +309,16 @@ flb_status flb_noise_normals(const flb_params* p, uint64_t step, uint64_t site0,
 flb_status flb_lattice_tables(int32_t lattice, int32_t* q, int32_t* c, double* w, double* T,
                               double* N, int32_t* cls);
 
-/* Record nsteps steps (same meaning as flb_step) into a HIP graph owned by the
- * handle, replacing any previous one.  The step index is read from device
- * memory, so every replay continues the noise sequence.  Nothing runs. */
+/* Record nsteps steps (same meaning as flb_step; nsteps even, stream not
+ * NULL) into HIP graphs owned by the handle, replacing any previous ones: one
+ * recording for each of the two population buffers the state can start
+ * from, so a replay continues the state after any number of ordinary steps.
+ * The step index is read from device memory, so every replay continues the
+ * noise sequence.  Nothing runs. */
 flb_status flb_graph_capture(flb_handle* h, int64_t nsteps, int32_t stats_stride, void* stream);
 
-/* Replay the captured graph once (advances the state by its nsteps). */
+/* Replay the captured steps once from the current buffer (advances the
+ * state by their nsteps).  FLB_ERR_STATE if nothing was captured. */
 flb_status flb_graph_launch(flb_handle* h, void* stream);
 
 /* Adjoint of one time step (reverse mode), for the gradient of a scalar loss.
@@ -399,6 +413,8 @@ flb_status flb_batch_moments(flb_batch* b, double* mode_sum, double* mode_sumsq,
                              int64_t* nsamples, void* stream);
 
 flb_status flb_batch_state(const flb_batch* b, void** cur, void** other, uint64_t* step);
+/* As flb_graph_capture / flb_graph_launch, for the batch (one recording per
+ * current buffer; the schedule in force at capture is kept). */
 flb_status flb_batch_graph_capture(flb_batch* b, int64_t nsteps, int32_t stats_stride,
                                    void* stream);
 flb_status flb_batch_graph_launch(flb_batch* b, void* stream);

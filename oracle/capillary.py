@@ -19,13 +19,24 @@ as 2 - 2 cos k, sigma from eq. surf-tension.
 * ``surface_tension``    eq. surf-tension; ``capillary_theory`` the expected
                          |h(k)|^2 = A kT / (sigma sum_a (2 - 2 cos k_a)), A the
                          interface area in sites.
+* ``bulk_pressure``      p0 = rho psi'(rho) - psi(rho), the bulk pressure of
+                         the eta = 1 force (the LB ideal pressure is replaced),
+                         App. A eq. he-force.
+* ``laplace_drop``       the interface tension of this scheme by mechanics: a
+                         2-D drop relaxed at kT = 0, its equimolar radius R and
+                         the bulk pressures inside and outside; Young-Laplace
+                         in 2-D gives sigma = R (p_in - p_out).
 * ``effective_kappa`` / ``effective_surface_tension``: a reading.  This
   lattice scheme's density fluctuations follow the Ornstein-Zernike form with
   kappa_eff(rho0) = kappa + (eta cs2 - rho0 psi''(rho0)) / (4 rho0) in place of
   kappa (pinned against ``spectra.stationary_spectrum``); the tension of an
   interface is then taken as the square-gradient integral
   sigma_eff = int sqrt(2 kappa_eff(rho) W(rho)) drho between the bulk
-  densities, W the double well above its common tangent.
+  densities, W the double well above its common tangent.  Parity unpinned:
+  the scheme's mechanical tension (``laplace_drop``) is not this integral
+  (about 0.4 of it at the capillary parameters), and its steady states are
+  not those of any square-gradient free energy with bulk density psi (a flat
+  interface balances p0 but not psi').
 
 Pins: ``tests/test_oracle_capillary.py``.
 """
@@ -134,3 +145,41 @@ def effective_surface_tension(p, rho_L, rho_V):
     val, _ = quad(lambda r: np.sqrt(max(2.0 * effective_kappa(p, r) * W(r), 0.0)), rho_V, rho_L,
                   epsabs=1e-14, epsrel=1e-12)
     return val
+
+
+def bulk_pressure(p, rho):
+    """p0 = rho psi'(rho) - psi(rho): the pressure of a uniform phase under the
+    eta = 1 force (F = -rho grad mu + cs2 grad rho cancels the LB pressure
+    rho cs2, and -rho grad psi' = -grad p0)."""
+    d = rho - p.rho_c
+    return rho * (2 * p.a * d + 4 * p.b * d ** 3) - _psi(p, rho)
+
+
+def laplace_drop(p, L, R0, nsteps, rho_L, rho_V, width):
+    """A liquid drop of radius R0 (mean-field profile of eq. denprof, width
+    ``width``) centred in an L x L periodic D2Q9 box of vapour, relaxed with
+    the oracle step at kT = 0 for ``nsteps`` steps.
+
+    Returns dict(R, rho_in, rho_out, dp, sigma): the bulk densities (the mean
+    density at distance below R0 - 3 width from the centre, and above
+    R0 + 3 width), the equimolar radius R = sqrt(sum (rho - rho_out) /
+    (pi (rho_in - rho_out))), the bulk pressure difference
+    dp = p0(rho_in) - p0(rho_out), and sigma = R dp, the tension by the 2-D
+    Young-Laplace law dp = sigma / R."""
+    from . import flb
+    if p.lattice != "D2Q9" or p.force_model != 1 or p.eta != 1:
+        raise ValueError("the drop is a D2Q9 run with the eta = 1 force")
+    q = p.with_(nx=L, ny=L, nz=1, kT=0.0)
+    y, x = np.mgrid[0:L, 0:L] + 0.5 - L / 2
+    r = np.hypot(x, y)
+    rho = 0.5 * (rho_L + rho_V) - 0.5 * (rho_L - rho_V) * np.tanh(2 * (r - R0) / width)
+    lat = flb.lattice_of(q)
+    S = flb.initial_state(q, (rho - q.rho0)[None])
+    for k in range(nsteps):
+        S = flb.step(S, k, q, lat)
+    d = flb.fields(S, q, lat)[0][0].numpy()
+    rin = float(d[r < R0 - 3 * width].mean())
+    rout = float(d[r > R0 + 3 * width].mean())
+    R = float(np.sqrt((d - rout).sum() / (np.pi * (rin - rout))))
+    dp = float(bulk_pressure(q, rin) - bulk_pressure(q, rout))
+    return dict(R=R, rho_in=rin, rho_out=rout, dp=dp, sigma=R * dp)

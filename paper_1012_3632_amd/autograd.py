@@ -53,8 +53,13 @@ class FLBRun(torch.autograd.Function):
         sim.adjoint_run(ctx.ckpts, abar, ck, N, grad=g)
         FLBRun.last_grads = dict(rate_shear=g[0], kT=g[1], rate_bulk=g[2], rate_ghost=g[3])
         dev = grad_rho.device
-        return (abar.to(ctx.dtype), torch.tensor(g[0], dtype=torch.float64, device=dev),
-                torch.tensor(g[1], dtype=torch.float64, device=dev), None, None, None)
+        # a parameter passed as a plain number (or a tensor without
+        # requires_grad) gets no gradient
+        need = ctx.needs_input_grad
+        g_f0 = abar.to(ctx.dtype) if need[0] else None
+        g_rs = torch.tensor(g[0], dtype=torch.float64, device=dev) if need[1] else None
+        g_kT = torch.tensor(g[1], dtype=torch.float64, device=dev) if need[2] else None
+        return g_f0, g_rs, g_kT, None, None, None
 
 
 def final_density(delta_f0, rate_shear, kT, params, nsteps, checkpoint_every=20):

@@ -19,7 +19,7 @@ SOURCES = ["kernels.hip", "adjoint.hip", "batch.hip", "spectrum.hip", "modeq.hip
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics", "-ffp-contract=on",
+    "-ffp-contract=on",
 ]
 
 

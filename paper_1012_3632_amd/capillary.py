@@ -9,10 +9,14 @@ local heights h(x) of both interfaces (eq. height-def,
 (``field_spectrum``).  The result is compared with the capillary structure
 factor A kT / (sigma (2 - 2 cos k)) (eq. capill-static on the lattice).
 
-Two tensions are available: eq. surf-tension with the model's kappa, and the
-effective tension of this lattice scheme, the square-gradient integral with
-kappa_eff(rho) = kappa + (eta cs2 - rho psi''(rho)) / (4 rho), the coefficient
-its small-k density fluctuations show.
+The paper's tension is eq. surf-tension with the model's kappa.  This lattice
+scheme does not reach eq. capill-static with it: its height spectrum has the
+capillary form with a tension ~1.45 times eq. surf-tension's, while drops
+relaxed by the same scheme at kT = 0 obey the Young-Laplace law with ~0.66
+times it.  ``effective_surface_tension`` (the square-gradient integral with
+kappa_eff(rho) = kappa + (eta cs2 - rho psi''(rho)) / (4 rho), the
+coefficient the scheme's small-k density fluctuations show) lies near the
+spectrum's value but is a reading, not a derived tension.
 """
 
 import numpy as np

@@ -151,8 +151,11 @@ struct flb_handle {
     int cfg;                // launch shape of steps without statistics
     int cfg_stats;          // launch shape of steps that accumulate statistics
     int pair_cfg;           // in-place shape for pairs of steps, or -1
-    hipGraph_t graph;
-    hipGraphExec_t gexec;
+    // captured steps, one graph per current buffer (index cur_a): kernel
+    // arguments hold the buffer pointers, so a replay must start from the
+    // buffer its graph was recorded for
+    hipGraph_t graph[2];
+    hipGraphExec_t gexec[2];
     int64_t graph_steps, graph_samples;
     hipStream_t aux;        // helper stream of flb_adjoint_run (created on first use)
     // scratch regions
@@ -167,6 +170,15 @@ struct flb_handle {
 };
 
 namespace {
+
+void release_graphs(flb_handle* h) {
+    for (int k = 0; k < 2; ++k) {
+        if (h->gexec[k]) (void)hipGraphExecDestroy(h->gexec[k]);
+        if (h->graph[k]) (void)hipGraphDestroy(h->graph[k]);
+        h->gexec[k] = nullptr;
+        h->graph[k] = nullptr;
+    }
+}
 
 void scratch_layout(const StepSpec& s, size_t V, size_t rb, size_t* drho_off, size_t* adj_off,
                     size_t* gpart_off, size_t* total) {
@@ -310,8 +322,8 @@ flb_status flb_init(const flb_params* p, void* f_a, void* f_b, void* scratch, vo
     // tile (no density pass); every other kind to shape 0
     h->cfg = h->cfg_stats = (h->spec.force && h->spec.lat == 0) ? 4 : 0;
     h->pair_cfg = -1;
-    h->graph = nullptr;
-    h->gexec = nullptr;
+    h->graph[0] = h->graph[1] = nullptr;
+    h->gexec[0] = h->gexec[1] = nullptr;
     size_t drho_off, adj_off, gp_off, total;
     scratch_layout(h->spec, h->V, h->real_bytes, &drho_off, &adj_off, &gp_off, &total);
     h->step_dev = (unsigned long long*)h->scratch;
@@ -510,28 +522,37 @@ flb_status flb_graph_capture(flb_handle* h, int64_t nsteps, int32_t stats_stride
         return fail(FLB_ERR_INVALID_ARG, "graph step count must be even (buffers alternate)");
     hipStream_t st = (hipStream_t)stream;
     if (!st) return fail(FLB_ERR_INVALID_ARG, "graph capture needs a non-null stream");
-    if (h->gexec) {
-        (void)hipGraphExecDestroy(h->gexec);
-        h->gexec = nullptr;
-    }
-    if (h->graph) {
-        (void)hipGraphDestroy(h->graph);
-        h->graph = nullptr;
-    }
+    release_graphs(h);
+    // record the steps once for each buffer the state can be in, so that a
+    // replay after an odd number of ordinary steps still continues the state
     const bool cur_a = h->cur_a;
-    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     int64_t ns = 0;
-    flb_status r = run_steps(h, nsteps, stats_stride, true, st, &ns);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(st, &g);
+    flb_status r = FLB_OK;
+    for (int k = 0; k < 2 && r == FLB_OK; ++k) {
+        h->cur_a = k == 1;
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            r = fail(FLB_ERR_HIP, "begin capture: %s", hipGetErrorString(e));
+            break;
+        }
+        r = run_steps(h, nsteps, stats_stride, true, st, &ns);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(st, &g);
+        if (r == FLB_OK && e != hipSuccess)
+            r = fail(FLB_ERR_HIP, "capture: %s", hipGetErrorString(e));
+        if (r != FLB_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            break;
+        }
+        h->graph[k] = g;
+        e = hipGraphInstantiate(&h->gexec[k], g, nullptr, nullptr, 0);
+        if (e != hipSuccess) r = fail(FLB_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    }
     h->cur_a = cur_a;   // nothing ran
     if (r != FLB_OK) {
-        if (g) (void)hipGraphDestroy(g);
+        release_graphs(h);
         return r;
     }
-    if (e != hipSuccess) return fail(FLB_ERR_HIP, "capture: %s", hipGetErrorString(e));
-    h->graph = g;
-    HIP_TRY(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
     h->graph_steps = nsteps;
     h->graph_samples = ns;
     return FLB_OK;
@@ -539,8 +560,9 @@ flb_status flb_graph_capture(flb_handle* h, int64_t nsteps, int32_t stats_stride
 
 flb_status flb_graph_launch(flb_handle* h, void* stream) {
     if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
-    if (!h->gexec) return fail(FLB_ERR_STATE, "no graph captured");
-    HIP_TRY(hipGraphLaunch(h->gexec, (hipStream_t)stream));
+    hipGraphExec_t ex = h->gexec[h->cur_a ? 1 : 0];
+    if (!ex) return fail(FLB_ERR_STATE, "no graph captured");
+    HIP_TRY(hipGraphLaunch(ex, (hipStream_t)stream));
     h->step += (uint64_t)h->graph_steps;
     h->nsamples += h->graph_samples;
     // graph_steps is even, so the current buffer is unchanged
@@ -1053,8 +1075,7 @@ flb_status flb_modeq_run(const flb_modeq_params* p, void* f, void* tmp, uint64_t
 
 flb_status flb_destroy(flb_handle* h) {
     if (!h) return FLB_OK;
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
+    release_graphs(h);
     if (h->aux) {
         (void)hipStreamSynchronize(h->aux);
         (void)hipStreamDestroy(h->aux);

@@ -369,14 +369,25 @@ struct flb_batch {
     uint64_t pair_bytes;   // > 0: in-place pairs, groups of replicas up to this many bytes
     int pair_cfg;          // persistent grid of the in-place steps
     std::vector<BatchGroup> groups;
-    hipGraph_t graph;
-    hipGraphExec_t gexec;
+    // captured steps, one graph per current buffer (index cur_a): kernel
+    // arguments hold the buffer pointers
+    hipGraph_t graph[2];
+    hipGraphExec_t gexec[2];
     int64_t graph_steps, graph_samples;
     void* cur() const { return cur_a ? fa : fb; }
     void* other() const { return cur_a ? fb : fa; }
 };
 
 namespace {
+
+void release_batch_graphs(flb_batch* b) {
+    for (int k = 0; k < 2; ++k) {
+        if (b->gexec[k]) (void)hipGraphExecDestroy(b->gexec[k]);
+        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+        b->gexec[k] = nullptr;
+        b->graph[k] = nullptr;
+    }
+}
 
 constexpr int N_GRID_CFG = 4;
 constexpr int GRID_PER_CU[N_GRID_CFG] = {8, 4, 16, 2};
@@ -579,8 +590,8 @@ flb_status flb_batch_init(const flb_params* base, int32_t nrep, const int32_t* d
     b->grid_cfg_stats = 0;
     b->pair_bytes = 0;
     b->pair_cfg = 2;
-    b->graph = nullptr;
-    b->gexec = nullptr;
+    b->graph[0] = b->graph[1] = nullptr;
+    b->gexec[0] = b->gexec[1] = nullptr;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -660,28 +671,36 @@ flb_status flb_batch_graph_capture(flb_batch* b, int64_t nsteps, int32_t stats_s
         return bfail(FLB_ERR_INVALID_ARG, "graph step count must be positive and even");
     hipStream_t st = (hipStream_t)stream;
     if (!st) return bfail(FLB_ERR_INVALID_ARG, "graph capture needs a non-null stream");
-    if (b->gexec) {
-        (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
-    }
-    if (b->graph) {
-        (void)hipGraphDestroy(b->graph);
-        b->graph = nullptr;
-    }
+    release_batch_graphs(b);
+    // one recording for each buffer the state can be in (see flb_graph_capture)
     const bool cur_a = b->cur_a;
-    BHIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     int64_t ns = 0;
-    flb_status r = batch_run(b, nsteps, stats_stride, true, st, &ns);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(st, &g);
-    b->cur_a = cur_a;
+    flb_status r = FLB_OK;
+    for (int k = 0; k < 2 && r == FLB_OK; ++k) {
+        b->cur_a = k == 1;
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            r = bfail(FLB_ERR_HIP, "begin capture: %s", hipGetErrorString(e));
+            break;
+        }
+        r = batch_run(b, nsteps, stats_stride, true, st, &ns);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(st, &g);
+        if (r == FLB_OK && e != hipSuccess)
+            r = bfail(FLB_ERR_HIP, "capture: %s", hipGetErrorString(e));
+        if (r != FLB_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            break;
+        }
+        b->graph[k] = g;
+        e = hipGraphInstantiate(&b->gexec[k], g, nullptr, nullptr, 0);
+        if (e != hipSuccess) r = bfail(FLB_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    b->cur_a = cur_a;   // nothing ran
     if (r != FLB_OK) {
-        if (g) (void)hipGraphDestroy(g);
+        release_batch_graphs(b);
         return r;
     }
-    if (e != hipSuccess) return bfail(FLB_ERR_HIP, "capture: %s", hipGetErrorString(e));
-    b->graph = g;
-    BHIP(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
     b->graph_steps = nsteps;
     b->graph_samples = ns;
     return FLB_OK;
@@ -689,8 +708,9 @@ flb_status flb_batch_graph_capture(flb_batch* b, int64_t nsteps, int32_t stats_s
 
 flb_status flb_batch_graph_launch(flb_batch* b, void* stream) {
     if (!b) return bfail(FLB_ERR_INVALID_ARG, "batch is NULL");
-    if (!b->gexec) return bfail(FLB_ERR_STATE, "no graph captured");
-    BHIP(hipGraphLaunch(b->gexec, (hipStream_t)stream));
+    hipGraphExec_t ex = b->gexec[b->cur_a ? 1 : 0];
+    if (!ex) return bfail(FLB_ERR_STATE, "no graph captured");
+    BHIP(hipGraphLaunch(ex, (hipStream_t)stream));
     b->step += (uint64_t)b->graph_steps;
     b->nsamples += b->graph_samples;
     return FLB_OK;
@@ -788,8 +808,7 @@ flb_status flb_batch_pairs(const flb_batch* b, uint64_t* pair_bytes, int32_t* ng
 }
 flb_status flb_batch_destroy(flb_batch* b) {
     if (!b) return FLB_OK;
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    release_batch_graphs(b);
     delete b;
     return FLB_OK;
 }

@@ -131,6 +131,28 @@ def test_run_gradient_matches_oracle(precision, lattice, force):
     np.testing.assert_allclose(got["extra"]["rate_ghost"], ref["rate_ghost"], rtol=tol)
 
 
+def test_run_gradient_with_float_parameters():
+    """Rate and kT passed as plain floats: backward returns dL/d(delta f0)
+    (equal to the run with tensor parameters) and no parameter gradients."""
+    from paper_1012_3632_amd.autograd import final_density
+    kw = dict(W.params_of("d2q9_256_adjoint", nx=40, ny=34), precision="fp32")
+    p = gpu_params(**kw)
+    df0 = torch.as_tensor(W.random_populations(9, (1, 34, 40), 3, 1e-3)).to("cuda", p.dtype)
+    grads = []
+    for as_tensor in (False, True):
+        x = df0.clone().requires_grad_(True)
+        rs, kT = kw["rate_shear"], kw["kT"]
+        if as_tensor:
+            rs = torch.tensor(rs, dtype=F64, requires_grad=True)
+            kT = torch.tensor(kT, dtype=F64, requires_grad=True)
+        rho = final_density(x, rs, kT, p, 30, 10)
+        (rho ** 2).mean().backward()
+        grads.append(x.grad.clone())
+        if as_tensor:
+            assert rs.grad is not None and kT.grad is not None
+    assert torch.equal(grads[0], grads[1])
+
+
 def test_d2q9_256_adjoint_full_size_vs_fd():
     """The differentiable workload at full size (D2Q9 256^2, FP32, 400 steps,
     checkpoint every 20): GPU gradients w.r.t. the shear rate, kT and the

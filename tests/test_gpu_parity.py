@@ -226,6 +226,40 @@ def test_graph_replay_matches_eager():
     np.testing.assert_array_equal(qa, qb)
 
 
+@pytest.mark.parametrize("pairs", [False, True])
+def test_graph_replay_after_an_odd_step(pairs):
+    """A graph captured with the state in one buffer and replayed after an
+    odd number of ordinary steps (the state then in the other buffer)
+    continues the state: capture 4, step 1, replay = 5 eager steps, bit for
+    bit, states and statistics; with in-place pairs as well."""
+    from paper_1012_3632_amd import Simulation
+    kw = dict(C2, precision="fp32", nx=64, ny=12, nz=10)
+    a = Simulation(gpu_params(**kw))
+    b = Simulation(gpu_params(**kw))
+    if pairs:
+        n, _ = a.launch_configs()
+        ip = [c for c in range(n) if a.launch_shape(c)[6]][0]
+        a.set_launch(ip)
+        b.set_launch(ip)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b.graph_capture(4, stats_stride=1)
+        b.step(1, stats_stride=1)
+        b.graph_launch()
+        b.step(1, stats_stride=1)   # back to the first buffer
+        b.graph_launch()
+        a.step(5, stats_stride=1)
+        a.step(5, stats_stride=1)
+        torch.cuda.synchronize()
+    assert a.step_index == b.step_index == 10
+    assert torch.equal(a.state(), b.state())
+    sa, qa, na = a.moments()
+    sb, qb, nb = b.moments()
+    assert na == nb == 10
+    np.testing.assert_array_equal(sa, sb)
+    np.testing.assert_array_equal(qa, qb)
+
+
 def test_resume_is_bit_exact():
     from paper_1012_3632_amd import Simulation
     kw = dict(C2, precision="fp32", nx=30, ny=20, nz=10)

@@ -165,3 +165,4 @@ def test_modeq_entry_points_reject_bad_pointers():
         with pytest.raises(FLBError) as e:
             call(name, *args)
         assert e.value.status == -1, (name, e.value)   # FLB_ERR_INVALID_ARG: rejected on the host
+

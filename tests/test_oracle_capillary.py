@@ -11,7 +11,12 @@
   (1/L) sum_k (2 - 2 cos k) |h(k)|^2, with height_spectrum's normalisation;
 * the effective square-gradient coefficient of the reading equals the one
   the exact linearized step gives at small k (fitted), for random wells,
-  rates, densities and both force forms.
+  rates, densities and both force forms;
+* mechanics: p0 = rho psi' - psi is the scheme's bulk pressure (a flat
+  interface relaxes to equal p0 in the two phases), and drops obey the 2-D
+  Young-Laplace law p_in - p_out = sigma / R with one tension sigma; that
+  tension is below eq. surf-tension's and far from the effective integral of
+  the reading, which mechanics therefore does not pin.
 """
 
 import numpy as np
@@ -93,3 +98,49 @@ def test_effective_kappa_is_the_linearized_steps():
         kap0 = np.linalg.lstsq(A, y, rcond=None)[0][0]
         np.testing.assert_allclose(kap0 * rho0, cap.effective_kappa(p, rho0) * rho0, atol=2e-5)
         checked += 1
+
+
+def _capillary_params():
+    return flb.Params(lattice="D2Q9", rho0=0.75, kT=0.0, force_model=1,
+                      a=-0.5 * BETA * (RL - RV) ** 2, b=BETA, rho_c=0.5 * (RL + RV),
+                      kappa=KAPPA, eta=1)
+
+
+def test_flat_interface_balances_the_bulk_pressure():
+    """A flat stripe of the capillary workload relaxed at kT = 0: the two
+    phases end at equal bulk pressure p0 (zero curvature, zero Laplace
+    pressure), which makes p0 the pressure the drop test compares.  Their
+    psi' differ by ~2.4e-4, three times the largest Laplace jump measured
+    below: the steady state is mechanical, not that of a free energy with
+    bulk density psi."""
+    p = _capillary_params().with_(nx=1, ny=96)
+    w = cap.interface_width(RL, RV, KAPPA, BETA)
+    y = np.arange(96) + 0.5
+    rho = RV + 0.5 * (RL - RV) * (np.tanh(2 * (y - 24) / w) - np.tanh(2 * (y - 72) / w))
+    S = flb.initial_state(p, (rho - p.rho0).reshape(1, 96, 1))
+    S, _ = flb.run(S, p, 6000)
+    d = flb.fields(S, p)[0].numpy()[0, :, 0]
+    rin, rout = d[48], d[0]
+    assert abs(cap.bulk_pressure(p, rin) - cap.bulk_pressure(p, rout)) < 2e-6
+    dpsi = lambda r: 2 * p.a * (r - p.rho_c) + 4 * p.b * (r - p.rho_c) ** 3
+    assert dpsi(rin) - dpsi(rout) > 1e-4
+
+
+@pytest.mark.slow
+def test_laplace_drops_fix_the_mechanical_tension():
+    """Two drops (R 20 in 80^2, R 28 in 112^2) relaxed at kT = 0: the bulk
+    pressure jump falls as 1/R (Young-Laplace in 2-D), sigma = R dp agreeing
+    within 10 % (the smaller drop's curvature correction); the tension is
+    0.55-0.8 of eq. surf-tension's and under half the effective integral of
+    the reading."""
+    p = _capillary_params()
+    w = cap.interface_width(RL, RV, KAPPA, BETA)
+    d1 = cap.laplace_drop(p, 80, 20.0, 3000, RL, RV, w)
+    d2 = cap.laplace_drop(p, 112, 28.0, 4000, RL, RV, w)
+    assert d1["dp"] > d2["dp"] > 0
+    assert abs(d1["sigma"] / d2["sigma"] - 1) < 0.1
+    s_eq = cap.surface_tension(RL, RV, KAPPA, BETA)
+    s_eff = cap.effective_surface_tension(p, RL, RV)
+    for d in (d1, d2):
+        assert 0.55 < d["sigma"] / s_eq < 0.8
+        assert d["sigma"] / s_eff < 0.5
