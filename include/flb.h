@@ -274,6 +274,23 @@ flb_status flb_modeq_step(const flb_modeq_params* p, const void* fin, void* fout
 flb_status flb_modeq_run(const flb_modeq_params* p, void* f, void* tmp, uint64_t step0,
                          int32_t nsteps, void* work, size_t work_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * step as flb_modeq_step, bit for bit, with the noise work taken from a fixed
+ * device array inside the library instead of a caller buffer.  The array
+ * holds flb_modeq_static_work_bytes() bytes (16 MiB) on each GPU the library
+ * runs on, from its first use there until the process ends, so the step
+ * needs 48 V <= 16 MiB (V <= 349525 sites, e.g. 512 x 512; kT = 0 needs no
+ * work and has no limit); larger lattices are rejected with
+ * FLB_ERR_INVALID_ARG before anything is queued.  fin, fout as for
+ * flb_modeq_step.  Calls no allocator.  Every call on a GPU uses that GPU's
+ * one array: calls that overlap on one GPU (other streams, other threads)
+ * race and must be ordered by the caller.  Asynchronous on `stream`. */
+flb_status flb_modeq_step_noalloc(const flb_modeq_params* p, const void* fin, void* fout,
+                                  uint64_t step, void* stream);
+/* Size in bytes of that fixed array.  Host only. */
+flb_status flb_modeq_static_work_bytes(size_t* bytes);
+
 /* Analysis: the moment fields of the pulled populations of state f,
  * m[a * V + site] = sum_i T_ai f_i(x - c_i) (device, FP64, 9 V), the modes
  * whose equal-time spectra eq. f-correl-yeo fixes.  Asynchronous. */

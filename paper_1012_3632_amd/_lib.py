@@ -111,6 +111,8 @@ PROTOS = {
     "flb_modeq_run": [P(flb_modeq_params), vp, vp, C.c_uint64, C.c_int32, vp, C.c_size_t, vp],
     "flb_modeq_noise": [P(flb_modeq_params), C.c_uint64, vp, vp, C.c_size_t, vp],
     "flb_modeq_moments": [P(flb_modeq_params), vp, vp, vp],
+    "flb_modeq_step_noalloc": [P(flb_modeq_params), vp, vp, C.c_uint64, vp],
+    "flb_modeq_static_work_bytes": [P(C.c_size_t)],
 }
 
 for _name, _args in PROTOS.items():

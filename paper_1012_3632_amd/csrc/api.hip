@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <string>
@@ -1029,6 +1030,87 @@ flb_status flb_modeq_step(const flb_modeq_params* p, const void* fin, void* fout
     const size_t V = (size_t)a.nx * a.ny;
     double* xi = nullptr;
     if (a.kT > 0.0) {
+        xi = (double*)((char*)work + 2 * V * sizeof(double2));
+        HIP_TRY(launch_modeq_noise(a, p->precision, (uint32_t)step, 1, work, xi, st));
+    }
+    HIP_TRY(launch_modeq_step(a, p->precision, fin, fout, (uint32_t)step, xi, st));
+    return FLB_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------- modified-equilibrium step without allocation
+//
+// The noise work of flb_modeq_step (the two complex noise spectra and the
+// filtered fields, 48 V bytes) lives in a fixed device array of this file
+// instead of a caller buffer.  Each GPU holds its own copy of the array from
+// the library's first use on it until the process ends.  In host code the
+// array's name is only a stand-in: its device address is looked up once per
+// device with hipGetSymbolAddress and that address is what the kernels get.
+
+namespace {
+
+constexpr size_t MODEQ_STATIC_BYTES = (size_t)16 << 20;
+constexpr int MAX_DEVICES = 64;
+
+static __device__ __align__(256) unsigned char scratch[MODEQ_STATIC_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES];
+
+// Device address of `scratch` on the current device (looked up on the first
+// call there, with that device current).
+flb_status static_scratch(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return fail(FLB_ERR_UNSUPPORTED, "device %d beyond the %d the library tracks", dev,
+                    MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(FLB_ERR_HIP, "hipGetSymbolAddress returned NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+flb_status flb_modeq_static_work_bytes(size_t* bytes) {
+    if (!bytes) return fail(FLB_ERR_INVALID_ARG, "NULL bytes");
+    *bytes = MODEQ_STATIC_BYTES;
+    return FLB_OK;
+}
+
+flb_status flb_modeq_step_noalloc(const flb_modeq_params* p, const void* fin, void* fout,
+                                  uint64_t step, void* stream) {
+    ModEqArgs a{};
+    flb_status r = modeq_args(p, &a);
+    if (r != FLB_OK) return r;
+    if (!fin || !fout) return fail(FLB_ERR_INVALID_ARG, "NULL populations");
+    if (fin == fout) return fail(FLB_ERR_INVALID_ARG, "fin and fout must differ");
+    if (!aligned(fin) || !aligned(fout))
+        return fail(FLB_ERR_INVALID_ARG, "populations must be 256-byte aligned");
+    const size_t need = a.kT > 0.0 ? modeq_work_bytes(a.nx, a.ny) : 0;
+    if (need > MODEQ_STATIC_BYTES)
+        return fail(FLB_ERR_INVALID_ARG,
+                    "the step needs %zu bytes of noise work, the fixed device array holds %zu "
+                    "(%d x %d sites is more than 48 V <= %zu allows)",
+                    need, MODEQ_STATIC_BYTES, a.nx, a.ny, MODEQ_STATIC_BYTES);
+    const hipStream_t st = (hipStream_t)stream;
+    double* xi = nullptr;
+    if (a.kT > 0.0) {
+        void* work = nullptr;
+        if ((r = static_scratch(&work)) != FLB_OK) return r;
+        // every byte the noise kernels read is written first in the same call
+        // (spectra by the row transform, fields by the inverse), so nothing
+        // has to be cleared
+        const size_t V = (size_t)a.nx * a.ny;
         xi = (double*)((char*)work + 2 * V * sizeof(double2));
         HIP_TRY(launch_modeq_noise(a, p->precision, (uint32_t)step, 1, work, xi, st));
     }

@@ -93,6 +93,12 @@ class ModEq:
         call("flb_modeq_step", C.byref(self.c), _ptr(fin), _ptr(fout), int(n), _ptr(self.work),
              int(self.nbytes), _stream(stream))
 
+    def step_into_noalloc(self, fin, fout, n, stream=None):
+        """The step of ``step_into`` with the library's fixed device work
+        array (no work buffer; lattices of at most 349525 sites)."""
+        call("flb_modeq_step_noalloc", C.byref(self.c), _ptr(fin), _ptr(fout), int(n),
+             _stream(stream))
+
     def moments(self, out=None, stream=None):
         """Moment fields of the pulled populations: (9, ny, nx) float64."""
         if out is None:

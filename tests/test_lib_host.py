@@ -166,3 +166,26 @@ def test_modeq_entry_points_reject_bad_pointers():
             call(name, *args)
         assert e.value.status == -1, (name, e.value)   # FLB_ERR_INVALID_ARG: rejected on the host
 
+
+def test_modeq_noalloc_step_rejects_on_the_host():
+    """flb_modeq_step_noalloc checks its parameters, pointers and the size of
+    its fixed 16 MiB work array on the host, before any device call."""
+    import ctypes as C
+
+    from paper_1012_3632_amd._lib import FLBError, call
+    from paper_1012_3632_amd.modeq import ModEqParams
+    nbytes = C.c_size_t()
+    call("flb_modeq_static_work_bytes", C.byref(nbytes))
+    assert nbytes.value == 16 << 20
+    ok = ModEqParams(nx=8, ny=8, kT=1e-5, cs2_0=0.07, kappa=0.08)
+    A, B, odd = C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p((1 << 20) + 8)
+    big = ok.with_(nx=1024, ny=342)            # 48 V = 16.03 MiB
+    assert 48 * 1024 * 342 > nbytes.value
+    bad_calls = [
+        (ok.to_c(), None, B), (ok.to_c(), A, A), (ok.to_c(), odd, B),
+        (ok.with_(rate_bulk=2.5).to_c(), A, B), (big.to_c(), A, B),
+    ]
+    for p, fin, fout in bad_calls:
+        with pytest.raises(FLBError) as e:
+            call("flb_modeq_step_noalloc", C.byref(p), fin, fout, 0, None)
+        assert e.value.status == -1, e.value
