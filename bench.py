@@ -140,15 +140,17 @@ def bench_main(args):
                    "lattice": "D3Q19", "sites": V, "launch_config": run_cfg,
                    "launch_shape": list(sim.launch_shape(run_cfg)),
                    "in_place_pairs": pair_cfg >= 0},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        # in-place pairs keep one 159 MB population buffer, which stays largely
+        # resident in the 256 MB last-level (Infinity) cache: the rate is that
+        # of HBM and that cache together ("hbm+llc"); d3q19_256_ideal below is
+        # the same step on a state 8 times larger, bound by HBM alone
+        "roofline": {"bound": "hbm+llc" if pair_cfg >= 0 else "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_from_profiles(profile_key(sim.launch_shape(run_cfg))),
                      "kernel": ("k_step_ip<D3Q19,float,stats> (in-place pair, phases 0 and 1)"
                                 if pair_cfg >= 0 else "k_step<D3Q19,float,ideal,stats>"),
                      "bytes_per_site": bytes_site,
-                     # in-place pairs keep one population buffer: 159 MB, within the
-                     # 256 MB last-level (Infinity) cache, so the state stays largely
-                     # resident there and the rate can exceed a two-buffer HBM stream
                      "working_set_bytes": (1 if pair_cfg >= 0 else 2) * 19 * 4 * V},
         "wall_timed_s": round(wall, 3),
         "fdt": fdt,
@@ -177,6 +179,8 @@ def bench_main(args):
     out["roofline"]["measured_copy_GBps"] = round(copy_gbs, 1)
     out["roofline"]["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
     del a, b
+    torch.cuda.empty_cache()
+    out["d3q19_256_ideal"] = ideal_256(stream, copy_gbs)
     # FP64 step beside it
     p64 = p.with_(precision="fp64")
     s64 = Simulation(p64)
@@ -190,10 +194,134 @@ def bench_main(args):
     torch.cuda.empty_cache()
 
     if not args.no_extras:
+        out["fp32_vs_fp64"] = long_parity(stream)
         out.update(extras(args, stream))
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(kw)
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
+
+
+def ideal_256(stream, copy_gbs):
+    """The headline step on a 256^3 lattice (1.27 GB per FP32 population
+    buffer, five times the last-level cache): in-place pairs and two buffers,
+    statistics every step, against 8 TB/s, the measured copy rate and the
+    measured rate of a plain in-place pass over a buffer of the same size."""
+    import torch
+
+    import flb_workloads as W
+    from paper_1012_3632_amd import Params, Simulation
+    p = Params.from_dict(dict(W.params_of("d3q19_128", nx=256, ny=256, nz=256), precision="fp32"))
+    V = p.nx * p.ny * p.nz
+    sim = Simulation(p)
+    (_, best_stats, best_ip, _), tms = sim.autotune(repeats=3)
+    res = {"workload": "d3q19_128's parameters on 256^3 (16.8 M sites), FP32, FP64 statistics "
+                       "every step", "sites": V}
+    for name, cfg in (("in_place_pairs", best_ip), ("two_buffers", best_stats)):
+        if cfg < 0:
+            continue
+        sim.set_launch(cfg)
+        sim.step(40, stats_stride=1)
+        ms = time_steps(sim, 200, 1, stream)
+        gbs = 152 * V / (ms * 1e-3) / 1e9
+        res[name] = {"launch_config": cfg, "launch_shape": list(sim.launch_shape(cfg)),
+                     "ms_per_step": round(ms, 5), "MLUPS": round(V / (ms * 1e-3) / 1e6, 1),
+                     "achieved_GBps_152B": round(gbs, 1), "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4),
+                     "frac_of_measured_copy": round(gbs / copy_gbs, 4)}
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    # measured ceilings: a flat in-place pass (x *= 1, torch) over one buffer
+    # of the state's size, and the step's own access pattern without its
+    # arithmetic (19 planes read and written per site, in place and between
+    # two buffers: flb_plane_stream_probe)
+    import ctypes as C
+
+    from paper_1012_3632_amd._lib import call
+    n = 19 * V
+    a = torch.ones(n, device="cuda")
+    bb = torch.ones(n, device="cuda")
+
+    def rate(fn):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(20):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return 2 * n * 4 * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    sp = C.c_void_p(stream.cuda_stream)
+    pa, pb = C.c_void_p(a.data_ptr()), C.c_void_p(bb.data_ptr())
+    ip_gbs = rate(lambda: a.mul_(1.0))
+    pat_ip = rate(lambda: call("flb_plane_stream_probe", pa, pa, 19, V, 1, sp))
+    pat_two = rate(lambda: call("flb_plane_stream_probe", pa, pb, 19, V, 1, sp))
+    del a, bb
+    torch.cuda.empty_cache()
+    res["measured_inplace_pass_GBps"] = round(ip_gbs, 1)
+    res["measured_copy_GBps"] = round(copy_gbs, 1)
+    res["measured_19plane_pattern_GBps"] = {"in_place": round(pat_ip, 1), "two_buffers": round(pat_two, 1)}
+    if "in_place_pairs" in res:
+        g = res["in_place_pairs"]["achieved_GBps_152B"]
+        res["in_place_pairs"]["frac_of_measured_inplace_pass"] = round(g / ip_gbs, 4)
+        res["in_place_pairs"]["frac_of_19plane_pattern"] = round(g / pat_ip, 4)
+    if "two_buffers" in res:
+        res["two_buffers"]["frac_of_19plane_pattern"] = round(
+            res["two_buffers"]["achieved_GBps_152B"] / pat_two, 4)
+    res["roofline"] = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "kernel": "k_step_ip<D3Q19,float,stats> (in-place pair)"}
+    best = min((v for k, v in res.items() if k in ("in_place_pairs", "two_buffers")),
+               key=lambda v: v["ms_per_step"])
+    res["roofline"].update(achieved=best["achieved_GBps_152B"], frac=best["frac_of_8TBps"])
+    return res
+
+
+def long_parity(stream):
+    """FP32 against the FP64 GPU step over the full lengths of the two 3-D
+    workloads (d3q19_128: 2000 steps; d3q19_256_landau, eta = 0: 5000 steps),
+    from the same initial state: max |f32 - f64| / max |f64| on unshifted
+    populations and the RMS of the shifted difference over the RMS of delta f64."""
+    import torch
+
+    import flb_workloads as W
+    from paper_1012_3632_amd import Params, Simulation, lattice_tables
+    w = torch.as_tensor(lattice_tables("D3Q19")["w"], device="cuda").view(19, 1, 1, 1)
+    res = {}
+    for name, nsteps in (("d3q19_128", 2000), ("d3q19_256_landau", 5000)):
+        kw = W.params_of(name)
+        drho = (W.initial_drho((kw["nz"], kw["ny"], kw["nx"]), 7, W.WORKLOADS[name]["init_noise"])
+                if kw.get("force_model") else None)
+        st, t = {}, {}
+        for prec in ("fp64", "fp32"):
+            sim = Simulation(Params.from_dict(dict(kw, precision=prec)), drho_init=drho)
+            if prec == "fp32":
+                sim.autotune(repeats=2)
+            elif kw.get("force_model"):
+                sim.set_launch(7)    # z-marching force step, 128 x 2 columns
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            sim.step(nsteps, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            t[prec] = e0.elapsed_time(e1) / nsteps
+            st[prec] = sim.state().clone()
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+        d = st["fp32"].double() - st["fp64"]
+        fmax = (st["fp64"] + w * kw["rho0"]).abs().max()
+        res[name] = {"steps": nsteps,
+                     "max_rel_err_unshifted": float("%.3e" % float(d.abs().max() / fmax)),
+                     "rms_rel_err_shifted": float("%.3e" % float(
+                         torch.sqrt((d * d).mean()) / torch.sqrt((st["fp64"] ** 2).mean()))),
+                     "mass_fp32_minus_fp64": float("%.3e" % float(st["fp32"].double().sum() - st["fp64"].sum())),
+                     "ms_per_step_fp32": round(t["fp32"], 4), "ms_per_step_fp64": round(t["fp64"], 4)}
+        del st, d
+        torch.cuda.empty_cache()
+    return res
 
 
 def extras(args, stream):
@@ -219,6 +347,9 @@ def extras(args, stream):
     # (19 reads + 19 writes + the density): 80 + 156 = 236 B per site
     res["d3q19_256_landau"] = {"ms_per_step": round(ms, 4), "MLUPS": round(V / (ms * 1e-3) / 1e6, 1),
                                "hbm_frac_algorithmic_236B": round(236 * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                               # the method's minimum: populations in and out plus
+                               # one density write and read (152 + 8 B)
+                               "hbm_frac_algorithmic_160B": round(160 * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                "launch_config": cfg_stats, "launch_shape": list(s.launch_shape(cfg_stats)),
                                "statistics": "every step"}
     s.close()
@@ -235,8 +366,10 @@ def extras(args, stream):
     del s
     torch.cuda.empty_cache()
 
-    # 64 replicas of uneven size, one persistent launch per step, captured graph
-    from paper_1012_3632_amd import Batch
+    # 64 replicas of uneven size (the realised draw is tests/golden/
+    # d3q19_batch64_edges.json), one persistent launch per step, the
+    # workload's 1000 steps captured in one graph
+    from paper_1012_3632_amd import Batch, lattice_tables
     wl = W.WORKLOADS["d3q19_batch64"]
     edges = W.batch_edges(wl["replicas"], wl["edges"], wl["size_seed"])
     pb = Params.from_dict(dict(lattice="D3Q19", precision="fp32", rho0=1.0, kT=wl["kT"],
@@ -245,11 +378,12 @@ def extras(args, stream):
     b = Batch(pb, [(e, e, e) for e in edges], seeds=list(range(wl["replicas"])))
     (_, best), _ = b.autotune(repeats=3)
     pair_bytes, ngroups = b.pairs()
-    gsteps = 100
+    gsteps = wl["steps"]
 
-    def batch_graph_ms():
+    def batch_graph_ms(fdt=False):
         b.graph_capture(gsteps, stats_stride=1, stream=stream)
-        b.graph_launch(stream=stream)
+        b.graph_launch(stream=stream)          # warm-up and burn-in: 1000 steps
+        b.reset_stats(stream=stream)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -260,6 +394,14 @@ def extras(args, stream):
         return e0.elapsed_time(e1) / gsteps
 
     ms = batch_graph_ms()
+    # per-replica fluctuation-dissipation check on the timed steps
+    s1, s2, nsamp = b.moments()
+    Nn = lattice_tables("D3Q19")["N"]
+    vol = np.array([e ** 3 for e in edges], dtype=np.float64)[:, None]
+    cnt = vol * nsamp
+    ratio = (s2 / cnt - (s1 / cnt) ** 2)[:, 4:] / (pb.rho0 * pb.kT * Nn[4:] * 3.0)
+    fdt_b = {"samples": int(nsamp), "max_rel_dev_all_replicas_modes": round(float(np.abs(ratio - 1).max()), 5),
+             "max_rel_dev_replica_mean": round(float(np.abs(ratio.mean(1) - 1).max()), 5)}
     # the other schedule, for the record
     b.set_pairs(0 if pair_bytes else 128 << 20)
     ms_other = batch_graph_ms()
@@ -271,7 +413,9 @@ def extras(args, stream):
                             "in_place_pair_groups": ngroups, "pair_group_bytes": pair_bytes,
                             ("ms_per_step_replica_interleaved" if pair_bytes else
                              "ms_per_step_pairs_128MiB_groups"): round(ms_other, 4),
-                            "graph_steps": gsteps, "statistics": "every step"}
+                            "graph_steps": gsteps, "statistics": "every step", "fdt": fdt_b,
+                            "edges_file": "tests/golden/d3q19_batch64_edges.json",
+                            "count_by_edge": {str(e): edges.count(e) for e in wl["edges"]}}
     b.close()
     del b
     torch.cuda.empty_cache()
@@ -449,49 +593,81 @@ def extras(args, stream):
     w = torch.tensor([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, dtype=torch.float64).view(-1, 1, 1, 1)
     df0 = (w * torch.as_tensor(drho)).to("cuda", torch.float32)
     target = torch.ones(pa.shape, dtype=torch.float64, device="cuda")
-    times = []
-    for rep in range(3):
+    # HIP events on the launch stream around the forward (FLBRun.forward:
+    # the steps and the checkpoints) and the backward (seed, recompute,
+    # reverse sweep): median and range over 7 repeats after one warm-up
+    fwd, bwd = [], []
+    for rep in range(8):
         x = df0.clone().requires_grad_(True)
         rs = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
         kT = torch.tensor(pa.kT, dtype=torch.float64, requires_grad=True)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        e0.record(stream)
         rho = FLBRun.apply(x, rs, kT, pa, wl["steps"], wl["checkpoint_every"])
         L = ((rho - target) ** 2).mean()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        e1.record(stream)
         L.backward()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        times.append((t1 - t0, t2 - t1))
-    fwd, bwd = min(t[0] for t in times), min(t[1] for t in times)
-    res["d2q9_256_adjoint"] = {"forward_ms": round(fwd * 1e3, 3), "backward_ms": round(bwd * 1e3, 3),
-                               "adjoint_forward_ratio": round(bwd / fwd, 3), "steps": wl["steps"],
+        e2.record(stream)
+        e2.synchronize()
+        if rep:
+            fwd.append(e0.elapsed_time(e1))
+            bwd.append(e1.elapsed_time(e2))
+    ratios = sorted(b_ / f_ for f_, b_ in zip(fwd, bwd))
+    res["d2q9_256_adjoint"] = {"forward_ms_median": round(float(np.median(fwd)), 3),
+                               "backward_ms_median": round(float(np.median(bwd)), 3),
+                               "adjoint_forward_ratio": round(float(np.median(ratios)), 3),
+                               "ratio_range": [round(ratios[0], 3), round(ratios[-1], 3)],
+                               "repeats": len(ratios), "steps": wl["steps"],
                                "checkpoint_every": wl["checkpoint_every"]}
     return res
 
 
-def cpu_baseline(kw):
-    """The FP64 oracle on the host cores, on a bounded sample of the workload:
-    full-size steps of the 128^3 lattice until about 10 s of CPU time (at
-    least two)."""
+def cpu_baseline():
+    """The FP64 oracle on the host cores, on bounded samples of the workloads,
+    with all the threads torch uses and with one: d3q19_128 (the headline
+    workload; full-size steps until about 8 s of wall time, at least one),
+    d2q9_32_fp64 (200 steps) and d2q9_256_adjoint (the forward step, 10 steps).
+    ``value`` is the d3q19_128 figure with all threads."""
+    import os as _os
+
     import torch
 
+    import flb_workloads as W
     from oracle import flb
-    po = flb.Params(**{k: v for k, v in kw.items() if k in flb.Params.__dataclass_fields__})
-    S = flb.initial_state(po)
-    S = flb.step(S, 0, po)   # untimed first step (allocator warm-up)
-    nsteps = 0
-    t0 = time.perf_counter()
-    while nsteps < 2 or time.perf_counter() - t0 < 10.0:
-        nsteps += 1
-        S = flb.step(S, nsteps, po)
-    dt = time.perf_counter() - t0
-    V = po.nx * po.ny * po.nz
-    return {"value": round(V * nsteps / dt / 1e6, 3), "unit": "MLUPS",
-            "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{nsteps} full-size steps of d3q19_128 (FP64 torch/numpy oracle), "
-                      f"{dt:.1f} s"}
+
+    def mlups(name, min_steps, seconds):
+        kw = W.params_of(name)
+        po = flb.Params(**{k: v for k, v in kw.items() if k in flb.Params.__dataclass_fields__})
+        drho = (W.initial_drho((po.nz, po.ny, po.nx), 7, W.WORKLOADS[name]["init_noise"])
+                if po.force_model else None)
+        S = flb.initial_state(po, drho)
+        S = flb.step(S, 0, po)   # untimed first step (allocator warm-up)
+        n = 0
+        t0 = time.perf_counter()
+        while n < min_steps or time.perf_counter() - t0 < seconds:
+            n += 1
+            S = flb.step(S, n, po)
+        dt = time.perf_counter() - t0
+        return V_of(po) * n / dt / 1e6, n, dt
+
+    V_of = lambda po: po.nx * po.ny * po.nz
+    all_threads = torch.get_num_threads()
+    res = {}
+    for threads in (all_threads, 1):
+        torch.set_num_threads(threads)
+        for name, mn, sec in (("d3q19_128", 1, 8.0 if threads > 1 else 0.0),
+                              ("d2q9_32_fp64", 200, 0.0), ("d2q9_256_adjoint", 10, 0.0)):
+            v, n, dt = mlups(name, mn, sec)
+            res[f"{name}_{threads}thr"] = {"MLUPS": round(v, 4), "steps": n, "s": round(dt, 2)}
+    torch.set_num_threads(all_threads)
+    return {"value": res[f"d3q19_128_{all_threads}thr"]["MLUPS"], "unit": "MLUPS",
+            "cores": all_threads, "kind": "oracle",
+            "sample": "full-size d3q19_128 steps of the FP64 torch/numpy oracle, "
+                      f"{res[f'd3q19_128_{all_threads}thr']['steps']} steps on {all_threads} threads "
+                      f"(host has {_os.cpu_count()} CPUs); per-workload figures at all threads and at "
+                      "one thread in 'workloads'",
+            "workloads": res}
 
 
 def main():
@@ -510,6 +686,9 @@ def main():
                     help="only time a plain in-place elementwise pass over buffers of 32 MB to 1 GiB")
     ap.add_argument("--profile-step", choices=["fp32", "fp64"],
                     help="only run the d3q19_128 step (fixed launch shape, statistics on)")
+    ap.add_argument("--profile-256", action="store_true",
+                    help="only run the d3q19_128 step on 256^3 (FP32, statistics every step): "
+                         "in-place pairs (128 x 2) and two buffers (128 x 2), 20 steps each")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -523,6 +702,8 @@ def main():
         profile_modeq(args.profile_modeq)
     elif args.profile_step:
         profile_step(args)
+    elif args.profile_256:
+        profile_256()
     else:
         bench_main(args)
 
@@ -592,6 +773,22 @@ def profile_step(args):
         sim.step(args.steps, stats_stride=0)
     torch.cuda.synchronize()
     print(json.dumps({"profile_step": args.profile_step, "configs": n, "steps_each": args.steps}))
+
+
+def profile_256():
+    """The 256^3 ideal-gas step in its in-place pair and two-buffer shapes
+    (launch configurations 10 and 1: 128 x 2 tiles), for kernel traces."""
+    import torch
+
+    import flb_workloads as W
+    from paper_1012_3632_amd import Params, Simulation
+    p = Params.from_dict(dict(W.params_of("d3q19_128", nx=256, ny=256, nz=256), precision="fp32"))
+    sim = Simulation(p)
+    for cfg in (10, 1):
+        sim.set_launch(cfg)
+        sim.step(20, stats_stride=1)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_256": [10, 1], "steps_each": 20}))
 
 
 if __name__ == "__main__":

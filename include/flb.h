@@ -65,7 +65,7 @@ typedef enum {
     FLB_OK = 0,
     FLB_ERR_INVALID_ARG = -1, /* a parameter, size or pointer was rejected     */
     FLB_ERR_HIP = -2,         /* a HIP runtime call failed                      */
-    FLB_ERR_NONFINITE = -3,   /* statistics contain NaN or Inf                  */
+    FLB_ERR_NONFINITE = -3,   /* a population or the statistics became NaN/Inf  */
     FLB_ERR_UNSUPPORTED = -4, /* combination not implemented                   */
     FLB_ERR_STATE = -5        /* call not valid in the handle's current state   */
 } flb_status;
@@ -127,6 +127,18 @@ flb_status flb_init(const flb_params* p, void* f_a, void* f_b, void* scratch, vo
  * Returns FLB_ERR_INVALID_ARG for nsteps < 0 or stats_stride < 0 (nothing
  * queued), FLB_ERR_HIP if a launch fails.  Asynchronous. */
 flb_status flb_step(flb_handle* h, int64_t nsteps, int32_t stats_stride, void* stream);
+
+/* Failure detection.  Every step's collision sets a device flag of the
+ * handle when the density it pulled at a site (the sum of the site's Q
+ * populations after streaming, Sec. V eq. lbe-moments) is NaN or Inf, so a
+ * non-finite population anywhere is seen within one step.  With every > 0,
+ * flb_step runs its steps in chunks of `every`, reads the flag after each
+ * chunk (synchronizing the stream) and returns FLB_ERR_NONFINITE as soon as
+ * it is set, with the step counter at the end of that chunk; every = 0
+ * (the default) turns the reads off, and flb_step stays asynchronous.  The
+ * flag is sticky; this call clears it (asynchronously on `stream`).
+ * FLB_ERR_INVALID_ARG for every < 0. */
+flb_status flb_set_check(flb_handle* h, int64_t every, void* stream);
 
 /* Current state: *cur receives the device buffer holding S_n, *other the
  * second buffer, *step the index n of the next step.  Host only. */
@@ -429,6 +441,9 @@ flb_status flb_batch_step(flb_batch* b, int64_t nsteps, int32_t stats_stride, vo
 flb_status flb_batch_moments(flb_batch* b, double* mode_sum, double* mode_sumsq,
                              int64_t* nsamples, void* stream);
 
+/* Zero the per-replica statistics and the sample count.  Asynchronous. */
+flb_status flb_batch_reset_stats(flb_batch* b, void* stream);
+
 flb_status flb_batch_state(const flb_batch* b, void** cur, void** other, uint64_t* step);
 /* As flb_graph_capture / flb_graph_launch, for the batch (one recording per
  * current buffer; the schedule in force at capture is kept). */
@@ -501,6 +516,16 @@ flb_status flb_batch_autotune(flb_batch* b, int32_t repeats, int32_t* best, doub
 flb_status flb_batch_set_pairs(flb_batch* b, uint64_t pair_bytes);
 /* The current pair_bytes and number of groups (0 when off).  Host only. */
 flb_status flb_batch_pairs(const flb_batch* b, uint64_t* pair_bytes, int32_t* ngroups);
+
+/* Calibration of the HBM roofline of the step kernels: `repeats` launches
+ * that each read q FP32 planes of V elements (plane stride V, the population
+ * layout) and write them back scaled by 1, one thread per site, to b (b = a:
+ * in place, the pattern of an in-place pair; b != a: the two-buffer
+ * pattern).  Moves 8 q V bytes per launch and does no arithmetic of the
+ * method.  a, b: device, 4 q V bytes each.  FLB_ERR_INVALID_ARG unless q is 9
+ * or 19, 0 < V < 2^31 and repeats >= 1.  Asynchronous. */
+flb_status flb_plane_stream_probe(const void* a, void* b, int32_t q, uint64_t V, int32_t repeats,
+                                  void* stream);
 
 /* Text of a status code; last error text (thread-local) with HIP details. */
 const char* flb_strerror(flb_status s);

@@ -63,6 +63,7 @@ PROTOS = {
     "flb_query_sizes": [P(flb_params), P(C.c_size_t), P(C.c_size_t), P(C.c_size_t)],
     "flb_init": [P(flb_params), vp, vp, vp, vp, vp, vp, P(vp)],
     "flb_step": [vp, C.c_int64, C.c_int32, vp],
+    "flb_set_check": [vp, C.c_int64, vp],
     "flb_state": [vp, P(vp), P(vp), P(C.c_uint64)],
     "flb_seek": [vp, C.c_uint64, vp],
     "flb_moments": [vp, P(C.c_double), P(C.c_double), P(C.c_int64), vp],
@@ -93,6 +94,7 @@ PROTOS = {
     "flb_batch_step": [vp, C.c_int64, C.c_int32, vp],
     "flb_batch_moments": [vp, P(C.c_double), P(C.c_double), P(C.c_int64), vp],
     "flb_batch_state": [vp, P(vp), P(vp), P(C.c_uint64)],
+    "flb_batch_reset_stats": [vp, vp],
     "flb_batch_graph_capture": [vp, C.c_int64, C.c_int32, vp],
     "flb_batch_graph_launch": [vp, vp],
     "flb_batch_destroy": [vp],
@@ -111,6 +113,7 @@ PROTOS = {
     "flb_modeq_run": [P(flb_modeq_params), vp, vp, C.c_uint64, C.c_int32, vp, C.c_size_t, vp],
     "flb_modeq_noise": [P(flb_modeq_params), C.c_uint64, vp, vp, C.c_size_t, vp],
     "flb_modeq_moments": [P(flb_modeq_params), vp, vp, vp],
+    "flb_plane_stream_probe": [vp, vp, C.c_int32, C.c_uint64, C.c_int32, vp],
     "flb_modeq_step_noalloc": [P(flb_modeq_params), vp, vp, C.c_uint64, vp],
     "flb_modeq_static_work_bytes": [P(C.c_size_t)],
 }

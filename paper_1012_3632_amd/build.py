@@ -14,7 +14,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libflb.so")
-SOURCES = ["kernels.hip", "adjoint.hip", "batch.hip", "spectrum.hip", "modeq.hip", "api.hip"]
+SOURCES = ["kernels.hip", "adjoint.hip", "batch.hip", "spectrum.hip", "modeq.hip", "api.hip",
+           "probe.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

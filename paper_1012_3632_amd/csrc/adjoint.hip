@@ -393,6 +393,7 @@ static CollideParams<Real> adj_collide_params(const StepSpec& s) {
     P.key0 = s.key0;
     P.key1 = s.key1;
     P.replica = s.replica;
+    P.nonfinite = nullptr;
     return P;
 }
 

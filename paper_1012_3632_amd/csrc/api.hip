@@ -42,7 +42,8 @@ flb_status fail(flb_status s, const char* fmt, ...) {
 
 constexpr double CS2 = 1.0 / 3.0;
 constexpr size_t ALIGN = 256;
-constexpr size_t SCRATCH_HEADER = 256;   // step counter for graph replays
+constexpr size_t SCRATCH_HEADER = 256;   // step counter for graph replays, non-finite flag
+constexpr size_t NONFINITE_OFF = 64;     // byte offset of the non-finite flag in the header
 
 int lattice_q(int lat) { return lat == FLB_D2Q9 ? 9 : 19; }
 int lattice_d(int lat) { return lat == FLB_D2Q9 ? 2 : 3; }
@@ -152,6 +153,7 @@ struct flb_handle {
     int cfg;                // launch shape of steps without statistics
     int cfg_stats;          // launch shape of steps that accumulate statistics
     int pair_cfg;           // in-place shape for pairs of steps, or -1
+    int64_t check_every;    // > 0: flb_step reads the non-finite flag every this many steps
     // captured steps, one graph per current buffer (index cur_a): kernel
     // arguments hold the buffer pointers, so a replay must start from the
     // buffer its graph was recorded for
@@ -205,16 +207,18 @@ flb_status do_step(flb_handle* h, bool sample, const unsigned long long* step_de
     return FLB_OK;
 }
 
+// Steps k = 0 .. nsteps - 1 of a call whose first k0 steps already ran; a
+// step is sampled when (k0 + k + 1) % stride == 0.
 flb_status run_steps(flb_handle* h, int64_t nsteps, int32_t stride, bool graph_mode,
-                     hipStream_t st, int64_t* samples) {
+                     hipStream_t st, int64_t* samples, int64_t k0 = 0) {
     int64_t ns = 0;
     const unsigned long long* dev = graph_mode ? h->step_dev : nullptr;
     const unsigned long long base = graph_mode ? 0ull : (unsigned long long)h->step;
     for (int64_t k = 0; k < nsteps;) {
-        const bool sample = stride > 0 && ((k + 1) % stride) == 0;
+        const bool sample = stride > 0 && ((k0 + k + 1) % stride) == 0;
         if (h->pair_cfg >= 0 && k + 1 < nsteps) {
             // two steps in place on the current buffer (no swap)
-            const bool sample1 = stride > 0 && ((k + 2) % stride) == 0;
+            const bool sample1 = stride > 0 && ((k0 + k + 2) % stride) == 0;
             HIP_TRY(launch_step_in_place(h->spec, h->pair_cfg, 0, h->cur(), dev,
                                          base + (unsigned long long)k,
                                          sample ? h->stats : nullptr, st));
@@ -328,6 +332,8 @@ flb_status flb_init(const flb_params* p, void* f_a, void* f_b, void* scratch, vo
     size_t drho_off, adj_off, gp_off, total;
     scratch_layout(h->spec, h->V, h->real_bytes, &drho_off, &adj_off, &gp_off, &total);
     h->step_dev = (unsigned long long*)h->scratch;
+    h->spec.nonfinite = (uint32_t*)(h->scratch + NONFINITE_OFF);
+    h->check_every = 0;
     h->drho = h->scratch + drho_off;
     h->adj_work = h->scratch + adj_off;
     h->gpartial = (double*)(h->scratch + gp_off);
@@ -351,13 +357,39 @@ flb_status flb_step(flb_handle* h, int64_t nsteps, int32_t stats_stride, void* s
     if (nsteps < 0 || stats_stride < 0)
         return fail(FLB_ERR_INVALID_ARG, "nsteps %lld, stats_stride %d", (long long)nsteps,
                     stats_stride);
-    int64_t ns = 0;
-    flb_status r = run_steps(h, nsteps, stats_stride, false, (hipStream_t)stream, &ns);
-    if (r != FLB_OK) return r;
-    h->step += (uint64_t)nsteps;
-    h->nsamples += ns;
+    hipStream_t st = (hipStream_t)stream;
+    // without checks one chunk; with checks, chunks of check_every steps, the
+    // device flag read (and the stream synchronized) after each
+    const int64_t chunk = h->check_every > 0 ? h->check_every : (nsteps > 0 ? nsteps : 1);
+    for (int64_t k0 = 0; k0 < nsteps; k0 += chunk) {
+        const int64_t n = nsteps - k0 < chunk ? nsteps - k0 : chunk;
+        int64_t ns = 0;
+        flb_status r = run_steps(h, n, stats_stride, false, st, &ns, k0);
+        if (r != FLB_OK) return r;
+        h->step += (uint64_t)n;
+        h->nsamples += ns;
+        if (h->check_every > 0) {
+            uint32_t flag = 0;
+            HIP_TRY(hipMemcpyAsync(&flag, h->spec.nonfinite, sizeof flag, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (flag) {
+                HIP_TRY(launch_set_u64(h->step_dev, h->step, st));
+                return fail(FLB_ERR_NONFINITE,
+                            "a non-finite density was pulled by a step before step %llu",
+                            (unsigned long long)h->step);
+            }
+        }
+    }
     // keep the device step counter in step with the host (graph replays read it)
-    HIP_TRY(launch_set_u64(h->step_dev, h->step, (hipStream_t)stream));
+    HIP_TRY(launch_set_u64(h->step_dev, h->step, st));
+    return FLB_OK;
+}
+
+flb_status flb_set_check(flb_handle* h, int64_t every, void* stream) {
+    if (!h) return fail(FLB_ERR_INVALID_ARG, "handle is NULL");
+    if (every < 0) return fail(FLB_ERR_INVALID_ARG, "every = %lld < 0", (long long)every);
+    h->check_every = every;
+    HIP_TRY(launch_fill_zero(h->spec.nonfinite, sizeof(uint32_t), (hipStream_t)stream));
     return FLB_OK;
 }
 

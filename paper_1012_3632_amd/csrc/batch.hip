@@ -413,6 +413,7 @@ CollideParams<Real> batch_collide_params(const flb_batch* b) {
     P.noise_local = p.noise_rho_local ? 1 : 0;
     P.key0 = P.key1 = 0;   // per replica
     P.replica = 0;
+    P.nonfinite = nullptr;
     return P;
 }
 
@@ -653,6 +654,15 @@ flb_status flb_batch_moments(flb_batch* b, double* mode_sum, double* mode_sumsq,
     if (nsamples) *nsamples = b->nsamples;
     for (double v : host)
         if (!std::isfinite(v)) return bfail(FLB_ERR_NONFINITE, "statistics are not finite");
+    return FLB_OK;
+}
+
+flb_status flb_batch_reset_stats(flb_batch* b, void* stream) {
+    if (!b) return bfail(FLB_ERR_INVALID_ARG, "batch is NULL");
+    // the per-chunk table is clear between calls; the accumulators follow it
+    BHIP(launch_fill_zero(batch_acc(b), (size_t)b->nrep * 2 * b->q * sizeof(double),
+                          (hipStream_t)stream));
+    b->nsamples = 0;
     return FLB_OK;
 }
 

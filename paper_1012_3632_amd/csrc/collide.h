@@ -34,6 +34,7 @@ struct CollideParams {
     int32_t noise_on;   // kT > 0
     int32_t noise_local;
     uint32_t key0, key1, replica;
+    uint32_t* nonfinite;  // set to 1 when a site's pulled density is not finite (nullable)
 };
 
 template <int LAT, typename Real>
@@ -361,6 +362,10 @@ __device__ __forceinline__ void collide_moments(Real (&m)[Lattice<LAT>::Q],
     using L = Lattice<LAT>;
     using S = Stress<LAT, Real>;
     constexpr int D = L::D;
+    // every population of the site enters m_0, so a NaN or Inf pulled into
+    // the site shows here (a plain vector store of the same value from any
+    // number of lanes)
+    if (P.nonfinite && !__builtin_isfinite(m[0])) *P.nonfinite = 1u;
     const Real rho = P.rho0 + m[0];
     const Real inv_rho = Real(1) / rho;
     Real u[D];

@@ -45,6 +45,7 @@ struct StepSpec {
     int noise_on, noise_local;
     uint32_t key0, key1, replica;
     double a, b, rho_c, kappa, eta;
+    uint32_t* nonfinite;   // device flag the collision sets on a non-finite density, or null
 };
 
 // Record the text returned by flb_last_error() (api.hip).

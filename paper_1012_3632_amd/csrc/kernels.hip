@@ -455,6 +455,7 @@ static CollideParams<Real> collide_params(const StepSpec& s) {
     P.key0 = s.key0;
     P.key1 = s.key1;
     P.replica = s.replica;
+    P.nonfinite = s.nonfinite;
     return P;
 }
 

@@ -195,6 +195,12 @@ class Simulation:
     def step(self, nsteps, stats_stride=0, stream=None):
         call("flb_step", self.handle, int(nsteps), int(stats_stride), _stream(stream))
 
+    def set_check(self, every, stream=None):
+        """every > 0: step() reads the library's non-finite flag every
+        ``every`` steps and raises FLBError (FLB_ERR_NONFINITE) once a NaN or
+        Inf population has been pulled; 0 turns the reads off.  Clears the flag."""
+        call("flb_set_check", self.handle, int(every), _stream(stream))
+
     def seek(self, step, stream=None):
         """Set the index of the next step (noise counter) without touching the state."""
         call("flb_seek", self.handle, int(step), _stream(stream))
@@ -458,6 +464,9 @@ class Batch:
         n = C.c_int64()
         call("flb_batch_moments", self._h, s, s2, C.byref(n), _stream(stream))
         return (np.array(s[:]).reshape(self.nrep, q), np.array(s2[:]).reshape(self.nrep, q), n.value)
+
+    def reset_stats(self, stream=None):
+        call("flb_batch_reset_stats", self._h, _stream(stream))
 
     def replica_state(self, r):
         """View of replica r's shifted populations, shape (q, nz, ny, nx)."""

@@ -104,13 +104,21 @@ def test_statistics_every_launch_d3q19(precision):
             np.testing.assert_allclose(s2, st["sumsq"], rtol=1e-11, err_msg=str(launch))
             np.testing.assert_allclose(s, st["sum"], rtol=1e-9, atol=1e-10, err_msg=str(launch))
         else:
-            # FP32 moments are summed in FP32 per thread before the FP64 reduction
+            # FP32 moments are summed in FP32 per 16-lane row before the FP64
+            # reduction.  Each of the N = sites x samples terms of a mode sum is
+            # off by ~1e-7 of its own size (FP32 storage of the shifted state and
+            # the row sums), so by Cauchy-Schwarz the sum is off by at most
+            # ~1e-7 sqrt(N sum m^2); bound it at 5e-6 sqrt(N sum m^2) against the
+            # oracle (the sums themselves are ~sqrt(N) times larger than that
+            # bound's scale for these zero-mean modes)
             np.testing.assert_allclose(s2, st["sumsq"], rtol=5e-5, err_msg=str(launch))
+            N = kw["nx"] * kw["ny"] * kw["nz"] * ns
+            bound = 5e-6 * np.sqrt(N * st["sumsq"])
+            assert np.all(np.abs(s - st["sum"]) <= bound), (launch, np.abs(s - st["sum"]) / bound)
             if ref is None:
                 ref = (s, s2)
+            # every launch shape sums the same FP32 values (bitwise equal states)
             np.testing.assert_allclose(s2, ref[1], rtol=1e-6, err_msg=str(launch))
-            np.testing.assert_allclose(s, ref[0], rtol=1e-5, atol=1e-6 * np.abs(ref[0]).max(),
-                                       err_msg=str(launch))
         sim.close()
 
 
@@ -258,6 +266,46 @@ def test_graph_replay_after_an_odd_step(pairs):
     assert na == nb == 10
     np.testing.assert_array_equal(sa, sb)
     np.testing.assert_array_equal(qa, qb)
+
+
+@pytest.mark.parametrize("kind", ["d3q19_ideal_pairs", "d3q19_landau_march", "d2q9_landau_fused"])
+def test_nonfinite_population_is_reported(kind):
+    """A NaN written into one population from the host: with checks on,
+    flb_step returns FLB_ERR_NONFINITE within the chunk that pulls it; with
+    checks off it stays asynchronous and returns FLB_OK; after the state is
+    reloaded and the flag cleared, steps succeed again."""
+    from paper_1012_3632_amd import Simulation
+    from paper_1012_3632_amd._lib import FLBError
+    if kind == "d3q19_ideal_pairs":
+        kw = dict(C2, precision="fp32", nx=64, ny=10, nz=6)
+    elif kind == "d3q19_landau_march":
+        kw = dict(C2, **LANDAU, precision="fp32", nx=64, ny=12, nz=20, kT=1e-6)
+    else:
+        kw = dict(W.params_of("d2q9_256_adjoint", nx=40, ny=24), precision="fp64")
+    sim = Simulation(gpu_params(**kw))
+    n, _ = sim.launch_configs()
+    if kind == "d3q19_ideal_pairs":
+        sim.set_launch([c for c in range(n) if sim.launch_shape(c)[6]][0])
+    elif kind == "d3q19_landau_march":
+        sim.set_launch([c for c in range(n) if sim.launch_shape(c)[5]][0])
+    sim.set_check(4)
+    sim.step(8, stats_stride=1)
+    good = sim.state().clone()
+    torch.cuda.synchronize()
+    bad = sim.state()
+    bad.view(-1)[bad.numel() // 3] = float("nan")
+    with pytest.raises(FLBError) as e:
+        sim.step(10, stats_stride=1)
+    assert e.value.status == -3
+    assert sim.step_index == 12        # stopped after the first chunk of 4
+    # reads off: asynchronous, no error
+    sim.set_check(0)
+    sim.step(3)
+    torch.cuda.synchronize()
+    sim.load_state(good)
+    sim.set_check(1)                   # clears the flag
+    sim.step(5)
+    assert np.isfinite(sim.state().cpu().numpy()).all()
 
 
 def test_resume_is_bit_exact():

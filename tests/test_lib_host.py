@@ -189,3 +189,18 @@ def test_modeq_noalloc_step_rejects_on_the_host():
         with pytest.raises(FLBError) as e:
             call("flb_modeq_step_noalloc", C.byref(p), fin, fout, 0, None)
         assert e.value.status == -1, e.value
+
+
+def test_batch64_edge_file_is_the_draw():
+    """tests/golden/d3q19_batch64_edges.json holds the replica edges the
+    batched workload draws (the realised list of the 64-replica run)."""
+    import json
+    import os
+
+    import flb_workloads as W
+    wl = W.WORKLOADS["d3q19_batch64"]
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "d3q19_batch64_edges.json")))
+    edges = W.batch_edges(wl["replicas"], wl["edges"], wl["size_seed"])
+    assert d["edges"] == edges and len(edges) == 64
+    assert d["sites"] == sum(e ** 3 for e in edges)
