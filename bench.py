@@ -92,7 +92,8 @@ def profile_key(shape):
     table (an in-place shape has one entry per phase of a pair)."""
     tx, ty, tz, spt, nt, _, ip, _ = shape
     if ip:
-        return ["k_step_ip_d3q19_fp32_stats_%dx%d_ph%d" % (tx, ty, ph) for ph in (0, 1)]
+        sp = "x%d" % spt if spt > 1 else ""
+        return ["k_step_ip_d3q19_fp32_stats_%dx%d%s_ph%d" % (tx, ty, sp, ph) for ph in (0, 1)]
     return ["k_step_d3q19_fp32_stats_%dx%dx%dx%d%s" % (tx, ty, tz, spt, "_nt" if nt else "")]
 
 

@@ -491,7 +491,7 @@ flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape)
 /* The same for a batch: the candidates are persistent grids of 8, 4, 16 or 2
  * blocks per compute unit; best[2] / best_ms[2] as for flb_autotune.  It then
  * times in-place pairs group by group (flb_batch_set_pairs) with groups of up
- * to 64, 128 and 192 MiB on each of the four grids, with statistics, and keeps
+ * to 64, 128, 160, 192, 224, 256 and 320 MiB on each of the four grids, with statistics, and keeps
  * the fastest (budget and grid) if it beats
  * the ordinary step with statistics (else turns pairs off).  The statistics
  * trials add only to the per-chunk table, which is clear between calls and

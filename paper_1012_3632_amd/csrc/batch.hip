@@ -56,6 +56,28 @@ struct RepInfo {
 
 __device__ __forceinline__ uint32_t div_small(uint32_t s, uint32_t inv) { return __umulhi(s, inv); }
 
+// Population accesses of one replica: one base pointer (rep) and 32-bit
+// element offsets i V + site (a replica's populations stay below 2^31
+// elements: V < 2^24 sites).  V is made opaque to the compiler by the
+// caller once per tile, so that the Q plane offsets are formed next to their
+// accesses instead of being hoisted out of the tile loop as Q separate
+// 64-bit plane bases (which spill).
+template <int LAT, typename Real>
+__device__ __forceinline__ void rep_pull(const Real* rep, uint32_t V, int x, int y, int z,
+                                         const RepInfo& R, Real (&f)[Lattice<LAT>::Q]) {
+    using L = Lattice<LAT>;
+    const int xm = x == 0 ? R.nx - 1 : x - 1, xp = x == R.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? R.ny - 1 : y - 1, yp = y == R.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? R.nz - 1 : z - 1, zp = z == R.nz - 1 ? 0 : z + 1;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int sx = L::cx[i] == 0 ? x : (L::cx[i] > 0 ? xm : xp);
+        const int sy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? ym : yp);
+        const int sz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zm : zp);
+        f[i] = plane_ld(rep, (uint32_t)i * V + (uint32_t)((sz * R.ny + sy) * R.nx + sx));
+    }
+}
+
 template <int LAT, typename Real, bool STATS>
 __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
                                                    Real* __restrict__ fout,
@@ -73,11 +95,6 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
     for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x, ++it) {
         const uint32_t r = chunk_rep[c];
         const RepInfo R = reps[r];
-        Geom g;
-        g.nx = R.nx;
-        g.ny = R.ny;
-        g.nz = R.nz;
-        g.V = R.V;
         const uint32_t s0 = (c - R.chunk0) * (uint32_t)BT;
         const uint32_t ds = R.nchunks * (uint32_t)BT;
         Real v[STATS ? 2 * Q : 1];
@@ -88,6 +105,8 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
 #pragma unroll 1
         for (int tt = 0; tt < CH; ++tt) {
             if (s0 + (uint32_t)tt * ds >= R.V) break;   // chunk with fewer tiles (uniform)
+            uint32_t Vr = R.V;
+            asm volatile("" : "+s"(Vr));
             const uint32_t s = s0 + (uint32_t)tt * ds + threadIdx.x;
             if (s < R.V) {
                 const uint32_t yz = div_small(s, R.inv_nx);
@@ -95,7 +114,7 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
                 const uint32_t z = div_small(yz, R.inv_ny);
                 const int y = (int)(yz - z * (uint32_t)R.ny);
                 Real f[Q], m[Q];
-                pull<LAT, Real>(fin + R.off, x, y, (int)z, g, f);
+                rep_pull<LAT, Real>(fin + R.off, Vr, x, y, (int)z, R, f);
                 M::forward(f, m);
                 if constexpr (STATS) {
 #pragma unroll
@@ -111,7 +130,7 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
                 M::inverse(m, f);
                 Real* out = fout + R.off;
 #pragma unroll
-                for (int i = 0; i < Q; ++i) out[(size_t)i * R.V + s] = f[i];
+                for (int i = 0; i < Q; ++i) plane_st(out, (uint32_t)i * Vr + s, f[i]);
             }
         }
         // the two LDS buffers alternate: the barrier inside the finish of
@@ -145,11 +164,6 @@ __global__ __launch_bounds__(BT) void k_batch_step_ip(Real* f, const RepInfo* __
     for (uint32_t c = c0 + blockIdx.x; c < c1; c += gridDim.x, ++it) {
         const uint32_t r = chunk_rep[c];
         const RepInfo R = reps[r];
-        Geom g;
-        g.nx = R.nx;
-        g.ny = R.ny;
-        g.nz = R.nz;
-        g.V = R.V;
         const uint32_t s0 = (c - R.chunk0) * (uint32_t)BT;
         const uint32_t ds = R.nchunks * (uint32_t)BT;
         Real* base = f + R.off;
@@ -161,6 +175,8 @@ __global__ __launch_bounds__(BT) void k_batch_step_ip(Real* f, const RepInfo* __
 #pragma unroll 1
         for (int tt = 0; tt < CH; ++tt) {
             if (s0 + (uint32_t)tt * ds >= R.V) break;   // chunk with fewer tiles (uniform)
+            uint32_t Vr = R.V;
+            asm volatile("" : "+s"(Vr));
             const uint32_t s = s0 + (uint32_t)tt * ds + threadIdx.x;
             if (s < R.V) {
                 const uint32_t yz = div_small(s, R.inv_nx);
@@ -169,10 +185,11 @@ __global__ __launch_bounds__(BT) void k_batch_step_ip(Real* f, const RepInfo* __
                 const int y = (int)(yz - z * (uint32_t)R.ny);
                 Real fl[Q], m[Q];
                 if constexpr (PH == 0) {
-                    pull<LAT, Real>(base, x, y, (int)z, g, fl);
+                    rep_pull<LAT, Real>(base, Vr, x, y, (int)z, R, fl);
                 } else {
+                    // local accesses: uniform plane bases, one lane offset
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) fl[i] = base[(size_t)L::opp[i] * R.V + s];
+                    for (int i = 0; i < Q; ++i) fl[i] = plane_ld(base + (size_t)L::opp[i] * R.V, s);
                 }
                 M::forward(fl, m);
                 if constexpr (STATS) {
@@ -195,11 +212,11 @@ __global__ __launch_bounds__(BT) void k_batch_step_ip(Real* f, const RepInfo* __
                         yy = yy < 0 ? yy + R.ny : (yy >= R.ny ? yy - R.ny : yy);
                         zz = zz < 0 ? zz + R.nz : (zz >= R.nz ? zz - R.nz : zz);
                         const uint32_t t = (uint32_t)xx + (uint32_t)R.nx * ((uint32_t)yy + (uint32_t)R.ny * (uint32_t)zz);
-                        base[(size_t)L::opp[i] * R.V + t] = fl[i];
+                        plane_st(base, (uint32_t)L::opp[i] * Vr + t, fl[i]);
                     }
                 } else {
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) base[(size_t)i * R.V + s] = fl[i];
+                    for (int i = 0; i < Q; ++i) plane_st(base + (size_t)i * R.V, s, fl[i]);
                 }
             }
         }
@@ -767,7 +784,7 @@ flb_status flb_batch_autotune(flb_batch* b, int32_t repeats, int32_t* best, doub
         uint64_t best_bytes = 0;
         int best_cfg = b->pair_cfg;
         float best_pair = bt[1];
-        for (uint64_t mib : {64ull, 128ull, 192ull}) {
+        for (uint64_t mib : {64ull, 128ull, 160ull, 192ull, 224ull, 256ull, 320ull}) {
             const std::vector<BatchGroup> groups = batch_groups(b, mib << 20);
             for (int c = 0; c < N_GRID_CFG; ++c) {
                 BHIP(hipEventRecord(e0, st));

@@ -12,6 +12,22 @@ namespace flb {
 
 // ------------------------------------------------------------------ helpers
 
+// The FP64 noise angle table for a block of NT threads: a copy of
+// SINCOS_TABLE in LDS (8 KB, filled here, one barrier), or, for FP32 (which
+// does not use it), the global table untouched.  All threads of the block
+// must call it.
+template <typename Real, int NT>
+__device__ __forceinline__ const double2* noise_table() {
+    if constexpr (sizeof(Real) == 8) {
+        __shared__ double2 lds_tab[512];
+        for (int t = threadIdx.x; t < 512; t += NT) lds_tab[t] = SINCOS_TABLE[t];
+        __syncthreads();
+        return lds_tab;
+    } else {
+        return SINCOS_TABLE;
+    }
+}
+
 template <int LAT>
 __device__ __forceinline__ uint32_t site_index(int x, int y, int z, const Geom& g) {
     return (uint32_t)((z * g.ny + y) * g.nx + x);

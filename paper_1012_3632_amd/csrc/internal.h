@@ -18,12 +18,12 @@ struct TileShape {
 };
 
 // Candidate tiles (the autotuner picks one per handle).
-constexpr int N_IDEAL_CFG = 13;
+constexpr int N_IDEAL_CFG = 15;
 constexpr TileShape IDEAL_CFG[N_IDEAL_CFG] = {
     {64, 4, 1, 1, 0},  {128, 2, 1, 1, 0}, {256, 1, 1, 1, 0}, {32, 8, 1, 1, 0},
     {128, 2, 1, 2, 0}, {64, 4, 1, 2, 0},  {128, 2, 1, 4, 0}, {256, 1, 1, 2, 0},
     {128, 2, 1, 1, 1}, {256, 1, 1, 1, 1}, {128, 2, 1, 1, 0, 0, 1}, {64, 4, 1, 1, 0, 0, 1},
-    {256, 1, 1, 1, 0, 0, 1}};
+    {256, 1, 1, 1, 0, 0, 1}, {128, 2, 1, 2, 0, 0, 1}, {64, 4, 1, 2, 0, 0, 1}};
 constexpr int N_FORCE3_CFG = 9;
 constexpr TileShape FORCE3_CFG[N_FORCE3_CFG] = {
     {32, 4, 2, 1, 0},     {16, 4, 4, 1, 0},     {64, 2, 2, 1, 0},

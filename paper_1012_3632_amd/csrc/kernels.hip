@@ -64,6 +64,8 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
     __shared__ double lds_stats[LDS_S];
 
     static_assert(!FORCE || SPT == 1, "the force tile covers one site per thread");
+    const double2* tab = SINCOS_TABLE;
+    if constexpr (!FORCE) tab = noise_table<Real, NT>();
     // with TX a multiple of 64 every wavefront lies in one (y, z) row
     constexpr bool ROWS = (TX % 64) == 0;
     int x0, y0, z0;
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
         const uint32_t site = site_index<LAT>(x, y, z, g);
         Real zn[2 * L::NPAIR];
         if (P.noise_on)
-            site_normals<L::NPAIR, Real>(site, st.get(), 0u, P.replica, P.key0, P.key1, zn);
+            site_normals<L::NPAIR, Real>(site, st.get(), 0u, P.replica, P.key0, P.key1, zn, tab);
         collide_moments<LAT, Real, FORCE>(m, F, zn, P);
         M::inverse(m, f);
         if constexpr (ROWS) {
@@ -153,12 +155,13 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
 
 // One step of an in-place pair (ideal gas), phase PH = 0 (pull, push to the
 // opposite plane at x + c_i) or 1 (local read of the opposite plane, store in
-// the ordinary layout); see push_rows_opp.  Tiles of TX x TY sites, TX a
-// multiple of 64; the collision, noise counters and statistics are those of
-// k_step, so a pair gives bit-identical populations to two ordinary steps.
-// With one buffer instead of two the working set of a lattice is halved,
-// which lets a 128^3 FP32 D3Q19 state stay in the 256 MB last-level cache.
-template <int LAT, typename Real, bool STATS, int PH, int TX, int TY>
+// the ordinary layout); see push_rows_opp.  Tiles of TX x (TY SPT) sites, TX a
+// multiple of 64, SPT sites per thread stacked in y as in k_step; the
+// collision, noise counters and statistics are those of k_step, so a pair
+// gives bit-identical populations to two ordinary steps.  With one buffer
+// instead of two the working set of a lattice is halved, which lets a 128^3
+// FP32 D3Q19 state stay in the 256 MB last-level cache.
+template <int LAT, typename Real, bool STATS, int PH, int TX, int TY, int SPT = 1>
 __global__ __launch_bounds__(TX* TY) void k_step_ip(Real* f, Geom g, CollideParams<Real> P,
                                                      StepIndex st, double* __restrict__ partial) {
     using L = Lattice<LAT>;
@@ -167,16 +170,20 @@ __global__ __launch_bounds__(TX* TY) void k_step_ip(Real* f, Geom g, CollidePara
     static_assert(TX % 64 == 0, "one (y, z) row per wavefront");
     constexpr int LDS_S = STATS ? 4 * (NT / 64) * 2 * Q : 1;
     __shared__ double lds_stats[LDS_S];
+    const double2* tab = noise_table<Real, NT>();
     int x0, y0, z0;
-    tile_origin<LAT, TX, TY, 1>(g, x0, y0, z0);
+    tile_origin<LAT, TX, TY * SPT, 1>(g, x0, y0, z0);
     const int tx = threadIdx.x % TX;
     const int ty = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / TX));
-    const int x = x0 + tx, y = y0 + ty, z = z0;
+    const int x = x0 + tx, z = z0;
     Real v[STATS ? 2 * Q : 1];
     if constexpr (STATS) {
 #pragma unroll
         for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
     }
+#pragma unroll
+    for (int sp = 0; sp < SPT; ++sp) {
+    const int y = y0 + ty + sp * TY;
     if (x < g.nx && y < g.ny && z < g.nz) {
         Real fl[Q], m[Q];
         if constexpr (PH == 0) pull_rows<LAT, Real>(f, x, y, z, g, fl);
@@ -185,14 +192,14 @@ __global__ __launch_bounds__(TX* TY) void k_step_ip(Real* f, Geom g, CollidePara
         if constexpr (STATS) {
 #pragma unroll
             for (int a = 0; a < Q; ++a) {
-                v[a] = m[a];
-                v[Q + a] = m[a] * m[a];
+                v[a] += m[a];
+                v[Q + a] += m[a] * m[a];
             }
         }
         const uint32_t site = site_index<LAT>(x, y, z, g);
         Real zn[2 * L::NPAIR];
         if (P.noise_on)
-            site_normals<L::NPAIR, Real>(site, st.get(), 0u, P.replica, P.key0, P.key1, zn);
+            site_normals<L::NPAIR, Real>(site, st.get(), 0u, P.replica, P.key0, P.key1, zn, tab);
         const Real F[D] = {};
         collide_moments<LAT, Real, false>(m, F, zn, P);
         M::inverse(m, fl);
@@ -202,6 +209,7 @@ __global__ __launch_bounds__(TX* TY) void k_step_ip(Real* f, Geom g, CollidePara
         asm volatile("" : "+v"(xs));
         if constexpr (PH == 0) push_rows_opp<LAT, Real>(f, xs, y, z, g, fl);
         else store_rows<LAT, Real>(f, xs, y, z, g, fl);
+    }
     }
     if constexpr (STATS) {
         const uint32_t b = xcd_remap(blockIdx.x, g.nblocks);
@@ -539,7 +547,9 @@ static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fou
             // in-place shapes: a lone step (not part of a pair) uses the ordinary kernel
             case 10: step_tile<LAT, Real, false, 128, 2, 1, 1>(s, fin, fout, drho, si, partial, st); break;
             case 11: step_tile<LAT, Real, false, 64, 4, 1, 1>(s, fin, fout, drho, si, partial, st); break;
-            default: step_tile<LAT, Real, false, 256, 1, 1, 1>(s, fin, fout, drho, si, partial, st); break;
+            case 12: step_tile<LAT, Real, false, 256, 1, 1, 1>(s, fin, fout, drho, si, partial, st); break;
+            case 13: step_tile<LAT, Real, false, 128, 2, 1, 2>(s, fin, fout, drho, si, partial, st); break;
+            default: step_tile<LAT, Real, false, 64, 4, 1, 2>(s, fin, fout, drho, si, partial, st); break;
         }
     } else if constexpr (LAT == 1) {
         switch (cfg) {
@@ -565,18 +575,18 @@ static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fou
     }
 }
 
-template <int LAT, typename Real, int TX, int TY>
+template <int LAT, typename Real, int TX, int TY, int SPT = 1>
 static void step_ip(const StepSpec& s, int phase, void* f, StepIndex si, double* partial,
                     hipStream_t st) {
-    const Geom g = make_geom(s, TileShape{TX, TY, 1, 1, 0, 0, 1});
+    const Geom g = make_geom(s, TileShape{TX, TY, 1, SPT, 0, 0, 1});
     const dim3 grid(g.nblocks), block(TX * TY);
     const CollideParams<Real> P = collide_params<Real>(s);
     if (phase == 0) {
-        if (partial) hipLaunchKernelGGL((k_step_ip<LAT, Real, true, 0, TX, TY>), grid, block, 0, st, (Real*)f, g, P, si, partial);
-        else hipLaunchKernelGGL((k_step_ip<LAT, Real, false, 0, TX, TY>), grid, block, 0, st, (Real*)f, g, P, si, partial);
+        if (partial) hipLaunchKernelGGL((k_step_ip<LAT, Real, true, 0, TX, TY, SPT>), grid, block, 0, st, (Real*)f, g, P, si, partial);
+        else hipLaunchKernelGGL((k_step_ip<LAT, Real, false, 0, TX, TY, SPT>), grid, block, 0, st, (Real*)f, g, P, si, partial);
     } else {
-        if (partial) hipLaunchKernelGGL((k_step_ip<LAT, Real, true, 1, TX, TY>), grid, block, 0, st, (Real*)f, g, P, si, partial);
-        else hipLaunchKernelGGL((k_step_ip<LAT, Real, false, 1, TX, TY>), grid, block, 0, st, (Real*)f, g, P, si, partial);
+        if (partial) hipLaunchKernelGGL((k_step_ip<LAT, Real, true, 1, TX, TY, SPT>), grid, block, 0, st, (Real*)f, g, P, si, partial);
+        else hipLaunchKernelGGL((k_step_ip<LAT, Real, false, 1, TX, TY, SPT>), grid, block, 0, st, (Real*)f, g, P, si, partial);
     }
 }
 
@@ -586,6 +596,8 @@ static void ip_dispatch(const StepSpec& s, int cfg, int phase, void* f, StepInde
     switch (cfg) {
         case 10: step_ip<LAT, Real, 128, 2>(s, phase, f, si, partial, st); break;
         case 11: step_ip<LAT, Real, 64, 4>(s, phase, f, si, partial, st); break;
+        case 13: step_ip<LAT, Real, 128, 2, 2>(s, phase, f, si, partial, st); break;
+        case 14: step_ip<LAT, Real, 64, 4, 2>(s, phase, f, si, partial, st); break;
         default: step_ip<LAT, Real, 256, 1>(s, phase, f, si, partial, st); break;
     }
 }

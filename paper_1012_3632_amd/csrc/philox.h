@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sincos_table.h"
+
 namespace flb {
 
 struct Philox4 {
@@ -64,54 +66,19 @@ __device__ __forceinline__ void box_muller(uint32_t r, uint32_t h, float& z0, fl
     z0 = rad * __builtin_amdgcn_cosf(v);
     z1 = rad * __builtin_amdgcn_sinf(v);
 }
-// sin and cos of 2 pi k / 65536 for an integer k in [1, 65536].  The angle is
-// reduced exactly in integers: quadrant q = k / 16384 and t = k mod 16384,
-// angle = q pi/2 + pi t / 32768; with a = min(t, 16384 - t) the reduced
-// argument y = pi a / 32768 lies in [0, pi/4], where the Taylor series of sin
-// to y^17 and of cos to y^18 are evaluated in Horner form (first omitted
-// terms below 1e-19).  The co-function and quadrant identities then give the
-// result; the only rounding before the series is that of y itself.
-__device__ __forceinline__ void sincos_turn16(uint32_t k, double& s, double& c) {
-    const uint32_t q = (k >> 14) & 3u;
-    const uint32_t t = k & 16383u;
-    const bool upper = t > 8192u;
-    const uint32_t a = upper ? 16384u - t : t;
-    constexpr double PI_32768 = 3.141592653589793 / 32768.0;
-    const double y = (double)a * PI_32768;
-    const double y2 = y * y;
-    // 1/n! for the series terms
-    constexpr double F3 = 1.0 / 6.0, F5 = F3 / 20.0, F7 = F5 / 42.0, F9 = F7 / 72.0,
-                     F11 = F9 / 110.0, F13 = F11 / 156.0, F15 = F13 / 210.0, F17 = F15 / 272.0;
-    constexpr double F2 = 0.5, F4 = F2 / 12.0, F6 = F4 / 30.0, F8 = F6 / 56.0, F10 = F8 / 90.0,
-                     F12 = F10 / 132.0, F14 = F12 / 182.0, F16 = F14 / 240.0, F18 = F16 / 306.0;
-    double ps = -F17;
-    ps = fma(ps, y2, F15);
-    ps = fma(ps, y2, -F13);
-    ps = fma(ps, y2, F11);
-    ps = fma(ps, y2, -F9);
-    ps = fma(ps, y2, F7);
-    ps = fma(ps, y2, -F5);
-    ps = fma(ps, y2, F3);
-    const double sy = fma(-ps * y2, y, y);   // y - y^3/3! + ...
-    double pc = F18;
-    pc = fma(pc, y2, -F16);
-    pc = fma(pc, y2, F14);
-    pc = fma(pc, y2, -F12);
-    pc = fma(pc, y2, F10);
-    pc = fma(pc, y2, -F8);
-    pc = fma(pc, y2, F6);
-    pc = fma(pc, y2, -F4);
-    pc = fma(pc, y2, F2);
-    const double cy = fma(-pc, y2, 1.0);     // 1 - y^2/2! + ...
-    // sin and cos of the angle within the quadrant
-    const double sp = upper ? cy : sy;
-    const double cp = upper ? sy : cy;
-    switch (q) {
-        case 0: s = sp; c = cp; break;
-        case 1: s = cp; c = -sp; break;
-        case 2: s = -sp; c = -cp; break;
-        default: s = -cp; c = sp; break;
-    }
+// sin and cos of 2 pi k / 65536 for an integer k in [1, 65536], from the
+// angle-sum identity: k = 256 j + l (j taken mod 256), A = 2 pi j / 256,
+// B = 2 pi l / 65536, and tab holds the correctly rounded (sin, cos) of A
+// (entries 0..255) and of B (entries 256..511); sin(A + B) = sA cB + cA sB,
+// cos(A + B) = cA cB - sA sB, each one product and one fused multiply-add
+// (within about one unit in the last place).  tab is SINCOS_TABLE or a copy
+// of it in LDS; every kernel gets the same bits either way.
+__device__ __forceinline__ void sincos_turn16(uint32_t k, const double2* tab, double& s,
+                                              double& c) {
+    const double2 a = tab[(k >> 8) & 255u];
+    const double2 b = tab[256u + (k & 255u)];
+    s = fma(a.x, b.y, a.y * b.x);
+    c = fma(a.y, b.y, -(a.x * b.x));
 }
 
 // -2 ln u for u = (r + 1) 2^-32.  With d = r + 1 = 2^e m (exact; the mantissa
@@ -150,12 +117,17 @@ __device__ __forceinline__ double neg2_log_u32(uint32_t r) {
     return -2.0 * fma(k, LN2_HEAD, fma(k, LN2_TAIL, ln_m));
 }
 
-__device__ __forceinline__ void box_muller(uint32_t r, uint32_t h, double& z0, double& z1) {
+__device__ __forceinline__ void box_muller(uint32_t r, uint32_t h, const double2* tab,
+                                           double& z0, double& z1) {
     const double rad = sqrt(neg2_log_u32(r));
     double s, c;
-    sincos_turn16(h + 1u, s, c);   // theta = 2 pi (h + 1) 2^-16
+    sincos_turn16(h + 1u, tab, s, c);   // theta = 2 pi (h + 1) 2^-16
     z0 = rad * c;
     z1 = rad * s;
+}
+__device__ __forceinline__ void box_muller(uint32_t r, uint32_t h, const double2*, float& z0,
+                                           float& z1) {
+    box_muller(r, h, z0, z1);
 }
 
 // The 2 NPAIR normals of one site-step.  Words w[0 ..) are the Philox outputs
@@ -170,10 +142,12 @@ struct NoiseLayout {
     static constexpr int NBLK = (NWORD + 3) / 4;
 };
 
+// tab: the FP64 angle table (SINCOS_TABLE, or a copy in LDS); FP32 ignores it.
 template <int NPAIR, typename Real>
 __device__ __forceinline__ void site_normals(uint32_t site, uint32_t step, uint32_t tag,
                                              uint32_t replica, uint32_t k0, uint32_t k1,
-                                             Real (&z)[2 * NPAIR]) {
+                                             Real (&z)[2 * NPAIR],
+                                             const double2* tab = SINCOS_TABLE) {
     constexpr int NBLK = NoiseLayout<NPAIR>::NBLK;
     uint32_t w[4 * NBLK];
 #pragma unroll
@@ -188,7 +162,7 @@ __device__ __forceinline__ void site_normals(uint32_t site, uint32_t step, uint3
     for (int p = 0; p < NPAIR; ++p) {
         const uint32_t a = w[NPAIR + p / 2];
         const uint32_t h = (p % 2 == 0) ? (a >> 16) : (a & 0xffffu);
-        box_muller(w[p], h, z[2 * p], z[2 * p + 1]);
+        box_muller(w[p], h, tab, z[2 * p], z[2 * p + 1]);
     }
 }
 
