@@ -687,6 +687,9 @@ def main():
                     help="only time a plain in-place elementwise pass over buffers of 32 MB to 1 GiB")
     ap.add_argument("--profile-step", choices=["fp32", "fp64"],
                     help="only run the d3q19_128 step (fixed launch shape, statistics on)")
+    ap.add_argument("--profile-landau", action="store_true",
+                    help="only run the d3q19_256_landau step (FP32, statistics every step) in "
+                         "launch configuration 8 (z-marching 128 x 2 columns, 16 planes), 6 steps")
     ap.add_argument("--profile-256", action="store_true",
                     help="only run the d3q19_128 step on 256^3 (FP32, statistics every step): "
                          "in-place pairs (128 x 2) and two buffers (128 x 2), 20 steps each")
@@ -705,6 +708,8 @@ def main():
         profile_step(args)
     elif args.profile_256:
         profile_256()
+    elif args.profile_landau:
+        profile_landau()
     else:
         bench_main(args)
 
@@ -774,6 +779,22 @@ def profile_step(args):
         sim.step(args.steps, stats_stride=0)
     torch.cuda.synchronize()
     print(json.dumps({"profile_step": args.profile_step, "configs": n, "steps_each": args.steps}))
+
+
+def profile_landau():
+    """The 256^3 square-gradient step (density pass + z-marching force step)
+    in the benchmark's launch shape, for kernel counters."""
+    import torch
+
+    import flb_workloads as W
+    from paper_1012_3632_amd import Params, Simulation
+    p = Params.from_dict(dict(W.params_of("d3q19_256_landau"), precision="fp32"))
+    drho = W.initial_drho(p.shape, 7, W.WORKLOADS["d3q19_256_landau"]["init_noise"])
+    sim = Simulation(p, drho_init=drho)
+    sim.set_launch(8)
+    sim.step(6, stats_stride=1)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_landau": 8, "steps": 6}))
 
 
 def profile_256():
