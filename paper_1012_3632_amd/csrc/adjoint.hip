@@ -51,6 +51,7 @@ __device__ __forceinline__ void collide_adjoint(const Real (&m)[Lattice<LAT>::Q]
     Real meq[S::count], mF[S::count];
     S::eval(rho, u, F, meq, mF);
     const Real sr = P.noise_local ? sqrt(rho) : sqrt(P.rho0);
+    const Real tc[3] = {sr * P.amp_cls[0], sr * P.amp_cls[1], sr * P.amp_cls[2]};
     Real rho_b = Real(0), u_b[D];
     mb[0] = mbs[0];
 #pragma unroll
@@ -74,7 +75,7 @@ __device__ __forceinline__ void collide_adjoint(const Real (&m)[Lattice<LAT>::Q]
         g *= gb;
         if (P.noise_on) {
             const int kk = a - D - 1;
-            const Real sz = sr * P.amp[kk] * z[kk] * gb;
+            const Real sz = mode_amp<LAT, Real>(tc, a) * z[kk] * gb;
             g += sz * (Real(1) - lam) / (lam * (Real(2) - lam));
             pg[1] += (double)(sz * inv2kT);
             if (P.noise_local) rho_b += Real(0.5) * sz * inv_rho;
@@ -89,7 +90,7 @@ __device__ __forceinline__ void collide_adjoint(const Real (&m)[Lattice<LAT>::Q]
         Real g = -m[a] * gb;
         if (P.noise_on) {
             const int kk = a - D - 1;
-            const Real sz = sr * P.amp[kk] * z[kk] * gb;
+            const Real sz = mode_amp<LAT, Real>(tc, a) * z[kk] * gb;
             g += sz * (Real(1) - lam) / (lam * (Real(2) - lam));
             pg[1] += (double)(sz * inv2kT);
             if (P.noise_local) rho_b += Real(0.5) * sz * inv_rho;
@@ -387,7 +388,7 @@ static CollideParams<Real> adj_collide_params(const StepSpec& s) {
     P.lam_bulk = (Real)s.lam_bulk;
     P.lam_shear = (Real)s.lam_shear;
     P.lam_ghost = (Real)s.lam_ghost;
-    for (int k = 0; k < KMAX; ++k) P.amp[k] = (Real)s.amp[k];
+    for (int c = 0; c < 3; ++c) P.amp_cls[c] = (Real)s.amp_cls[c];
     P.noise_on = s.noise_on;
     P.noise_local = s.noise_local;
     P.key0 = s.key0;

@@ -48,19 +48,6 @@ constexpr size_t NONFINITE_OFF = 64;     // byte offset of the non-finite flag i
 int lattice_q(int lat) { return lat == FLB_D2Q9 ? 9 : 19; }
 int lattice_d(int lat) { return lat == FLB_D2Q9 ? 2 : 3; }
 
-template <int LAT>
-void fill_amp(const flb_params& p, double (&amp)[15]) {
-    using L = Lattice<LAT>;
-    int k = 0;
-    for (int a = L::D + 1; a < L::Q; ++a, ++k) {
-        const double lam = L::cls[a] == CLS_BULK ? p.rate_bulk
-                           : L::cls[a] == CLS_SHEAR ? p.rate_shear
-                                                    : p.rate_ghost;
-        amp[k] = std::sqrt(p.kT * L::N[a] * lam * (2.0 - lam) / CS2);
-    }
-    for (; k < 15; ++k) amp[k] = 0.0;
-}
-
 flb_status validate(const flb_params* p) {
     if (!p) return fail(FLB_ERR_INVALID_ARG, "params is NULL");
     if (p->lattice != FLB_D2Q9 && p->lattice != FLB_D3Q19)
@@ -108,8 +95,8 @@ StepSpec spec_of(const flb_params& p) {
     s.lam_bulk = p.rate_bulk;
     s.lam_shear = p.rate_shear;
     s.lam_ghost = p.rate_ghost;
-    if (p.lattice == FLB_D2Q9) fill_amp<0>(p, s.amp);
-    else fill_amp<1>(p, s.amp);
+    const double lam[3] = {p.rate_bulk, p.rate_shear, p.rate_ghost};
+    for (int c = 0; c < 3; ++c) s.amp_cls[c] = std::sqrt(p.kT * lam[c] * (2.0 - lam[c]) / CS2);
     s.noise_on = p.kT > 0.0;
     s.noise_local = p.noise_rho_local ? 1 : 0;
     s.key0 = (uint32_t)(p.seed & 0xffffffffu);

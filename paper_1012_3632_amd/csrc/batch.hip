@@ -56,6 +56,29 @@ struct RepInfo {
 
 __device__ __forceinline__ uint32_t div_small(uint32_t s, uint32_t inv) { return __umulhi(s, inv); }
 
+// Periodic neighbourhood of a site of one replica: the x of x - 1, x, x + 1,
+// the row offsets (y - 1, y, y + 1) nx and the plane offsets (z - 1, z,
+// z + 1) nx ny, so that the site index of x + c is three additions.
+struct Nbr {
+    uint32_t xs[3], row[3], pl[3];
+    __device__ __forceinline__ Nbr(int x, int y, int z, const struct RepInfo& R);
+    __device__ __forceinline__ uint32_t at(int cx, int cy, int cz) const {
+        return pl[1 + cz] + row[1 + cy] + xs[1 + cx];
+    }
+};
+__device__ __forceinline__ Nbr::Nbr(int x, int y, int z, const RepInfo& R) {
+    const uint32_t nx = (uint32_t)R.nx, nxy = (uint32_t)R.nx * (uint32_t)R.ny;
+    xs[0] = (uint32_t)(x == 0 ? R.nx - 1 : x - 1);
+    xs[1] = (uint32_t)x;
+    xs[2] = (uint32_t)(x == R.nx - 1 ? 0 : x + 1);
+    row[0] = (uint32_t)(y == 0 ? R.ny - 1 : y - 1) * nx;
+    row[1] = (uint32_t)y * nx;
+    row[2] = (uint32_t)(y == R.ny - 1 ? 0 : y + 1) * nx;
+    pl[0] = (uint32_t)(z == 0 ? R.nz - 1 : z - 1) * nxy;
+    pl[1] = (uint32_t)z * nxy;
+    pl[2] = (uint32_t)(z == R.nz - 1 ? 0 : z + 1) * nxy;
+}
+
 // Population accesses of one replica: one base pointer (rep) and 32-bit
 // element offsets i V + site (a replica's populations stay below 2^31
 // elements: V < 2^24 sites).  V is made opaque to the compiler by the
@@ -63,19 +86,12 @@ __device__ __forceinline__ uint32_t div_small(uint32_t s, uint32_t inv) { return
 // accesses instead of being hoisted out of the tile loop as Q separate
 // 64-bit plane bases (which spill).
 template <int LAT, typename Real>
-__device__ __forceinline__ void rep_pull(const Real* rep, uint32_t V, int x, int y, int z,
-                                         const RepInfo& R, Real (&f)[Lattice<LAT>::Q]) {
+__device__ __forceinline__ void rep_pull(const Real* rep, uint32_t V, const Nbr& nb,
+                                         Real (&f)[Lattice<LAT>::Q]) {
     using L = Lattice<LAT>;
-    const int xm = x == 0 ? R.nx - 1 : x - 1, xp = x == R.nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? R.ny - 1 : y - 1, yp = y == R.ny - 1 ? 0 : y + 1;
-    const int zm = z == 0 ? R.nz - 1 : z - 1, zp = z == R.nz - 1 ? 0 : z + 1;
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const int sx = L::cx[i] == 0 ? x : (L::cx[i] > 0 ? xm : xp);
-        const int sy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? ym : yp);
-        const int sz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zm : zp);
-        f[i] = plane_ld(rep, (uint32_t)i * V + (uint32_t)((sz * R.ny + sy) * R.nx + sx));
-    }
+    for (int i = 0; i < L::Q; ++i)
+        f[i] = plane_ld(rep, (uint32_t)i * V + nb.at(-L::cx[i], -L::cy[i], -L::cz[i]));
 }
 
 template <int LAT, typename Real, bool STATS>
@@ -114,7 +130,7 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
                 const uint32_t z = div_small(yz, R.inv_ny);
                 const int y = (int)(yz - z * (uint32_t)R.ny);
                 Real f[Q], m[Q];
-                rep_pull<LAT, Real>(fin + R.off, Vr, x, y, (int)z, R, f);
+                rep_pull<LAT, Real>(fin + R.off, Vr, Nbr(x, y, (int)z, R), f);
                 M::forward(f, m);
                 if constexpr (STATS) {
 #pragma unroll
@@ -185,7 +201,7 @@ __global__ __launch_bounds__(BT) void k_batch_step_ip(Real* f, const RepInfo* __
                 const int y = (int)(yz - z * (uint32_t)R.ny);
                 Real fl[Q], m[Q];
                 if constexpr (PH == 0) {
-                    rep_pull<LAT, Real>(base, Vr, x, y, (int)z, R, fl);
+                    rep_pull<LAT, Real>(base, Vr, Nbr(x, y, (int)z, R), fl);
                 } else {
                     // local accesses: uniform plane bases, one lane offset
 #pragma unroll
@@ -205,15 +221,14 @@ __global__ __launch_bounds__(BT) void k_batch_step_ip(Real* f, const RepInfo* __
                 collide_moments<LAT, Real, false>(m, F, zn, P);
                 M::inverse(m, fl);
                 if constexpr (PH == 0) {
+                    // neighbourhood formed again after the collision (not held
+                    // in registers through it)
+                    int xs = x;
+                    asm volatile("" : "+v"(xs));
+                    const Nbr nb(xs, y, (int)z, R);
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) {
-                        int xx = x + L::cx[i], yy = y + L::cy[i], zz = (int)z + L::cz[i];
-                        xx = xx < 0 ? xx + R.nx : (xx >= R.nx ? xx - R.nx : xx);
-                        yy = yy < 0 ? yy + R.ny : (yy >= R.ny ? yy - R.ny : yy);
-                        zz = zz < 0 ? zz + R.nz : (zz >= R.nz ? zz - R.nz : zz);
-                        const uint32_t t = (uint32_t)xx + (uint32_t)R.nx * ((uint32_t)yy + (uint32_t)R.ny * (uint32_t)zz);
-                        plane_st(base, (uint32_t)L::opp[i] * Vr + t, fl[i]);
-                    }
+                    for (int i = 0; i < Q; ++i)
+                        plane_st(base, (uint32_t)L::opp[i] * Vr + nb.at(L::cx[i], L::cy[i], L::cz[i]), fl[i]);
                 } else {
 #pragma unroll
                     for (int i = 0; i < Q; ++i) plane_st(base + (size_t)i * R.V, s, fl[i]);
@@ -417,15 +432,9 @@ CollideParams<Real> batch_collide_params(const flb_batch* b) {
     P.lam_bulk = (Real)p.rate_bulk;
     P.lam_shear = (Real)p.rate_shear;
     P.lam_ghost = (Real)p.rate_ghost;
-    using LL = Lattice<LAT>;
-    int k = 0;
-    for (int a = LL::D + 1; a < LL::Q; ++a, ++k) {
-        const double lam = LL::cls[a] == CLS_BULK ? p.rate_bulk
-                           : LL::cls[a] == CLS_SHEAR ? p.rate_shear
-                                                     : p.rate_ghost;
-        P.amp[k] = (Real)std::sqrt(p.kT * LL::N[a] * lam * (2.0 - lam) / CS2);
-    }
-    for (; k < KMAX; ++k) P.amp[k] = Real(0);
+    const double lam[3] = {p.rate_bulk, p.rate_shear, p.rate_ghost};
+    for (int c = 0; c < 3; ++c)
+        P.amp_cls[c] = (Real)std::sqrt(p.kT * lam[c] * (2.0 - lam[c]) / CS2);
     P.noise_on = p.kT > 0.0;
     P.noise_local = p.noise_rho_local ? 1 : 0;
     P.key0 = P.key1 = 0;   // per replica

@@ -23,19 +23,52 @@
 namespace flb {
 
 constexpr int QMAX = 19;
-constexpr int KMAX = 15;
 
 // Physical parameters of the collision, uniform over a launch.
 template <typename Real>
 struct CollideParams {
     Real rho0;
     Real lam_bulk, lam_shear, lam_ghost;
-    Real amp[KMAX];     // sqrt(kT N_a lam_a (2 - lam_a) / cs2), non-conserved modes in order
+    Real amp_cls[3];    // sqrt(kT lam (2 - lam) / cs2) of the bulk, shear and ghost rates
     int32_t noise_on;   // kT > 0
     int32_t noise_local;
     uint32_t key0, key1, replica;
     uint32_t* nonfinite;  // set to 1 when a site's pulled density is not finite (nullable)
 };
+
+// sqrt(x) of a positive constant by Newton's iteration (compile time).
+constexpr double const_sqrt(double x, double r = 1.0, int n = 0) {
+    return n == 60 ? r : const_sqrt(x, 0.5 * (r + x / r), n + 1);
+}
+
+// sqrt(N_a) for every mode of a lattice, evaluated by the compiler.
+template <int LAT>
+struct ModeSqrtN {
+    struct Tab {
+        double v[Lattice<LAT>::Q];
+    };
+    static constexpr Tab make() {
+        Tab t{};
+        for (int a = 0; a < Lattice<LAT>::Q; ++a) t.v[a] = const_sqrt(Lattice<LAT>::N[a]);
+        return t;
+    }
+    static constexpr Tab tab = make();
+};
+
+// Rate class of mode a for the class amplitudes: 0 bulk, 1 shear, 2 ghost.
+template <int LAT>
+__host__ __device__ constexpr int amp_class(int a) {
+    return Lattice<LAT>::cls[a] == CLS_BULK ? 0 : (Lattice<LAT>::cls[a] == CLS_SHEAR ? 1 : 2);
+}
+
+// Noise amplitude of mode a: the per-mode variance rho kT N_a lam_a
+// (2 - lam_a) / cs2 of Sec. V eq. noise-lbe is N_a times a rate-class factor,
+// so sigma_a = sqrt(N_a) tc[class], tc = sqrt(rho) times the class
+// amplitudes.  a is a constant of an unrolled loop.
+template <int LAT, typename Real>
+__host__ __device__ __forceinline__ Real mode_amp(const Real (&tc)[3], int a) {
+    return tc[amp_class<LAT>(a)] * Real(ModeSqrtN<LAT>::tab.v[a]);
+}
 
 template <int LAT, typename Real>
 struct Moments {
@@ -392,8 +425,9 @@ __device__ __forceinline__ void collide_moments(Real (&m)[Lattice<LAT>::Q],
     for (int a = S::first + S::count; a < L::Q; ++a) m[a] = m[a] - P.lam_ghost * m[a];
     if (P.noise_on) {
         const Real sr = P.noise_local ? sqrt(rho) : sqrt(P.rho0);
+        const Real tc[3] = {sr * P.amp_cls[0], sr * P.amp_cls[1], sr * P.amp_cls[2]};
 #pragma unroll
-        for (int k = 0; k < L::K; ++k) m[D + 1 + k] += sr * P.amp[k] * z[k];
+        for (int k = 0; k < L::K; ++k) m[D + 1 + k] += mode_amp<LAT, Real>(tc, D + 1 + k) * z[k];
     }
 }
 

@@ -41,7 +41,7 @@ struct StepSpec {
     int force;         // 0 ideal, 1 Landau
     int nx, ny, nz;
     double rho0, kT, lam_bulk, lam_shear, lam_ghost;
-    double amp[15];
+    double amp_cls[3];   // sqrt(kT lam (2 - lam) / cs2) for the bulk, shear and ghost rates
     int noise_on, noise_local;
     uint32_t key0, key1, replica;
     double a, b, rho_c, kappa, eta;

@@ -274,13 +274,18 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(
         FM::store_plane(rreg, lds_r + FM::rslot(z + 2, zb) * FM::NRP);
         if (z + 1 < ze) FM::load_plane(drho, g, off, z + 3, rreg);
         // x is re-read each plane, so that per-plane lane addresses are not
-        // hoisted out of the loop (they would hold two VGPRs per plane)
+        // hoisted out of the loop (they would hold two VGPRs per plane); the
+        // plane stride likewise, so that the 19 64-bit plane bases are formed
+        // by scalar arithmetic next to their accesses instead of being held
+        // in SGPRs through the loop (which spills them to VGPR lanes)
         int xl = x;
         asm volatile("" : "+v"(xl));
+        Geom gz = g;
+        asm volatile("" : "+s"(gz.V));
         Real f[Q];
         if (inxy) {
-            if constexpr (ROWS) pull_rows<1, Real>(fin, xl, y, z, g, f);
-            else pull<1, Real>(fin, xl, y, z, g, f);
+            if constexpr (ROWS) pull_rows<1, Real>(fin, xl, y, z, gz, f);
+            else pull<1, Real>(fin, xl, y, z, gz, f);
         }
         __syncthreads();
         FM::mu_plane(lds_r, lds_m, z + 1, zb, fp);
@@ -307,12 +312,12 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(
                 const size_t row = (size_t)(uint32_t)((z * g.ny + y) * g.nx);
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    if constexpr (NTS) plane_st_nt(fout + ((size_t)i * g.V + row), (uint32_t)xl, f[i]);
-                    else plane_st(fout + ((size_t)i * g.V + row), (uint32_t)xl, f[i]);
+                    if constexpr (NTS) plane_st_nt(fout + ((size_t)i * gz.V + row), (uint32_t)xl, f[i]);
+                    else plane_st(fout + ((size_t)i * gz.V + row), (uint32_t)xl, f[i]);
                 }
             } else {
 #pragma unroll
-                for (int i = 0; i < Q; ++i) plane_st(fout + (size_t)i * g.V, site, f[i]);
+                for (int i = 0; i < Q; ++i) plane_st(fout + (size_t)i * gz.V, site, f[i]);
             }
         }
     }
@@ -457,7 +462,7 @@ static CollideParams<Real> collide_params(const StepSpec& s) {
     P.lam_bulk = (Real)s.lam_bulk;
     P.lam_shear = (Real)s.lam_shear;
     P.lam_ghost = (Real)s.lam_ghost;
-    for (int k = 0; k < KMAX; ++k) P.amp[k] = (Real)s.amp[k];
+    for (int c = 0; c < 3; ++c) P.amp_cls[c] = (Real)s.amp_cls[c];
     P.noise_on = s.noise_on;
     P.noise_local = s.noise_local;
     P.key0 = s.key0;
