@@ -1,8 +1,9 @@
 """Fluctuation-dissipation checks of the GPU statistics at the workload sizes.
 
-Stationary per-site variance of every mode equals G_aa = rho0 kT N_a / cs2
-(Sec. IV.A eqs. G-ideal, mu-ideal; Sec. IV.B.1 eq. g-mat-forcing for the
-non-conserved modes of the force-based fluid), within 1 %.
+Ideal gas: the stationary per-site variance of every mode equals G_aa =
+rho0 kT N_a / cs2 (Sec. IV.A eqs. G-ideal, mu-ideal), within 1 %.
+Force-based fluid (Sec. IV.B.1): every mode's variance equals that of the
+exactly solved linearized lattice step, within 0.2 %.
 """
 
 import numpy as np
@@ -51,14 +52,25 @@ def test_fdt_d3q19_128(precision):
     np.testing.assert_allclose(ratio, 1.0, atol=0.01)
 
 
-def test_fdt_d3q19_landau_noncons():
-    """Force-based fluid: noise as for the ideal gas (eq. noise-nonideal), so the
-    non-conserved modes keep G_aa = rho0 kT N_a / cs2."""
-    from paper_1012_3632_amd import Simulation, lattice_tables
-    kw = dict(W.params_of("d3q19_256_landau", nx=64, ny=64, nz=64), precision="fp32", kT=1e-6)
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_fdt_d3q19_landau_exact_linear_theory(precision):
+    """Force-based fluid (the d3q19_256_landau parameters on 24^3, from rest):
+    the measured per-site variance of every mode equals the stationary
+    variance of the linearized lattice step (tests/golden/
+    landau_site_variances_24.json, written from the oracle's exact spectra)
+    within 0.2 % (measured: 0.05 %; the sampling error of 30,000 steps of
+    13,824 sites is a few 1e-4).  That value is not G_aa = rho0 kT N_a / cs2 exactly: at
+    finite k the force and streaming couple the density to the other modes
+    (0.964 G for the density, 1.011 G for two ghost modes on this machine)."""
+    import json
+    import os
+    from paper_1012_3632_amd import Simulation
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "landau_site_variances_24.json")))
+    n = gold["n"]
+    kw = dict(W.params_of("d3q19_256_landau", nx=n, ny=n, nz=n), precision=precision)
     sim = Simulation(gpu_params(**kw))
-    var, n = _variances(sim, 500, 1000)
-    N = lattice_tables("D3Q19")["N"]
-    G = kw["kT"] * N * 3
-    ratio = var / G
-    np.testing.assert_allclose(ratio[4:], 1.0, atol=0.02)
+    var, nsamp = _variances(sim, 3000, 30000)
+    ratio = var / np.asarray(gold["variance"])
+    print("measured / exact linearized:", np.round(ratio, 4))
+    np.testing.assert_allclose(ratio, 1.0, atol=0.002)
