@@ -28,7 +28,8 @@ fluctuations in the discrete Boltzmann equation"):
 * ``capillary`` -- the capillary-fluctuation analysis of Sec. VI: interface
   heights by fitting the mean-field profile (eqs. height-def, denprof), their
   spectrum, eq. surf-tension and the capillary structure factor
-  (eq. capill-static), and the effective tension of this lattice scheme.
+  (eq. capill-static), and the scheme's interface tension by mechanics
+  (Young-Laplace drops at kT = 0).
 * ``modeq``    -- the modified-equilibrium (Swift) model of Sec. IV.B,
   linearized about rest on D2Q9: equilibrium moments of eq. meq-yeo, the
   correlations of eq. f-correl-yeo, the noise covariance fixed by the lattice
@@ -38,6 +39,7 @@ fluctuations in the discrete Boltzmann equation"):
   w.r.t. the initial populations, the shear rate and kT, by reverse-mode
   automatic differentiation of ``flb`` (plain definition of the derivative).
 
-Parity status of each function is stated in its docstring; see also the
-"parity unpinned" notes there.
+Every function is pinned by the CPU tests ``tests/test_oracle_*.py`` against
+closed forms, printed values, invariants or brute force (each module's
+docstring names its pins).
 """

@@ -26,23 +26,16 @@ as 2 - 2 cos k, sigma from eq. surf-tension.
                          2-D drop relaxed at kT = 0, its equimolar radius R and
                          the bulk pressures inside and outside; Young-Laplace
                          in 2-D gives sigma = R (p_in - p_out).
-* ``effective_kappa`` / ``effective_surface_tension``: a reading.  This
-  lattice scheme's density fluctuations follow the Ornstein-Zernike form with
-  kappa_eff(rho0) = kappa + (eta cs2 - rho0 psi''(rho0)) / (4 rho0) in place of
-  kappa (pinned against ``spectra.stationary_spectrum``); the tension of an
-  interface is then taken as the square-gradient integral
-  sigma_eff = int sqrt(2 kappa_eff(rho) W(rho)) drho between the bulk
-  densities, W the double well above its common tangent.  Parity unpinned:
-  the scheme's mechanical tension (``laplace_drop``) is not this integral
-  (about 0.4 of it at the capillary parameters), and its steady states are
-  not those of any square-gradient free energy with bulk density psi (a flat
-  interface balances p0 but not psi').
+* ``effective_kappa``    kappa_eff(rho0) = kappa + (eta cs2 - rho0 psi''(rho0))
+                         / (4 rho0): the coefficient of k^2 in this lattice
+                         scheme's small-k density fluctuations (Ornstein-
+                         Zernike form), pinned against the exact linearized
+                         step (``spectra.stationary_spectrum``).
 
 Pins: ``tests/test_oracle_capillary.py``.
 """
 
 import numpy as np
-from scipy.integrate import quad
 from scipy.optimize import brentq, minimize_scalar
 
 from . import lattice as _lattice
@@ -126,25 +119,8 @@ def _psi2(p, r):
 
 def effective_kappa(p, rho):
     """kappa + (eta cs2 - rho psi''(rho)) / (4 rho): the square-gradient
-    coefficient of this lattice scheme's small-k density fluctuations (a
-    reading, pinned against the linearized step)."""
+    coefficient of this lattice scheme's small-k density fluctuations."""
     return p.kappa + (p.eta * CS2 - rho * _psi2(p, rho)) / (4.0 * rho)
-
-
-def effective_surface_tension(p, rho_L, rho_V):
-    """int_{rho_V}^{rho_L} sqrt(2 kappa_eff(rho) W(rho)) drho, W = psi minus its
-    chord between the bulk densities (the common tangent of a symmetric well).
-    For the paper's force (eta = 1), where psi is the whole bulk free energy."""
-    if p.eta != 1:
-        raise ValueError("the bulk free energy is psi alone only for eta = 1")
-    pl, pv = _psi(p, rho_L), _psi(p, rho_V)
-
-    def W(r):
-        return _psi(p, r) - (pv + (r - rho_V) * (pl - pv) / (rho_L - rho_V))
-
-    val, _ = quad(lambda r: np.sqrt(max(2.0 * effective_kappa(p, r) * W(r), 0.0)), rho_V, rho_L,
-                  epsabs=1e-14, epsrel=1e-12)
-    return val
 
 
 def bulk_pressure(p, rho):

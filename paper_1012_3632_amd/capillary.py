@@ -13,10 +13,7 @@ The paper's tension is eq. surf-tension with the model's kappa.  This lattice
 scheme does not reach eq. capill-static with it: its height spectrum has the
 capillary form with a tension ~1.45 times eq. surf-tension's, while drops
 relaxed by the same scheme at kT = 0 obey the Young-Laplace law with ~0.66
-times it.  ``effective_surface_tension`` (the square-gradient integral with
-kappa_eff(rho) = kappa + (eta cs2 - rho psi''(rho)) / (4 rho), the
-coefficient the scheme's small-k density fluctuations show) lies near the
-spectrum's value but is a reading, not a derived tension.
+times it.
 """
 
 import numpy as np
@@ -24,7 +21,6 @@ import torch
 
 from .sim import Params, Simulation, field_spectrum
 
-CS2 = 1.0 / 3.0
 
 
 def well(rho_L, rho_V, beta):
@@ -62,21 +58,6 @@ def stripe(p, y1, y2, rho_L, rho_V, width):
 def surface_tension(rho_L, rho_V, kappa, beta):
     """(rho_L - rho_V)^3 sqrt(2 kappa beta) / 6 (eq. surf-tension)."""
     return (rho_L - rho_V) ** 3 * np.sqrt(2.0 * kappa * beta) / 6.0
-
-
-def effective_surface_tension(p, rho_L, rho_V, n=200001):
-    """int sqrt(2 kappa_eff(rho) W(rho)) drho over [rho_V, rho_L] (Simpson),
-    W = psi above its chord between the phases; the paper's force (eta = 1)."""
-    if p.eta != 1:
-        raise ValueError("defined for eta = 1, where psi is the whole bulk free energy")
-    r = np.linspace(rho_V, rho_L, n)
-    psi = lambda x: p.a * (x - p.rho_c) ** 2 + p.b * (x - p.rho_c) ** 4
-    W = psi(r) - (psi(rho_V) + (r - rho_V) * (psi(rho_L) - psi(rho_V)) / (rho_L - rho_V))
-    psi2 = 2 * p.a + 12 * p.b * (r - p.rho_c) ** 2
-    keff = p.kappa + (p.eta * CS2 - r * psi2) / (4.0 * r)
-    f = np.sqrt(np.maximum(2.0 * keff * W, 0.0))
-    h = (rho_L - rho_V) / (n - 1)
-    return h / 3.0 * (f[0] + f[-1] + 4.0 * f[1:-1:2].sum() + 2.0 * f[2:-1:2].sum())
 
 
 def capillary_theory(p, kT, sigma):

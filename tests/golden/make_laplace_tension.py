@@ -43,8 +43,7 @@ def main():
         workload="d2q9_capillary scheme: D2Q9, eta = 1, beta 0.1, kappa 0.08, rho_L 1, "
                  "rho_V 0.5, all rates 1, kT = 0",
         drops=rows, sigma_inf=float(s_inf), curvature_coefficient=float(c),
-        sigma_eq_surf_tension=float(cap.surface_tension(RHO_L, RHO_V, KAPPA, BETA)),
-        sigma_effective_reading=float(cap.effective_surface_tension(p, RHO_L, RHO_V)))
+        sigma_eq_surf_tension=float(cap.surface_tension(RHO_L, RHO_V, KAPPA, BETA)))
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "laplace_tension.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)

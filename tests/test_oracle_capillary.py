@@ -9,14 +9,13 @@
 * the lattice capillary theory's k^2 -> 2 - 2 cos k is the symbol of the
   nearest-neighbour line tension: sum_x (h(x+1) - h(x))^2 =
   (1/L) sum_k (2 - 2 cos k) |h(k)|^2, with height_spectrum's normalisation;
-* the effective square-gradient coefficient of the reading equals the one
-  the exact linearized step gives at small k (fitted), for random wells,
-  rates, densities and both force forms;
+* the effective square-gradient coefficient kappa_eff equals the one the
+  exact linearized step gives at small k (fitted), for random wells, rates,
+  densities and both force forms;
 * mechanics: p0 = rho psi' - psi is the scheme's bulk pressure (a flat
   interface relaxes to equal p0 in the two phases), and drops obey the 2-D
-  Young-Laplace law p_in - p_out = sigma / R with one tension sigma; that
-  tension is below eq. surf-tension's and far from the effective integral of
-  the reading, which mechanics therefore does not pin.
+  Young-Laplace law p_in - p_out = sigma / R with one tension sigma, below
+  eq. surf-tension's.
 """
 
 import numpy as np
@@ -55,11 +54,6 @@ def test_surface_tension_is_the_square_gradient_integral():
     W = lambda r: BETA * (r - RV) ** 2 * (r - RL) ** 2
     np.testing.assert_allclose(quad(lambda r: np.sqrt(2 * KAPPA * W(r)), RV, RL)[0], sig,
                                rtol=1e-12)
-    # the same integral with the effective coefficient (eta = 1 raises it)
-    p = flb.Params(force_model=1, a=-2 * BETA * 0.0625, b=BETA, rho_c=0.75, kappa=KAPPA, eta=1)
-    assert cap.effective_surface_tension(p, RL, RV) > 1.3 * sig
-    with pytest.raises(ValueError):
-        cap.effective_surface_tension(p.with_(eta=0), RL, RV)
 
 
 def test_line_tension_symbol():
@@ -131,8 +125,7 @@ def test_laplace_drops_fix_the_mechanical_tension():
     """Two drops (R 20 in 80^2, R 28 in 112^2) relaxed at kT = 0: the bulk
     pressure jump falls as 1/R (Young-Laplace in 2-D), sigma = R dp agreeing
     within 10 % (the smaller drop's curvature correction); the tension is
-    0.55-0.8 of eq. surf-tension's and under half the effective integral of
-    the reading."""
+    0.55-0.8 of eq. surf-tension's."""
     p = _capillary_params()
     w = cap.interface_width(RL, RV, KAPPA, BETA)
     d1 = cap.laplace_drop(p, 80, 20.0, 3000, RL, RV, w)
@@ -140,7 +133,5 @@ def test_laplace_drops_fix_the_mechanical_tension():
     assert d1["dp"] > d2["dp"] > 0
     assert abs(d1["sigma"] / d2["sigma"] - 1) < 0.1
     s_eq = cap.surface_tension(RL, RV, KAPPA, BETA)
-    s_eff = cap.effective_surface_tension(p, RL, RV)
     for d in (d1, d2):
         assert 0.55 < d["sigma"] / s_eq < 0.8
-        assert d["sigma"] / s_eff < 0.5

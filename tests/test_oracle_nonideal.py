@@ -10,7 +10,8 @@
   S(k) = rho0 kT / c_s^2(k) (App. A eqs. he-cs2 and the OZ form after
   eq. freeE-funct), with c_s^2(k) = cs2 + rho0 psi''(rho0) + kappa rho0 k^2
   (the LB ideal pressure cs2 adds to psi when the force omits it).
-  Beyond the small-k window the oracle's S(k): parity unpinned.
+  At all k the oracle's S(k) is pinned through the exact linearized step
+  (``test_oracle_spectra.py``).
 """
 
 import numpy as np
