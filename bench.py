@@ -692,6 +692,9 @@ def main():
     ap.add_argument("--profile-landau", action="store_true",
                     help="only run the d3q19_256_landau step (FP32, statistics every step) in "
                          "launch configuration 8 (z-marching 128 x 2 columns, 16 planes), 6 steps")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="only run the d3q19_batch64 replicas (FP32, statistics every step), "
+                         "in-place groups of up to 256 MiB, 4 steps")
     ap.add_argument("--profile-256", action="store_true",
                     help="only run the d3q19_128 step on 256^3 (FP32, statistics every step): "
                          "in-place pairs (128 x 2) and two buffers (128 x 2), 20 steps each")
@@ -712,6 +715,8 @@ def main():
         profile_256()
     elif args.profile_landau:
         profile_landau()
+    elif args.profile_batch:
+        profile_batch()
     else:
         bench_main(args)
 
@@ -797,6 +802,25 @@ def profile_landau():
     sim.step(6, stats_stride=1)
     torch.cuda.synchronize()
     print(json.dumps({"profile_landau": 8, "steps": 6}))
+
+
+def profile_batch():
+    """The 64 uneven replicas in the grouped in-place schedule (groups of up
+    to 256 MiB, default grid), for kernel counters."""
+    import torch
+
+    import flb_workloads as W
+    from paper_1012_3632_amd import Batch, Params
+    wl = W.WORKLOADS["d3q19_batch64"]
+    edges = W.batch_edges(wl["replicas"], wl["edges"], wl["size_seed"])
+    pb = Params.from_dict(dict(lattice="D3Q19", precision="fp32", rho0=1.0, kT=wl["kT"],
+                               rate_bulk=wl["rate_bulk"], rate_shear=wl["rate_shear"],
+                               rate_ghost=wl["rate_ghost"]))
+    b = Batch(pb, [(e, e, e) for e in edges], seeds=list(range(wl["replicas"])))
+    b.set_pairs(256 << 20)
+    b.step(4, stats_stride=1)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_batch": list(b.pairs()), "steps": 4}))
 
 
 def profile_256():

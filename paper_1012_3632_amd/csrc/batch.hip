@@ -56,42 +56,86 @@ struct RepInfo {
 
 __device__ __forceinline__ uint32_t div_small(uint32_t s, uint32_t inv) { return __umulhi(s, inv); }
 
-// Periodic neighbourhood of a site of one replica: the x of x - 1, x, x + 1,
-// the row offsets (y - 1, y, y + 1) nx and the plane offsets (z - 1, z,
-// z + 1) nx ny, so that the site index of x + c is three additions.
+// Periodic neighbourhood of site s = x + nx (y + ny z) of one replica, in
+// bytes: s4 = s sizeof(Real) and the wrapped byte steps to x -+ 1, y -+ 1 and
+// z -+ 1 (modulo 2^32), each a selection between two uniform values, so that
+// the byte offset of x + c is s4 plus up to three of them (no multiplies;
+// the partial sums are shared between directions).
+template <typename Real>
 struct Nbr {
-    uint32_t xs[3], row[3], pl[3];
-    __device__ __forceinline__ Nbr(int x, int y, int z, const struct RepInfo& R);
+    uint32_t s4, dx[2], dy[2], dz[2];
+    __device__ __forceinline__ Nbr(uint32_t s, int x, int y, int z, const struct RepInfo& R);
     __device__ __forceinline__ uint32_t at(int cx, int cy, int cz) const {
-        return pl[1 + cz] + row[1 + cy] + xs[1 + cx];
+        uint32_t o = s4;
+        if (cz) o += dz[cz > 0];
+        if (cy) o += dy[cy > 0];
+        if (cx) o += dx[cx > 0];
+        return o;
     }
 };
-__device__ __forceinline__ Nbr::Nbr(int x, int y, int z, const RepInfo& R) {
-    const uint32_t nx = (uint32_t)R.nx, nxy = (uint32_t)R.nx * (uint32_t)R.ny;
-    xs[0] = (uint32_t)(x == 0 ? R.nx - 1 : x - 1);
-    xs[1] = (uint32_t)x;
-    xs[2] = (uint32_t)(x == R.nx - 1 ? 0 : x + 1);
-    row[0] = (uint32_t)(y == 0 ? R.ny - 1 : y - 1) * nx;
-    row[1] = (uint32_t)y * nx;
-    row[2] = (uint32_t)(y == R.ny - 1 ? 0 : y + 1) * nx;
-    pl[0] = (uint32_t)(z == 0 ? R.nz - 1 : z - 1) * nxy;
-    pl[1] = (uint32_t)z * nxy;
-    pl[2] = (uint32_t)(z == R.nz - 1 ? 0 : z + 1) * nxy;
+template <typename Real>
+__device__ __forceinline__ Nbr<Real>::Nbr(uint32_t s, int x, int y, int z, const RepInfo& R) {
+    constexpr uint32_t E = sizeof(Real);
+    const uint32_t ex = E, ey = E * (uint32_t)R.nx, ez = ey * (uint32_t)R.ny;
+    const uint32_t wx = ey - ex, wy = ez - ey, wz = E * R.V - ez;   // a wrap: period minus a step
+    s4 = s * E;
+    dx[0] = x == 0 ? wx : 0u - ex;
+    dx[1] = x == R.nx - 1 ? 0u - wx : ex;
+    dy[0] = y == 0 ? wy : 0u - ey;
+    dy[1] = y == R.ny - 1 ? 0u - wy : ey;
+    dz[0] = z == 0 ? wz : 0u - ez;
+    dz[1] = z == R.nz - 1 ? 0u - wz : ez;
 }
 
-// Population accesses of one replica: one base pointer (rep) and 32-bit
-// element offsets i V + site (a replica's populations stay below 2^31
-// elements: V < 2^24 sites).  V is made opaque to the compiler by the
-// caller once per tile, so that the Q plane offsets are formed next to their
-// accesses instead of being hoisted out of the tile loop as Q separate
-// 64-bit plane bases (which spill).
+// The populations of one replica (Q planes of V sites from rep) as a buffer
+// resource: an access is the resource plus a uniform byte offset (plane i:
+// i V sizeof(Real), an SGPR) plus the lane's 32-bit byte offset, so no lane
+// forms a 64-bit address.  The record count is the replica's population
+// bytes (a replica has V < 2^24 sites).  V is made opaque to the compiler by
+// the caller once per tile (an empty asm on an SGPR), so that the plane
+// offsets are formed next to their accesses instead of being hoisted out of
+// the tile loop and held.  Word 3 of the resource is the CDNA raw-buffer
+// format (32-bit data format, no swizzle, no stride).
 template <int LAT, typename Real>
-__device__ __forceinline__ void rep_pull(const Real* rep, uint32_t V, const Nbr& nb,
-                                         Real (&f)[Lattice<LAT>::Q]) {
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rep_rsrc(const Real* rep, uint32_t V) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<Real*>(rep), 0,
+                                             (int)((uint32_t)Lattice<LAT>::Q * V * sizeof(Real)),
+                                             0x00020000);
+}
+__device__ __forceinline__ uint32_t plane_soff(uint32_t Vr, int i, uint32_t esize) {
+    return (uint32_t)i * Vr * esize;
+}
+__device__ __forceinline__ float rep_ld(__amdgpu_buffer_rsrc_t r, uint32_t Vr, int i, uint32_t boff,
+                                        float) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)boff, (int)plane_soff(Vr, i, 4), 0));
+}
+__device__ __forceinline__ double rep_ld(__amdgpu_buffer_rsrc_t r, uint32_t Vr, int i,
+                                         uint32_t boff, double) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 w = __builtin_amdgcn_raw_buffer_load_b64(r, (int)boff, (int)plane_soff(Vr, i, 8), 0);
+    return __longlong_as_double((long long)(((unsigned long long)w.y << 32) | w.x));
+}
+__device__ __forceinline__ void rep_st(__amdgpu_buffer_rsrc_t r, uint32_t Vr, int i, uint32_t boff,
+                                       float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)boff, (int)plane_soff(Vr, i, 4), 0);
+}
+__device__ __forceinline__ void rep_st(__amdgpu_buffer_rsrc_t r, uint32_t Vr, int i, uint32_t boff,
+                                       double v) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    u2 w;
+    w.x = (unsigned int)b;
+    w.y = (unsigned int)(b >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)boff, (int)plane_soff(Vr, i, 8), 0);
+}
+
+template <int LAT, typename Real>
+__device__ __forceinline__ void rep_pull(__amdgpu_buffer_rsrc_t rep, uint32_t Vr,
+                                         const Nbr<Real>& nb, Real (&f)[Lattice<LAT>::Q]) {
     using L = Lattice<LAT>;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        f[i] = plane_ld(rep, (uint32_t)i * V + nb.at(-L::cx[i], -L::cy[i], -L::cz[i]));
+        f[i] = rep_ld(rep, Vr, i, nb.at(-L::cx[i], -L::cy[i], -L::cz[i]), Real(0));
 }
 
 template <int LAT, typename Real, bool STATS>
@@ -130,7 +174,8 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
                 const uint32_t z = div_small(yz, R.inv_ny);
                 const int y = (int)(yz - z * (uint32_t)R.ny);
                 Real f[Q], m[Q];
-                rep_pull<LAT, Real>(fin + R.off, Vr, Nbr(x, y, (int)z, R), f);
+                rep_pull<LAT, Real>(rep_rsrc<LAT, Real>(fin + R.off, R.V), Vr,
+                                    Nbr<Real>(s, x, y, (int)z, R), f);
                 M::forward(f, m);
                 if constexpr (STATS) {
 #pragma unroll
@@ -144,9 +189,12 @@ __global__ __launch_bounds__(BT) void k_batch_step(const Real* __restrict__ fin,
                 const Real F[D] = {};
                 collide_moments<LAT, Real, false>(m, F, zn, P);
                 M::inverse(m, f);
-                Real* out = fout + R.off;
+                const __amdgpu_buffer_rsrc_t out = rep_rsrc<LAT, Real>(fout + R.off, R.V);
+                const uint32_t s4 = s * (uint32_t)sizeof(Real);
+                uint32_t Vs = Vr;   // the store offsets are not those of the loads
+                asm volatile("" : "+s"(Vs));
 #pragma unroll
-                for (int i = 0; i < Q; ++i) plane_st(out, (uint32_t)i * Vr + s, f[i]);
+                for (int i = 0; i < Q; ++i) rep_st(out, Vs, i, s4, f[i]);
             }
         }
         // the two LDS buffers alternate: the barrier inside the finish of
@@ -182,7 +230,7 @@ __global__ __launch_bounds__(BT) void k_batch_step_ip(Real* f, const RepInfo* __
         const RepInfo R = reps[r];
         const uint32_t s0 = (c - R.chunk0) * (uint32_t)BT;
         const uint32_t ds = R.nchunks * (uint32_t)BT;
-        Real* base = f + R.off;
+        const __amdgpu_buffer_rsrc_t rb = rep_rsrc<LAT, Real>(f + R.off, R.V);
         Real v[STATS ? 2 * Q : 1];
         if constexpr (STATS) {
 #pragma unroll
@@ -201,11 +249,12 @@ __global__ __launch_bounds__(BT) void k_batch_step_ip(Real* f, const RepInfo* __
                 const int y = (int)(yz - z * (uint32_t)R.ny);
                 Real fl[Q], m[Q];
                 if constexpr (PH == 0) {
-                    rep_pull<LAT, Real>(base, Vr, Nbr(x, y, (int)z, R), fl);
+                    rep_pull<LAT, Real>(rb, Vr, Nbr<Real>(s, x, y, (int)z, R), fl);
                 } else {
-                    // local accesses: uniform plane bases, one lane offset
+                    // local accesses: one lane offset for every plane
+                    const uint32_t s4 = s * (uint32_t)sizeof(Real);
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) fl[i] = plane_ld(base + (size_t)L::opp[i] * R.V, s);
+                    for (int i = 0; i < Q; ++i) fl[i] = rep_ld(rb, Vr, L::opp[i], s4, Real(0));
                 }
                 M::forward(fl, m);
                 if constexpr (STATS) {
@@ -225,13 +274,18 @@ __global__ __launch_bounds__(BT) void k_batch_step_ip(Real* f, const RepInfo* __
                     // in registers through it)
                     int xs = x;
                     asm volatile("" : "+v"(xs));
-                    const Nbr nb(xs, y, (int)z, R);
+                    const Nbr<Real> nb(s, xs, y, (int)z, R);
+                    uint32_t Vs = Vr;   // the store offsets are not those of the loads
+                    asm volatile("" : "+s"(Vs));
 #pragma unroll
                     for (int i = 0; i < Q; ++i)
-                        plane_st(base, (uint32_t)L::opp[i] * Vr + nb.at(L::cx[i], L::cy[i], L::cz[i]), fl[i]);
+                        rep_st(rb, Vs, L::opp[i], nb.at(L::cx[i], L::cy[i], L::cz[i]), fl[i]);
                 } else {
+                    const uint32_t s4 = s * (uint32_t)sizeof(Real);
+                    uint32_t Vs = Vr;
+                    asm volatile("" : "+s"(Vs));
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) plane_st(base + (size_t)i * R.V, s, fl[i]);
+                    for (int i = 0; i < Q; ++i) rep_st(rb, Vs, i, s4, fl[i]);
                 }
             }
         }

@@ -49,6 +49,51 @@ __global__ void k_density(const Real* __restrict__ fin, Real* __restrict__ out, 
     out[s] = acc;
 }
 
+// The collision and store of one site of k_step from its pulled populations
+// f; FIRST: the first site this thread adds to its statistics, which then
+// take its moments directly (no zeroed accumulators).
+template <int LAT, typename Real, bool FORCE, bool STATS, bool ROWS, bool NTS, bool FIRST>
+__device__ __forceinline__ void step_site(Real (&f)[Lattice<LAT>::Q], Real* __restrict__ fout,
+                                          int x, int y, int z, const Geom& g,
+                                          const CollideParams<Real>& P,
+                                          const Real (&F)[Lattice<LAT>::D], uint32_t step,
+                                          const double2* tab, Real* v) {
+    using L = Lattice<LAT>;
+    using M = Moments<LAT, Real>;
+    constexpr int Q = L::Q;
+    Real m[Q];
+    M::forward(f, m);
+    if constexpr (STATS) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            if constexpr (FIRST) {
+                v[a] = m[a];
+                v[Q + a] = m[a] * m[a];
+            } else {
+                v[a] += m[a];
+                v[Q + a] += m[a] * m[a];
+            }
+        }
+    }
+    const uint32_t site = site_index<LAT>(x, y, z, g);
+    Real zn[2 * L::NPAIR];
+    if (P.noise_on)
+        site_normals<L::NPAIR, Real>(site, step, 0u, P.replica, P.key0, P.key1, zn, tab);
+    collide_moments<LAT, Real, FORCE>(m, F, zn, P);
+    M::inverse(m, f);
+    if constexpr (ROWS) {
+        const size_t row = (size_t)(uint32_t)((z * g.ny + y) * g.nx);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if constexpr (NTS) plane_st_nt(fout + ((size_t)i * g.V + row), (uint32_t)x, f[i]);
+            else plane_st(fout + ((size_t)i * g.V + row), (uint32_t)x, f[i]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) plane_st(fout + (size_t)i * g.V, site, f[i]);
+    }
+}
+
 template <int LAT, typename Real, bool FORCE, bool STATS, int TX, int TY, int TZ, int SPT,
           bool NTS, bool FUSED = false>
 __global__ __launch_bounds__(TX* TY* TZ) void k_step(
@@ -101,17 +146,8 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
         if (in0) FT::force(lds_force, lds_force + FT::NR, fp, P.rho0, tx, ty, tz, F);
     }
 
-    Real v[2 * Q];
-    if constexpr (STATS) {
-#pragma unroll
-        for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
-    }
-#pragma unroll
-    for (int sp = 0; sp < SPT; ++sp) {
-    const int y = y0 + ty + sp * TY;
-    const bool inside = x < g.nx && y < g.ny && z < g.nz;
-    if (inside) {
-        Real f[Q], m[Q];
+    // pulled populations of one site (the force path has them already)
+    auto pull_site = [&](int y, Real (&f)[Q]) {
         if constexpr (FORCE) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) f[i] = fpre[i];
@@ -120,32 +156,39 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
         } else {
             pull<LAT, Real>(fin, x, y, z, g, f);
         }
-        M::forward(f, m);
+    };
+    const uint32_t step = st.get();
+    Real v[2 * Q];
+    if (x0 + TX <= g.nx && y0 + TY * SPT <= g.ny && z0 + TZ <= g.nz) {
+        // the tile lies inside the lattice (uniform): no per-lane checks
+        {
+            Real f[Q];
+            pull_site(y0 + ty, f);
+            step_site<LAT, Real, FORCE, STATS, ROWS, NTS, true>(f, fout, x, y0 + ty, z, g, P, F,
+                                                                step, tab, v);
+        }
+#pragma unroll
+        for (int sp = 1; sp < SPT; ++sp) {
+            Real f[Q];
+            pull_site(y0 + ty + sp * TY, f);
+            step_site<LAT, Real, FORCE, STATS, ROWS, NTS, false>(f, fout, x, y0 + ty + sp * TY, z,
+                                                                 g, P, F, step, tab, v);
+        }
+    } else {
         if constexpr (STATS) {
 #pragma unroll
-            for (int a = 0; a < Q; ++a) {
-                v[a] += m[a];
-                v[Q + a] += m[a] * m[a];
+            for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
+        }
+#pragma unroll
+        for (int sp = 0; sp < SPT; ++sp) {
+            const int y = y0 + ty + sp * TY;
+            if (x < g.nx && y < g.ny && z < g.nz) {
+                Real f[Q];
+                pull_site(y, f);
+                step_site<LAT, Real, FORCE, STATS, ROWS, NTS, false>(f, fout, x, y, z, g, P, F,
+                                                                     step, tab, v);
             }
         }
-        const uint32_t site = site_index<LAT>(x, y, z, g);
-        Real zn[2 * L::NPAIR];
-        if (P.noise_on)
-            site_normals<L::NPAIR, Real>(site, st.get(), 0u, P.replica, P.key0, P.key1, zn, tab);
-        collide_moments<LAT, Real, FORCE>(m, F, zn, P);
-        M::inverse(m, f);
-        if constexpr (ROWS) {
-            const size_t row = (size_t)(uint32_t)((z * g.ny + y) * g.nx);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                if constexpr (NTS) plane_st_nt(fout + ((size_t)i * g.V + row), (uint32_t)x, f[i]);
-                else plane_st(fout + ((size_t)i * g.V + row), (uint32_t)x, f[i]);
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) plane_st(fout + (size_t)i * g.V, site, f[i]);
-        }
-    }
     }
     if constexpr (STATS) {
         const uint32_t b = xcd_remap(blockIdx.x, g.nblocks);
@@ -161,12 +204,61 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
 // gives bit-identical populations to two ordinary steps.  With one buffer
 // instead of two the working set of a lattice is halved, which lets a 128^3
 // FP32 D3Q19 state stay in the 256 MB last-level cache.
+// The update of one site of an in-place pair; FIRST: the site is the first
+// this thread adds to its statistics, which take its moments directly (no
+// zeroed accumulators to merge with lanes that skip a site).
+template <int LAT, typename Real, bool STATS, int PH, bool FIRST>
+__device__ __forceinline__ void ip_site(Real* f, int x, int y, int z, const Geom& g,
+                                        const CollideParams<Real>& P, uint32_t step,
+                                        const double2* tab, Real* v) {
+    using L = Lattice<LAT>;
+    using M = Moments<LAT, Real>;
+    constexpr int Q = L::Q, D = L::D;
+    Real fl[Q], m[Q];
+    if constexpr (PH == 0) pull_rows<LAT, Real>(f, x, y, z, g, fl);
+    else load_rows_opp<LAT, Real>(f, x, y, z, g, fl);
+    M::forward(fl, m);
+    if constexpr (STATS) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            if constexpr (FIRST) {
+                v[a] = m[a];
+                v[Q + a] = m[a] * m[a];
+            } else {
+                v[a] += m[a];
+                v[Q + a] += m[a] * m[a];
+            }
+        }
+    }
+    const uint32_t site = site_index<LAT>(x, y, z, g);
+    Real zn[2 * L::NPAIR];
+    if (P.noise_on) site_normals<L::NPAIR, Real>(site, step, 0u, P.replica, P.key0, P.key1, zn, tab);
+    const Real F[D] = {};
+    collide_moments<LAT, Real, false>(m, F, zn, P);
+    M::inverse(m, fl);
+    // x is re-read here so that the store addresses are formed late
+    // (not held in registers through the collision)
+    int xs = x;
+    asm volatile("" : "+v"(xs));
+    if constexpr (PH == 0) push_rows_opp<LAT, Real>(f, xs, y, z, g, fl);
+    else store_rows<LAT, Real>(f, xs, y, z, g, fl);
+}
+
+// One step of an in-place pair (ideal gas), phase PH = 0 (pull, push to the
+// opposite plane at x + c_i) or 1 (local read of the opposite plane, store in
+// the ordinary layout); see push_rows_opp.  Tiles of TX x (TY SPT) sites, TX a
+// multiple of 64, SPT sites per thread stacked in y as in k_step; the
+// collision, noise counters and statistics are those of k_step, so a pair
+// gives bit-identical populations to two ordinary steps.  With one buffer
+// instead of two the working set of a lattice is halved, which lets a 128^3
+// FP32 D3Q19 state stay in the 256 MB last-level cache.  A tile inside the
+// lattice (the test is uniform over the block) takes a path with no per-lane
+// range checks.
 template <int LAT, typename Real, bool STATS, int PH, int TX, int TY, int SPT = 1>
 __global__ __launch_bounds__(TX* TY) void k_step_ip(Real* f, Geom g, CollideParams<Real> P,
                                                      StepIndex st, double* __restrict__ partial) {
     using L = Lattice<LAT>;
-    using M = Moments<LAT, Real>;
-    constexpr int Q = L::Q, D = L::D, NT = TX * TY;
+    constexpr int Q = L::Q, NT = TX * TY;
     static_assert(TX % 64 == 0, "one (y, z) row per wavefront");
     constexpr int LDS_S = STATS ? 4 * (NT / 64) * 2 * Q : 1;
     __shared__ double lds_stats[LDS_S];
@@ -176,40 +268,24 @@ __global__ __launch_bounds__(TX* TY) void k_step_ip(Real* f, Geom g, CollidePara
     const int tx = threadIdx.x % TX;
     const int ty = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / TX));
     const int x = x0 + tx, z = z0;
+    const uint32_t step = st.get();
     Real v[STATS ? 2 * Q : 1];
-    if constexpr (STATS) {
+    if (x0 + TX <= g.nx && y0 + TY * SPT <= g.ny && z < g.nz) {
+        ip_site<LAT, Real, STATS, PH, true>(f, x, y0 + ty, z, g, P, step, tab, v);
 #pragma unroll
-        for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
-    }
-#pragma unroll
-    for (int sp = 0; sp < SPT; ++sp) {
-    const int y = y0 + ty + sp * TY;
-    if (x < g.nx && y < g.ny && z < g.nz) {
-        Real fl[Q], m[Q];
-        if constexpr (PH == 0) pull_rows<LAT, Real>(f, x, y, z, g, fl);
-        else load_rows_opp<LAT, Real>(f, x, y, z, g, fl);
-        M::forward(fl, m);
+        for (int sp = 1; sp < SPT; ++sp)
+            ip_site<LAT, Real, STATS, PH, false>(f, x, y0 + ty + sp * TY, z, g, P, step, tab, v);
+    } else {
         if constexpr (STATS) {
 #pragma unroll
-            for (int a = 0; a < Q; ++a) {
-                v[a] += m[a];
-                v[Q + a] += m[a] * m[a];
-            }
+            for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
         }
-        const uint32_t site = site_index<LAT>(x, y, z, g);
-        Real zn[2 * L::NPAIR];
-        if (P.noise_on)
-            site_normals<L::NPAIR, Real>(site, st.get(), 0u, P.replica, P.key0, P.key1, zn, tab);
-        const Real F[D] = {};
-        collide_moments<LAT, Real, false>(m, F, zn, P);
-        M::inverse(m, fl);
-        // x is re-read here so that the store addresses are formed late
-        // (not held in registers through the collision)
-        int xs = x;
-        asm volatile("" : "+v"(xs));
-        if constexpr (PH == 0) push_rows_opp<LAT, Real>(f, xs, y, z, g, fl);
-        else store_rows<LAT, Real>(f, xs, y, z, g, fl);
-    }
+#pragma unroll
+        for (int sp = 0; sp < SPT; ++sp) {
+            const int y = y0 + ty + sp * TY;
+            if (x < g.nx && y < g.ny && z < g.nz)
+                ip_site<LAT, Real, STATS, PH, false>(f, x, y, z, g, P, step, tab, v);
+        }
     }
     if constexpr (STATS) {
         const uint32_t b = xcd_remap(blockIdx.x, g.nblocks);
