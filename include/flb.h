@@ -253,8 +253,8 @@ flb_status flb_interface_heights(flb_handle* h, const flb_interface* ifs, int32_
  * --------------------------------------------------------------------- */
 typedef struct flb_modeq_params {
     int32_t nx, ny;       /* periodic lattice, each in [1, 1024]                        */
-    int32_t precision;    /* FLB_FP32 or FLB_FP64 (state and step arithmetic; the noise
-                             transforms are FP64)                                        */
+    int32_t precision;    /* FLB_FP32 or FLB_FP64: state, step arithmetic and the noise
+                             transforms and fields                                       */
     int32_t reserved;     /* 0                                                          */
     double rho0;          /* > 0                                                        */
     double kT;            /* >= 0; 0 runs the deterministic step and needs no work      */
@@ -264,9 +264,9 @@ typedef struct flb_modeq_params {
     uint64_t seed;        /* Philox key                                                 */
 } flb_modeq_params;
 
-/* Minimum device work bytes of flb_modeq_step / _run / _noise: 48 V per
- * step of a noise batch (the complex noise spectra, then the filtered
- * fields).  Rejects invalid parameters
+/* Minimum device work bytes of flb_modeq_step / _run / _noise: per step of
+ * a noise batch the two complex noise spectra and the two filtered fields,
+ * 24 V bytes in FP32 and 48 V in FP64.  Rejects invalid parameters
  * (FLB_ERR_INVALID_ARG), including rates for which the (e, eps) covariance
  * is not positive semidefinite somewhere on [cs2_0, cs2_0 + kappa rho0 16/3]. */
 flb_status flb_modeq_work_bytes(const flb_modeq_params* p, size_t* bytes);
@@ -280,7 +280,8 @@ flb_status flb_modeq_step(const flb_modeq_params* p, const void* fin, void* fout
 
 /* nsteps steps with indices step0 .. step0 + nsteps - 1; the result is in f,
  * tmp (device, 9 V reals) is overwritten.  The noise of consecutive steps is
- * drawn and filtered in batches of b = min(16, work_bytes / (48 V)) steps
+ * drawn and filtered in batches of b = min(16, work_bytes / w) steps, w the
+ * per-step bytes of flb_modeq_work_bytes
  * (one launch set per batch; a larger work buffer fills more of the chip at
  * small lattices).  The result does not depend on b. */
 flb_status flb_modeq_run(const flb_modeq_params* p, void* f, void* tmp, uint64_t step0,
@@ -292,8 +293,9 @@ flb_status flb_modeq_run(const flb_modeq_params* p, void* f, void* tmp, uint64_t
  * device array inside the library instead of a caller buffer.  The array
  * holds flb_modeq_static_work_bytes() bytes (16 MiB) on each GPU the library
  * runs on, from its first use there until the process ends, so the step
- * needs 48 V <= 16 MiB (V <= 349525 sites, e.g. 512 x 512; kT = 0 needs no
- * work and has no limit); larger lattices are rejected with
+ * needs 24 V <= 16 MiB in FP32 (V <= 699050 sites, e.g. 1024 x 512) and
+ * 48 V <= 16 MiB in FP64 (V <= 349525, e.g. 512 x 512); kT = 0 needs no
+ * work and has no limit; larger lattices are rejected with
  * FLB_ERR_INVALID_ARG before anything is queued.  fin, fout as for
  * flb_modeq_step.  Calls no allocator.  Every call on a GPU uses that GPU's
  * one array: calls that overlap on one GPU (other streams, other threads)
@@ -309,8 +311,8 @@ flb_status flb_modeq_static_work_bytes(size_t* bytes);
 flb_status flb_modeq_moments(const flb_modeq_params* p, const void* f, double* m, void* stream);
 
 /* Verification: the filtered (e, eps) noise of step `step`, xi[0 .. V) = xi_e,
- * xi[V .. 2V) = xi_eps (device, FP64). */
-flb_status flb_modeq_noise(const flb_modeq_params* p, uint64_t step, double* xi, void* work,
+ * xi[V .. 2V) = xi_eps (device, reals of p->precision). */
+flb_status flb_modeq_noise(const flb_modeq_params* p, uint64_t step, void* xi, void* work,
                            size_t work_bytes, void* stream);
 
 /* Verification: the raw Philox4x32-10 words the step draws for noise block

@@ -948,6 +948,7 @@ flb_status modeq_args(const flb_modeq_params* p, ModEqArgs* a) {
         return fail(FLB_ERR_INVALID_ARG, "modified-equilibrium extents must be in [1, 1024]");
     if (p->precision != FLB_FP32 && p->precision != FLB_FP64)
         return fail(FLB_ERR_INVALID_ARG, "precision must be FLB_FP32 or FLB_FP64");
+    a->prec = p->precision == FLB_FP64 ? 1 : 0;
     if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0) || !(p->kT >= 0.0) || !std::isfinite(p->kT))
         return fail(FLB_ERR_INVALID_ARG, "rho0 must be positive and kT >= 0");
     const double rates[3] = {p->rate_bulk, p->rate_shear, p->rate_ghost};
@@ -989,13 +990,21 @@ flb_status modeq_args(const flb_modeq_params* p, ModEqArgs* a) {
     return FLB_OK;
 }
 
+// The filtered noise fields of a batch of nb steps follow its nb complex
+// spectrum pairs in the work buffer.
+void* modeq_fields(const ModEqArgs& a, void* work, int nb) {
+    const size_t V = (size_t)a.nx * a.ny;
+    const size_t csize = a.prec == 0 ? 2 * sizeof(float) : 2 * sizeof(double);
+    return (char*)work + (size_t)nb * 2 * V * csize;
+}
+
 flb_status modeq_work_ok(const ModEqArgs& a, const void* work, size_t work_bytes) {
     if (a.kT == 0.0) return FLB_OK;
     if (!work) return fail(FLB_ERR_INVALID_ARG, "work is NULL");
     if (!aligned(work)) return fail(FLB_ERR_INVALID_ARG, "work must be 256-byte aligned");
-    if (work_bytes < modeq_work_bytes(a.nx, a.ny))
+    if (work_bytes < modeq_work_bytes(a.nx, a.ny, a.prec))
         return fail(FLB_ERR_INVALID_ARG, "work holds %zu bytes, %zu needed", work_bytes,
-                    modeq_work_bytes(a.nx, a.ny));
+                    modeq_work_bytes(a.nx, a.ny, a.prec));
     return FLB_OK;
 }
 
@@ -1006,19 +1015,21 @@ flb_status flb_modeq_work_bytes(const flb_modeq_params* p, size_t* bytes) {
     if (!bytes) return fail(FLB_ERR_INVALID_ARG, "NULL bytes");
     const flb_status r = modeq_args(p, &a);
     if (r != FLB_OK) return r;
-    *bytes = modeq_work_bytes(a.nx, a.ny);
+    *bytes = modeq_work_bytes(a.nx, a.ny, a.prec);
     return FLB_OK;
 }
 
-flb_status flb_modeq_noise(const flb_modeq_params* p, uint64_t step, double* xi, void* work,
+flb_status flb_modeq_noise(const flb_modeq_params* p, uint64_t step, void* xi, void* work,
                            size_t work_bytes, void* stream) {
     ModEqArgs a{};
     flb_status r = modeq_args(p, &a);
     if (r != FLB_OK) return r;
     if (!xi || !work) return fail(FLB_ERR_INVALID_ARG, "NULL argument");
     if (!aligned(work)) return fail(FLB_ERR_INVALID_ARG, "work must be 256-byte aligned");
-    if ((uintptr_t)xi % sizeof(double)) return fail(FLB_ERR_INVALID_ARG, "xi must be 8-byte aligned");
-    if (work_bytes < modeq_work_bytes(a.nx, a.ny))
+    const size_t rsize = a.prec == 0 ? sizeof(float) : sizeof(double);
+    if ((uintptr_t)xi % rsize)
+        return fail(FLB_ERR_INVALID_ARG, "xi must be aligned to its %zu-byte reals", rsize);
+    if (work_bytes < modeq_work_bytes(a.nx, a.ny, a.prec))
         return fail(FLB_ERR_INVALID_ARG, "work too small");
     HIP_TRY(launch_modeq_noise(a, p->precision, (uint32_t)step, 1, work, xi, (hipStream_t)stream));
     return FLB_OK;
@@ -1046,10 +1057,9 @@ flb_status flb_modeq_step(const flb_modeq_params* p, const void* fin, void* fout
         return fail(FLB_ERR_INVALID_ARG, "populations must be 256-byte aligned");
     if ((r = modeq_work_ok(a, work, work_bytes)) != FLB_OK) return r;
     const hipStream_t st = (hipStream_t)stream;
-    const size_t V = (size_t)a.nx * a.ny;
-    double* xi = nullptr;
+    void* xi = nullptr;
     if (a.kT > 0.0) {
-        xi = (double*)((char*)work + 2 * V * sizeof(double2));
+        xi = modeq_fields(a, work, 1);
         HIP_TRY(launch_modeq_noise(a, p->precision, (uint32_t)step, 1, work, xi, st));
     }
     HIP_TRY(launch_modeq_step(a, p->precision, fin, fout, (uint32_t)step, xi, st));
@@ -1115,22 +1125,22 @@ flb_status flb_modeq_step_noalloc(const flb_modeq_params* p, const void* fin, vo
     if (fin == fout) return fail(FLB_ERR_INVALID_ARG, "fin and fout must differ");
     if (!aligned(fin) || !aligned(fout))
         return fail(FLB_ERR_INVALID_ARG, "populations must be 256-byte aligned");
-    const size_t need = a.kT > 0.0 ? modeq_work_bytes(a.nx, a.ny) : 0;
+    const size_t need = a.kT > 0.0 ? modeq_work_bytes(a.nx, a.ny, a.prec) : 0;
     if (need > MODEQ_STATIC_BYTES)
         return fail(FLB_ERR_INVALID_ARG,
                     "the step needs %zu bytes of noise work, the fixed device array holds %zu "
-                    "(%d x %d sites is more than 48 V <= %zu allows)",
-                    need, MODEQ_STATIC_BYTES, a.nx, a.ny, MODEQ_STATIC_BYTES);
+                    "(%d x %d sites is more than %d V <= %zu allows)",
+                    need, MODEQ_STATIC_BYTES, a.nx, a.ny, a.prec == 0 ? 24 : 48,
+                    MODEQ_STATIC_BYTES);
     const hipStream_t st = (hipStream_t)stream;
-    double* xi = nullptr;
+    void* xi = nullptr;
     if (a.kT > 0.0) {
         void* work = nullptr;
         if ((r = static_scratch(&work)) != FLB_OK) return r;
         // every byte the noise kernels read is written first in the same call
         // (spectra by the row transform, fields by the inverse), so nothing
         // has to be cleared
-        const size_t V = (size_t)a.nx * a.ny;
-        xi = (double*)((char*)work + 2 * V * sizeof(double2));
+        xi = modeq_fields(a, work, 1);
         HIP_TRY(launch_modeq_noise(a, p->precision, (uint32_t)step, 1, work, xi, st));
     }
     HIP_TRY(launch_modeq_step(a, p->precision, fin, fout, (uint32_t)step, xi, st));
@@ -1149,14 +1159,15 @@ flb_status flb_modeq_run(const flb_modeq_params* p, void* f, void* tmp, uint64_t
     if ((r = modeq_work_ok(a, work, work_bytes)) != FLB_OK) return r;
     const hipStream_t st = (hipStream_t)stream;
     const size_t V = (size_t)a.nx * a.ny;
+    const size_t rsize = a.prec == 0 ? sizeof(float) : sizeof(double);
     // noise batches of up to MODEQ_MAX_BATCH steps, as many as work holds
-    size_t fit = a.kT > 0.0 ? work_bytes / modeq_work_bytes(a.nx, a.ny) : 1;
+    size_t fit = a.kT > 0.0 ? work_bytes / modeq_work_bytes(a.nx, a.ny, a.prec) : 1;
     const int nb_max = (int)(fit < (size_t)MODEQ_MAX_BATCH ? fit : MODEQ_MAX_BATCH);
     for (int32_t k0 = 0; k0 < nsteps; k0 += nb_max) {
         const int nb = nsteps - k0 < nb_max ? nsteps - k0 : nb_max;
-        double* xi = nullptr;
+        char* xi = nullptr;
         if (a.kT > 0.0) {
-            xi = (double*)((char*)work + (size_t)nb * 2 * V * sizeof(double2));
+            xi = (char*)modeq_fields(a, work, nb);
             HIP_TRY(launch_modeq_noise(a, p->precision, (uint32_t)(step0 + k0), nb, work, xi, st));
         }
         for (int b = 0; b < nb; ++b) {
@@ -1164,7 +1175,7 @@ flb_status flb_modeq_run(const flb_modeq_params* p, void* f, void* tmp, uint64_t
             const void* in = (k % 2 == 0) ? f : tmp;
             void* out = (k % 2 == 0) ? tmp : f;
             HIP_TRY(launch_modeq_step(a, p->precision, in, out, (uint32_t)(step0 + k),
-                                      xi ? xi + (size_t)b * 2 * V : nullptr, st));
+                                      xi ? xi + (size_t)b * 2 * V * rsize : nullptr, st));
         }
     }
     if (nsteps % 2) {

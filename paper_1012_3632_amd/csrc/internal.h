@@ -109,25 +109,28 @@ hipError_t launch_interface_heights(int prec, const void* drho, double rho0, int
 // Linearized modified-equilibrium model (modeq.hip), D2Q9.
 struct ModEqArgs {
     int nx, ny;
+    int prec;            // 0 FP32, 1 FP64: the state, the noise transforms and fields
     double rho0, kT, cs2_0, kappa;
     double rate_bulk, rate_shear, rate_ghost;
     uint32_t k0, k1;     // Philox key
     double amp[4];       // white-noise amplitudes of p_xx, p_xy, q_x, q_y
 };
-// Work per step of a noise batch: the two complex noise spectra (2 V
-// double2) and the filtered noise fields xi_e, xi_eps (2 V double).
+// Work per step of a noise batch, in the state's precision (prec 0 FP32,
+// 1 FP64): the two complex noise spectra (2 V complex values) and the
+// filtered noise fields xi_e, xi_eps (2 V reals): 24 V bytes in FP32, 48 V
+// in FP64.
 constexpr int MODEQ_MAX_BATCH = 16;
-size_t modeq_work_bytes(int nx, int ny);
+size_t modeq_work_bytes(int nx, int ny, int prec);
 // The noise of steps step0 .. step0 + nb - 1: spectra of step b at
-// W + 2 V b (double2), filtered fields at xi + 2 V b.
+// W + 2 V b (complex), filtered fields at xi + 2 V b (reals of prec).
 hipError_t launch_modeq_noise(const ModEqArgs& a, int prec, uint32_t step0, int nb, void* W,
-                              double* xi, hipStream_t st);
+                              void* xi, hipStream_t st);
 // Moment fields of the pulled populations, FP64, m[a * V + site].
 hipError_t launch_modeq_moments(const ModEqArgs& a, int prec, const void* fin, double* m,
                                 hipStream_t st);
 // One step; xi = that step's filtered fields, or null for kT = 0.
 hipError_t launch_modeq_step(const ModEqArgs& a, int prec, const void* fin, void* fout,
-                             uint32_t step, const double* xi, hipStream_t st);
+                             uint32_t step, const void* xi, hipStream_t st);
 
 // Adjoint launchers (adjoint.hip).
 hipError_t launch_adjoint_seed(const StepSpec& s, const void* rhobar, void* abar, hipStream_t st);

@@ -39,7 +39,9 @@
 // input for the rows, and for the columns decimation in frequency forward
 // (bit-reversed output), the mix in that order, then decimation in time back.
 // Other extents (at most 1024) use direct sums.  Then k_meq_step applies the
-// step.
+// step.  The transforms and the filtered fields are in the state's precision
+// (R = float or double; twiddles and Cholesky factors formed in FP64 and
+// rounded once).
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -54,30 +56,45 @@ constexpr int MQ_THREADS = 256;
 constexpr int MQ_MAXK = SPECTRUM_MAX_N / MQ_THREADS;   // outputs per thread and line
 constexpr int MQ_TX = 64, MQ_TY = 4;
 
+// Complex values of precision R in LDS and in the work buffer.
+template <typename R> struct Cx;
+template <> struct Cx<double> {
+    using T = double2;
+    static __device__ __forceinline__ T make(double re, double im) { return make_double2(re, im); }
+};
+template <> struct Cx<float> {
+    using T = float2;
+    static __device__ __forceinline__ T make(float re, float im) { return make_float2(re, im); }
+};
+template <typename R> using cx_t = typename Cx<R>::T;
+
 // X(k) = sum_j x(j) exp(-+ 2 pi i j k / n) (sign - forward, + inverse), from a
 // line in LDS and the forward twiddles tw[j] = exp(-2 pi i j / n).
-__device__ __forceinline__ double2 dft_at(const double2* __restrict__ buf,
-                                          const double2* __restrict__ tw, int n, int k,
+template <typename R>
+__device__ __forceinline__ cx_t<R> dft_at(const cx_t<R>* __restrict__ buf,
+                                          const cx_t<R>* __restrict__ tw, int n, int k,
                                           bool inverse) {
-    double re = 0.0, im = 0.0;
+    R re = R(0), im = R(0);
     int idx = 0;   // j k mod n
     for (int j = 0; j < n; ++j) {
-        const double2 x = buf[j];
-        const double2 w = tw[idx];
-        const double wi = inverse ? -w.y : w.y;
+        const cx_t<R> x = buf[j];
+        const cx_t<R> w = tw[idx];
+        const R wi = inverse ? -w.y : w.y;
         re = fma(x.x, w.x, fma(-x.y, wi, re));
         im = fma(x.x, wi, fma(x.y, w.x, im));
         idx += k;
         if (idx >= n) idx -= n;
     }
-    return make_double2(re, im);
+    return Cx<R>::make(re, im);
 }
 
-__device__ __forceinline__ void twiddles(double2* tw, int n) {
+// tw[j] = exp(-2 pi i j / n), evaluated in FP64 and rounded to R.
+template <typename R>
+__device__ __forceinline__ void twiddles(cx_t<R>* tw, int n) {
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         double s, c;
         sincospi(2.0 * (double)j / (double)n, &s, &c);
-        tw[j] = make_double2(c, -s);
+        tw[j] = Cx<R>::make((R)c, (R)-s);
     }
 }
 
@@ -92,11 +109,12 @@ __device__ __forceinline__ int brev(int j, int logn) {
 
 // a + w x, a - w x for complex values, w's imaginary part negated for an
 // inverse transform
-__device__ __forceinline__ void bfly(double2& a, double2& x, double2 w, bool inverse) {
-    const double wi = inverse ? -w.y : w.y;
-    const double vr = x.x * w.x - x.y * wi, vi = x.x * wi + x.y * w.x;
-    x = make_double2(a.x - vr, a.y - vi);
-    a = make_double2(a.x + vr, a.y + vi);
+template <typename R>
+__device__ __forceinline__ void bfly(cx_t<R>& a, cx_t<R>& x, cx_t<R> w, bool inverse) {
+    const R wi = inverse ? -w.y : w.y;
+    const R vr = x.x * w.x - x.y * wi, vi = x.x * wi + x.y * w.x;
+    x = Cx<R>::make(a.x - vr, a.y - vi);
+    a = Cx<R>::make(a.x + vr, a.y + vi);
 }
 
 // In place, the NL lines b[L n .. (L + 1) n) (n = 2^logn), each loaded in
@@ -107,7 +125,8 @@ __device__ __forceinline__ void bfly(double2& a, double2& x, double2 w, bool inv
 // so a thread loads them once, applies both stages in registers and stores
 // them; the quads of a pass are disjoint.  An odd last stage is a plain
 // radix-2 pass.  Ends with a barrier.
-__device__ __forceinline__ void fft_lines_dit(double2* b, const double2* __restrict__ tw, int NL,
+template <typename R>
+__device__ __forceinline__ void fft_lines_dit(cx_t<R>* b, const cx_t<R>* __restrict__ tw, int NL,
                                               int n, int logn, bool inverse) {
     int s = 1;
     for (; s + 1 <= logn; s += 2) {
@@ -119,12 +138,12 @@ __device__ __forceinline__ void fft_lines_dit(double2* b, const double2* __restr
             const int q = t - L * nq;
             const int pos = q & (h - 1);
             const int a = L * n + ((q >> (s - 1)) << (s + 1)) + pos;
-            double2 x0 = b[a], x1 = b[a + h], x2 = b[a + 2 * h], x3 = b[a + 3 * h];
-            const double2 w1 = tw[pos * st1];
-            bfly(x0, x1, w1, inverse);   // stage s
-            bfly(x2, x3, w1, inverse);
-            bfly(x0, x2, tw[pos * st2], inverse);         // stage s + 1
-            bfly(x1, x3, tw[(pos + h) * st2], inverse);
+            cx_t<R> x0 = b[a], x1 = b[a + h], x2 = b[a + 2 * h], x3 = b[a + 3 * h];
+            const cx_t<R> w1 = tw[pos * st1];
+            bfly<R>(x0, x1, w1, inverse);   // stage s
+            bfly<R>(x2, x3, w1, inverse);
+            bfly<R>(x0, x2, tw[pos * st2], inverse);         // stage s + 1
+            bfly<R>(x1, x3, tw[(pos + h) * st2], inverse);
             b[a] = x0;
             b[a + h] = x1;
             b[a + 2 * h] = x2;
@@ -141,8 +160,8 @@ __device__ __forceinline__ void fft_lines_dit(double2* b, const double2* __restr
             const int bt = t - L * nh;
             const int pos = bt & (h - 1);
             const int i0 = L * n + ((bt >> (s - 1)) << s) + pos;
-            double2 u = b[i0], x = b[i0 + h];
-            bfly(u, x, tw[pos * st1], inverse);
+            cx_t<R> u = b[i0], x = b[i0 + h];
+            bfly<R>(u, x, tw[pos * st1], inverse);
             b[i0] = u;
             b[i0 + h] = x;
         }
@@ -150,16 +169,18 @@ __device__ __forceinline__ void fft_lines_dit(double2* b, const double2* __restr
     }
 }
 
-__device__ __forceinline__ void fft2_lines(double2* b, const double2* __restrict__ tw, int n,
+template <typename R>
+__device__ __forceinline__ void fft2_lines(cx_t<R>* b, const cx_t<R>* __restrict__ tw, int n,
                                            int logn, bool inverse) {
-    fft_lines_dit(b, tw, 2, n, logn, inverse);
+    fft_lines_dit<R>(b, tw, 2, n, logn, inverse);
 }
 
 // (u, v) -> (u + v, (u - v) w): the decimation-in-frequency butterfly
-__device__ __forceinline__ void bfly_dif(double2& u, double2& v, double2 w) {
-    const double dr = u.x - v.x, di = u.y - v.y;
-    u = make_double2(u.x + v.x, u.y + v.y);
-    v = make_double2(dr * w.x - di * w.y, dr * w.y + di * w.x);
+template <typename R>
+__device__ __forceinline__ void bfly_dif(cx_t<R>& u, cx_t<R>& v, cx_t<R> w) {
+    const R dr = u.x - v.x, di = u.y - v.y;
+    u = Cx<R>::make(u.x + v.x, u.y + v.y);
+    v = Cx<R>::make(dr * w.x - di * w.y, dr * w.y + di * w.x);
 }
 
 // In place, the NL lines of b (natural order) become their forward
@@ -167,7 +188,8 @@ __device__ __forceinline__ void bfly_dif(double2& u, double2& v, double2 w) {
 // half n/2 down to 1, two per pass (halves 2 q and q combine the elements a,
 // a + q, a + 2q, a + 3q of a group of 4q); an odd last stage (half 1) alone.
 // Ends with a barrier.
-__device__ __forceinline__ void fft_lines_dif(double2* b, const double2* __restrict__ tw, int NL,
+template <typename R>
+__device__ __forceinline__ void fft_lines_dif(cx_t<R>* b, const cx_t<R>* __restrict__ tw, int NL,
                                               int n, int logn) {
     int s = logn;
     for (; s >= 2; s -= 2) {
@@ -179,12 +201,12 @@ __device__ __forceinline__ void fft_lines_dif(double2* b, const double2* __restr
             const int qq = t - L * nq;
             const int pos = qq & (q4 - 1);
             const int a = L * n + ((qq >> (s - 2)) << s) + pos;
-            double2 x0 = b[a], x1 = b[a + q4], x2 = b[a + 2 * q4], x3 = b[a + 3 * q4];
-            bfly_dif(x0, x2, tw[pos * stA]);          // half 2 q4
-            bfly_dif(x1, x3, tw[(pos + q4) * stA]);
-            const double2 wC = tw[pos * stC];         // half q4
-            bfly_dif(x0, x1, wC);
-            bfly_dif(x2, x3, wC);
+            cx_t<R> x0 = b[a], x1 = b[a + q4], x2 = b[a + 2 * q4], x3 = b[a + 3 * q4];
+            bfly_dif<R>(x0, x2, tw[pos * stA]);          // half 2 q4
+            bfly_dif<R>(x1, x3, tw[(pos + q4) * stA]);
+            const cx_t<R> wC = tw[pos * stC];         // half q4
+            bfly_dif<R>(x0, x1, wC);
+            bfly_dif<R>(x2, x3, wC);
             b[a] = x0;
             b[a + q4] = x1;
             b[a + 2 * q4] = x2;
@@ -197,8 +219,8 @@ __device__ __forceinline__ void fft_lines_dif(double2* b, const double2* __restr
         for (int t = threadIdx.x; t < NL * nh; t += blockDim.x) {
             const int L = t >> (logn - 1);
             const int i0 = L * n + 2 * (t - L * nh);
-            double2 u = b[i0], v = b[i0 + 1];
-            bfly_dif(u, v, make_double2(1.0, 0.0));
+            cx_t<R> u = b[i0], v = b[i0 + 1];
+            bfly_dif<R>(u, v, Cx<R>::make(R(1), R(0)));
             b[i0] = u;
             b[i0 + 1] = v;
         }
@@ -206,30 +228,49 @@ __device__ __forceinline__ void fft_lines_dif(double2* b, const double2* __restr
     }
 }
 
+// Lower Cholesky factor of the (e, eps) noise block at wavenumber (kx, ky),
+// given cos kx and cos ky, in FP64.
+__device__ __forceinline__ void meq_chol(const ModEqArgs& a, double cx, double cy, double& l11,
+                                         double& l21, double& l22) {
+    const double pre = 12.0 * a.rho0 * a.kT;
+    const double le = a.rate_bulk, lg = a.rate_ghost;
+    const double lap = (4.0 / 3.0) * (2.0 - cx - cy) + (2.0 / 3.0) * (1.0 - cx * cy);
+    const double c2 = a.cs2_0 + a.kappa * a.rho0 * lap;
+    const double see = pre * le * (2.0 - le) * (2.0 - 3.0 * c2);
+    const double sep = pre * (3.0 * c2 - 1.0) * (le + lg - le * lg);
+    const double spp = pre * lg * (2.0 - lg) * (5.0 - 3.0 * c2);
+    l11 = sqrt(fmax(see, 0.0));
+    l21 = l11 > 0.0 ? sep / l11 : 0.0;
+    l22 = sqrt(fmax(spp - l21 * l21, 0.0));
+}
+
+// Dynamic LDS of the noise kernels (lines and twiddles of either precision).
+extern __shared__ __align__(16) unsigned char lds_mq[];
+
 template <typename Real>
 __global__ __launch_bounds__(MQ_THREADS) void k_meq_noise_x(ModEqArgs a, uint32_t step0,
-                                                            double2* __restrict__ W) {
-    extern __shared__ double2 lds_mq[];
+                                                            cx_t<Real>* __restrict__ W) {
+    using C = cx_t<Real>;
     const int n = a.nx, y = blockIdx.x;
     const size_t V = (size_t)a.nx * a.ny;
     const uint32_t step = step0 + blockIdx.y;
     W += (size_t)blockIdx.y * 2 * V;
-    double2* tw = lds_mq;
-    double2* be = lds_mq + n;
-    double2* bp = lds_mq + 2 * n;
+    C* tw = (C*)lds_mq;
+    C* be = tw + n;
+    C* bp = tw + 2 * n;
     const bool fft = pow2(n);
     const int logn = log2i(n);
-    twiddles(tw, n);
+    twiddles<Real>(tw, n);
     for (int x = threadIdx.x; x < n; x += blockDim.x) {
         Real z[6];
         site_normals<3, Real>((uint32_t)(x + n * y), step, 0u, 0u, a.k0, a.k1, z);
         const int j = fft ? brev(x, logn) : x;
-        be[j] = make_double2((double)z[0], 0.0);
-        bp[j] = make_double2((double)z[5], 0.0);
+        be[j] = Cx<Real>::make(z[0], Real(0));
+        bp[j] = Cx<Real>::make(z[5], Real(0));
     }
     __syncthreads();
     if (fft) {
-        fft2_lines(be, tw, n, logn, false);
+        fft2_lines<Real>(be, tw, n, logn, false);
         for (int k = threadIdx.x; k < n; k += blockDim.x) {
             W[(size_t)y * n + k] = be[k];
             W[V + (size_t)y * n + k] = bp[k];
@@ -237,52 +278,45 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_noise_x(ModEqArgs a, uint32_
         return;
     }
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        W[(size_t)y * n + k] = dft_at(be, tw, n, k, false);
-        W[V + (size_t)y * n + k] = dft_at(bp, tw, n, k, false);
+        W[(size_t)y * n + k] = dft_at<Real>(be, tw, n, k, false);
+        W[V + (size_t)y * n + k] = dft_at<Real>(bp, tw, n, k, false);
     }
 }
 
+template <typename Real>
 __global__ __launch_bounds__(MQ_THREADS) void k_meq_filter_y(ModEqArgs a,
-                                                             double2* __restrict__ W) {
-    extern __shared__ double2 lds_mq[];
+                                                             cx_t<Real>* __restrict__ W) {
+    using C = cx_t<Real>;
     const int n = a.ny, nx = a.nx, kx = blockIdx.x;
     const size_t V = (size_t)a.nx * a.ny;
     W += (size_t)blockIdx.y * 2 * V;
-    double2* tw = lds_mq;
-    double2* be = lds_mq + n;
-    double2* bp = lds_mq + 2 * n;
+    C* tw = (C*)lds_mq;
+    C* be = tw + n;
+    C* bp = tw + 2 * n;
     const bool fft = pow2(n);
     const int logn = log2i(n);
-    twiddles(tw, n);
+    twiddles<Real>(tw, n);
     for (int y = threadIdx.x; y < n; y += blockDim.x) {
         const int j = fft ? brev(y, logn) : y;
         be[j] = W[(size_t)y * nx + kx];
         bp[j] = W[V + (size_t)y * nx + kx];
     }
     __syncthreads();
-    if (fft) fft2_lines(be, tw, n, logn, false);
+    if (fft) fft2_lines<Real>(be, tw, n, logn, false);
     double sx, cx;
     sincospi(2.0 * (double)kx / (double)nx, &sx, &cx);
-    const double pre = 12.0 * a.rho0 * a.kT;
-    const double le = a.rate_bulk, lg = a.rate_ghost;
-    double2 oe[MQ_MAXK], op[MQ_MAXK];
+    C oe[MQ_MAXK], op[MQ_MAXK];
 #pragma unroll
     for (int r = 0; r < MQ_MAXK; ++r) {
         const int ky = threadIdx.x + r * MQ_THREADS;
         if (ky < n) {
-            const double2 ze = fft ? be[ky] : dft_at(be, tw, n, ky, false);
-            const double2 zp = fft ? bp[ky] : dft_at(bp, tw, n, ky, false);
-            const double cy = tw[ky].x;
-            const double lap = (4.0 / 3.0) * (2.0 - cx - cy) + (2.0 / 3.0) * (1.0 - cx * cy);
-            const double c2 = a.cs2_0 + a.kappa * a.rho0 * lap;
-            const double see = pre * le * (2.0 - le) * (2.0 - 3.0 * c2);
-            const double sep = pre * (3.0 * c2 - 1.0) * (le + lg - le * lg);
-            const double spp = pre * lg * (2.0 - lg) * (5.0 - 3.0 * c2);
-            const double l11 = sqrt(fmax(see, 0.0));
-            const double l21 = l11 > 0.0 ? sep / l11 : 0.0;
-            const double l22 = sqrt(fmax(spp - l21 * l21, 0.0));
-            oe[r] = make_double2(l11 * ze.x, l11 * ze.y);
-            op[r] = make_double2(l21 * ze.x + l22 * zp.x, l21 * ze.y + l22 * zp.y);
+            const C ze = fft ? be[ky] : dft_at<Real>(be, tw, n, ky, false);
+            const C zp = fft ? bp[ky] : dft_at<Real>(bp, tw, n, ky, false);
+            double d11, d21, d22;
+            meq_chol(a, cx, (double)tw[ky].x, d11, d21, d22);
+            const Real l11 = (Real)d11, l21 = (Real)d21, l22 = (Real)d22;
+            oe[r] = Cx<Real>::make(l11 * ze.x, l11 * ze.y);
+            op[r] = Cx<Real>::make(l21 * ze.x + l22 * zp.x, l21 * ze.y + l22 * zp.y);
         }
     }
     __syncthreads();   // every forward value has been read from be, bp
@@ -297,7 +331,7 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_filter_y(ModEqArgs a,
     }
     __syncthreads();
     if (fft) {
-        fft2_lines(be, tw, n, logn, true);
+        fft2_lines<Real>(be, tw, n, logn, true);
         for (int y = threadIdx.x; y < n; y += blockDim.x) {
             W[(size_t)y * nx + kx] = be[y];
             W[V + (size_t)y * nx + kx] = bp[y];
@@ -305,8 +339,8 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_filter_y(ModEqArgs a,
         return;
     }
     for (int y = threadIdx.x; y < n; y += blockDim.x) {
-        W[(size_t)y * nx + kx] = dft_at(be, tw, n, y, true);
-        W[V + (size_t)y * nx + kx] = dft_at(bp, tw, n, y, true);
+        W[(size_t)y * nx + kx] = dft_at<Real>(be, tw, n, y, true);
+        W[V + (size_t)y * nx + kx] = dft_at<Real>(bp, tw, n, y, true);
     }
 }
 
@@ -317,50 +351,41 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_filter_y(ModEqArgs a,
 // transforms take that order back to natural order (decimation in time), so
 // no permutation step is needed.  Lines in LDS: e of columns 0 .. CB-1, then
 // eps.  nx must be a multiple of CB.
-template <int CB>
+template <typename Real, int CB>
 __global__ __launch_bounds__(MQ_THREADS) void k_meq_filter_cols(ModEqArgs a,
-                                                                double2* __restrict__ W) {
-    extern __shared__ double2 lds_mq[];
+                                                                cx_t<Real>* __restrict__ W) {
+    using C = cx_t<Real>;
     const int n = a.ny, nx = a.nx, kx0 = blockIdx.x * CB;
     const int logn = log2i(n);
     const size_t V = (size_t)a.nx * a.ny;
     W += (size_t)blockIdx.y * 2 * V;
-    double2* tw = lds_mq;
-    double2* b = lds_mq + n;
-    twiddles(tw, n);
+    C* tw = (C*)lds_mq;
+    C* b = tw + n;
+    twiddles<Real>(tw, n);
     for (int idx = threadIdx.x; idx < CB * n; idx += blockDim.x) {
         const int y = idx / CB, c = idx - y * CB;
         b[c * n + y] = W[(size_t)y * nx + kx0 + c];
         b[(CB + c) * n + y] = W[V + (size_t)y * nx + kx0 + c];
     }
     __syncthreads();
-    fft_lines_dif(b, tw, 2 * CB, n, logn);
+    fft_lines_dif<Real>(b, tw, 2 * CB, n, logn);
     double cxs[CB];
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
         double sx;
         sincospi(2.0 * (double)(kx0 + c) / (double)nx, &sx, &cxs[c]);
     }
-    const double pre = 12.0 * a.rho0 * a.kT;
-    const double le = a.rate_bulk, lg = a.rate_ghost;
     for (int idx = threadIdx.x; idx < CB * n; idx += blockDim.x) {
         const int c = idx >> logn, j = idx & (n - 1);
-        const double cx = cxs[c];
-        const double cy = tw[brev(j, logn)].x;
-        const double lap = (4.0 / 3.0) * (2.0 - cx - cy) + (2.0 / 3.0) * (1.0 - cx * cy);
-        const double c2 = a.cs2_0 + a.kappa * a.rho0 * lap;
-        const double see = pre * le * (2.0 - le) * (2.0 - 3.0 * c2);
-        const double sep = pre * (3.0 * c2 - 1.0) * (le + lg - le * lg);
-        const double spp = pre * lg * (2.0 - lg) * (5.0 - 3.0 * c2);
-        const double l11 = sqrt(fmax(see, 0.0));
-        const double l21 = l11 > 0.0 ? sep / l11 : 0.0;
-        const double l22 = sqrt(fmax(spp - l21 * l21, 0.0));
-        const double2 ze = b[c * n + j], zp = b[(CB + c) * n + j];
-        b[c * n + j] = make_double2(l11 * ze.x, l11 * ze.y);
-        b[(CB + c) * n + j] = make_double2(l21 * ze.x + l22 * zp.x, l21 * ze.y + l22 * zp.y);
+        double d11, d21, d22;
+        meq_chol(a, cxs[c], (double)tw[brev(j, logn)].x, d11, d21, d22);
+        const Real l11 = (Real)d11, l21 = (Real)d21, l22 = (Real)d22;
+        const C ze = b[c * n + j], zp = b[(CB + c) * n + j];
+        b[c * n + j] = Cx<Real>::make(l11 * ze.x, l11 * ze.y);
+        b[(CB + c) * n + j] = Cx<Real>::make(l21 * ze.x + l22 * zp.x, l21 * ze.y + l22 * zp.y);
     }
     __syncthreads();
-    fft_lines_dit(b, tw, 2 * CB, n, logn, true);
+    fft_lines_dit<Real>(b, tw, 2 * CB, n, logn, true);
     for (int idx = threadIdx.x; idx < CB * n; idx += blockDim.x) {
         const int y = idx / CB, c = idx - y * CB;
         W[(size_t)y * nx + kx0 + c] = b[c * n + y];
@@ -368,21 +393,22 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_filter_cols(ModEqArgs a,
     }
 }
 
+template <typename Real>
 __global__ __launch_bounds__(MQ_THREADS) void k_meq_noise_ix(ModEqArgs a,
-                                                             const double2* __restrict__ W,
-                                                             double* __restrict__ xi) {
-    extern __shared__ double2 lds_mq[];
+                                                             const cx_t<Real>* __restrict__ W,
+                                                             Real* __restrict__ xi) {
+    using C = cx_t<Real>;
     const int n = a.nx, y = blockIdx.x;
     const size_t V = (size_t)a.nx * a.ny;
-    const double inv_v = 1.0 / (double)V;
+    const Real inv_v = (Real)(1.0 / (double)V);
     W += (size_t)blockIdx.y * 2 * V;
     xi += (size_t)blockIdx.y * 2 * V;
-    double2* tw = lds_mq;
-    double2* be = lds_mq + n;
-    double2* bp = lds_mq + 2 * n;
+    C* tw = (C*)lds_mq;
+    C* be = tw + n;
+    C* bp = tw + 2 * n;
     const bool fft = pow2(n);
     const int logn = log2i(n);
-    twiddles(tw, n);
+    twiddles<Real>(tw, n);
     for (int x = threadIdx.x; x < n; x += blockDim.x) {
         const int j = fft ? brev(x, logn) : x;
         be[j] = W[(size_t)y * n + x];
@@ -390,7 +416,7 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_noise_ix(ModEqArgs a,
     }
     __syncthreads();
     if (fft) {
-        fft2_lines(be, tw, n, logn, true);
+        fft2_lines<Real>(be, tw, n, logn, true);
         for (int x = threadIdx.x; x < n; x += blockDim.x) {
             xi[(size_t)y * n + x] = be[x].x * inv_v;
             xi[V + (size_t)y * n + x] = bp[x].x * inv_v;
@@ -398,8 +424,8 @@ __global__ __launch_bounds__(MQ_THREADS) void k_meq_noise_ix(ModEqArgs a,
         return;
     }
     for (int x = threadIdx.x; x < n; x += blockDim.x) {
-        xi[(size_t)y * n + x] = dft_at(be, tw, n, x, true).x * inv_v;
-        xi[V + (size_t)y * n + x] = dft_at(bp, tw, n, x, true).x * inv_v;
+        xi[(size_t)y * n + x] = dft_at<Real>(be, tw, n, x, true).x * inv_v;
+        xi[V + (size_t)y * n + x] = dft_at<Real>(bp, tw, n, x, true).x * inv_v;
     }
 }
 
@@ -413,7 +439,7 @@ __global__ __launch_bounds__(MQ_TX * MQ_TY) void k_meq_step(ModEqArgs a, Geom g,
                                                             const Real* __restrict__ fin,
                                                             Real* __restrict__ fout,
                                                             uint32_t step,
-                                                            const double* __restrict__ xi) {
+                                                            const Real* __restrict__ xi) {
     using L = Lattice<0>;
     constexpr int SX = MQ_TX + 2, NS = SX * (MQ_TY + 2);
     constexpr int NRING = NS - MQ_TX * MQ_TY;   // halo sites: two rows of SX, two columns of TY
@@ -482,12 +508,12 @@ __global__ __launch_bounds__(MQ_TX * MQ_TY) void k_meq_step(ModEqArgs a, Geom g,
     if (xi) {
         Real z[6];
         site_normals<3, Real>(site, step, 0u, 0u, a.k0, a.k1, z);
-        m[3] += Real(xi[site]);
+        m[3] += xi[site];
         m[4] += Real(a.amp[0]) * z[1];
         m[5] += Real(a.amp[1]) * z[2];
         m[6] += Real(a.amp[2]) * z[3];
         m[7] += Real(a.amp[3]) * z[4];
-        m[8] += Real(xi[g.V + site]);
+        m[8] += xi[g.V + site];
     }
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
@@ -537,63 +563,70 @@ hipError_t launch_modeq_moments(const ModEqArgs& a, int prec, const void* fin, d
     return hipGetLastError();
 }
 
-size_t modeq_work_bytes(int nx, int ny) {
+size_t modeq_work_bytes(int nx, int ny, int prec) {
     const size_t V = (size_t)nx * ny;
-    return 2 * V * sizeof(double2) + 2 * V * sizeof(double);
+    const size_t r = prec == 0 ? sizeof(float) : sizeof(double);
+    return 2 * V * (2 * r) + 2 * V * r;
 }
 
-hipError_t launch_modeq_noise(const ModEqArgs& a, int prec, uint32_t step0, int nb, void* W,
-                              double* xi, hipStream_t st) {
-    double2* Wc = (double2*)W;
-    const size_t lx = 3 * (size_t)a.nx * sizeof(double2), ly = 3 * (size_t)a.ny * sizeof(double2);
+namespace {
+
+// Choice of CB for k_meq_filter_cols: the widest of 4, 2 that divides nx and
+// whose lines fit the block's LDS, else 1.
+int filter_cols_cb(const ModEqArgs& a, size_t csize) {
+    int dev = 0, lmax = 65536;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    const size_t per = (size_t)a.ny * csize;
+    for (int c : {4, 2})
+        if (a.nx % c == 0 && (1 + 2 * (size_t)c) * per <= (size_t)lmax) return c;
+    return 1;
+}
+
+template <typename Real, int CB>
+hipError_t launch_filter_cols(const ModEqArgs& a, int nb, cx_t<Real>* W, hipStream_t st) {
+    const size_t lc = (1 + 2 * (size_t)CB) * (size_t)a.ny * sizeof(cx_t<Real>);
+    hipError_t e = hipFuncSetAttribute((const void*)k_meq_filter_cols<Real, CB>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc);
+    if (e != hipSuccess) return e;
+    const dim3 gc((unsigned)(a.nx / CB), (unsigned)nb);
+    hipLaunchKernelGGL((k_meq_filter_cols<Real, CB>), gc, dim3(MQ_THREADS), lc, st, a, W);
+    return hipSuccess;
+}
+
+template <typename Real>
+hipError_t launch_noise_t(const ModEqArgs& a, uint32_t step0, int nb, void* Wv, Real* xi,
+                          hipStream_t st) {
+    using C = cx_t<Real>;
+    C* W = (C*)Wv;
+    const size_t lx = 3 * (size_t)a.nx * sizeof(C), ly = 3 * (size_t)a.ny * sizeof(C);
     const dim3 gx((unsigned)a.ny, (unsigned)nb), gy((unsigned)a.nx, (unsigned)nb);
-    if (prec == 0)
-        hipLaunchKernelGGL(k_meq_noise_x<float>, gx, dim3(MQ_THREADS), lx, st, a, step0, Wc);
-    else
-        hipLaunchKernelGGL(k_meq_noise_x<double>, gx, dim3(MQ_THREADS), lx, st, a, step0, Wc);
-    const bool p2 = (a.ny & (a.ny - 1)) == 0;
-    int cb = 1;
-    if (p2) {
-        int dev = 0, lmax = 65536;
-        if (hipGetDevice(&dev) == hipSuccess)
-            (void)hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        const size_t per = (size_t)a.ny * sizeof(double2);
-        for (int c : {4, 2}) {
-            if (a.nx % c == 0 && (1 + 2 * (size_t)c) * per <= (size_t)lmax) {
-                cb = c;
-                break;
-            }
-        }
-        const size_t lc = (1 + 2 * (size_t)cb) * per;
-        const dim3 gc((unsigned)(a.nx / cb), (unsigned)nb);
+    hipLaunchKernelGGL(k_meq_noise_x<Real>, gx, dim3(MQ_THREADS), lx, st, a, step0, W);
+    if ((a.ny & (a.ny - 1)) == 0) {
         hipError_t e = hipSuccess;
-        switch (cb) {
-            case 4:
-                e = hipFuncSetAttribute((const void*)k_meq_filter_cols<4>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc);
-                if (e == hipSuccess)
-                    hipLaunchKernelGGL(k_meq_filter_cols<4>, gc, dim3(MQ_THREADS), lc, st, a, Wc);
-                break;
-            case 2:
-                e = hipFuncSetAttribute((const void*)k_meq_filter_cols<2>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc);
-                if (e == hipSuccess)
-                    hipLaunchKernelGGL(k_meq_filter_cols<2>, gc, dim3(MQ_THREADS), lc, st, a, Wc);
-                break;
-            default:
-                hipLaunchKernelGGL(k_meq_filter_cols<1>, gc, dim3(MQ_THREADS), lc, st, a, Wc);
-                break;
+        switch (filter_cols_cb(a, sizeof(C))) {
+            case 4: e = launch_filter_cols<Real, 4>(a, nb, W, st); break;
+            case 2: e = launch_filter_cols<Real, 2>(a, nb, W, st); break;
+            default: e = launch_filter_cols<Real, 1>(a, nb, W, st); break;
         }
         if (e != hipSuccess) return e;
     } else {
-        hipLaunchKernelGGL(k_meq_filter_y, gy, dim3(MQ_THREADS), ly, st, a, Wc);
+        hipLaunchKernelGGL(k_meq_filter_y<Real>, gy, dim3(MQ_THREADS), ly, st, a, W);
     }
-    hipLaunchKernelGGL(k_meq_noise_ix, gx, dim3(MQ_THREADS), lx, st, a, (const double2*)Wc, xi);
+    hipLaunchKernelGGL(k_meq_noise_ix<Real>, gx, dim3(MQ_THREADS), lx, st, a, (const C*)W, xi);
     return hipGetLastError();
 }
 
+}  // namespace
+
+hipError_t launch_modeq_noise(const ModEqArgs& a, int prec, uint32_t step0, int nb, void* W,
+                              void* xi, hipStream_t st) {
+    if (prec == 0) return launch_noise_t<float>(a, step0, nb, W, (float*)xi, st);
+    return launch_noise_t<double>(a, step0, nb, W, (double*)xi, st);
+}
+
 hipError_t launch_modeq_step(const ModEqArgs& a, int prec, const void* fin, void* fout,
-                             uint32_t step, const double* xi, hipStream_t st) {
+                             uint32_t step, const void* xi, hipStream_t st) {
     const size_t V = (size_t)a.nx * a.ny;
     Geom g{};
     g.nx = a.nx;
@@ -608,10 +641,10 @@ hipError_t launch_modeq_step(const ModEqArgs& a, int prec, const void* fin, void
     const dim3 grid((unsigned)g.nbx, (unsigned)g.nby);
     if (prec == 0)
         hipLaunchKernelGGL(k_meq_step<float>, grid, dim3(MQ_TX * MQ_TY), 0, st, a, g,
-                           (const float*)fin, (float*)fout, step, xi);
+                           (const float*)fin, (float*)fout, step, (const float*)xi);
     else
         hipLaunchKernelGGL(k_meq_step<double>, grid, dim3(MQ_TX * MQ_TY), 0, st, a, g,
-                           (const double*)fin, (double*)fout, step, xi);
+                           (const double*)fin, (double*)fout, step, (const double*)xi);
     return hipGetLastError();
 }
 

@@ -95,7 +95,8 @@ class ModEq:
 
     def step_into_noalloc(self, fin, fout, n, stream=None):
         """The step of ``step_into`` with the library's fixed device work
-        array (no work buffer; lattices of at most 349525 sites)."""
+        array (no work buffer; lattices of at most 699050 sites in FP32,
+        349525 in FP64)."""
         call("flb_modeq_step_noalloc", C.byref(self.c), _ptr(fin), _ptr(fout), int(n),
              _stream(stream))
 
@@ -107,8 +108,9 @@ class ModEq:
         return out
 
     def noise(self, n, stream=None):
-        """The filtered (e, eps) noise of step n: (2, ny, nx) float64."""
-        out = torch.empty((2, self.p.ny, self.p.nx), dtype=torch.float64, device=self.f.device)
+        """The filtered (e, eps) noise of step n: (2, ny, nx) in the state's
+        precision."""
+        out = torch.empty((2, self.p.ny, self.p.nx), dtype=self.p.dtype, device=self.f.device)
         call("flb_modeq_noise", C.byref(self.c), int(n), _ptr(out), _ptr(self.work),
              int(self.nbytes), _stream(stream))
         return out

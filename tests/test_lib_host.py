@@ -115,15 +115,16 @@ def test_capillary_theory_equals_oracle():
 
 
 def test_modeq_validation_and_sizes():
-    """flb_modeq_work_bytes: 48 V bytes; invalid extents, rates, kT, c_s^2(k)
+    """flb_modeq_work_bytes: 24 V bytes in FP32, 48 V in FP64; invalid extents, rates, kT, c_s^2(k)
     above 0.6 and rates that leave the (e, eps) covariance indefinite are
     rejected on the host."""
     from paper_1012_3632_amd._lib import FLBError
     from paper_1012_3632_amd.modeq import ModEqParams, paper_params, work_bytes
     ok = ModEqParams(nx=8, ny=8, kT=1e-5, cs2_0=0.07, kappa=0.08, rate_bulk=1.2, rate_shear=1.6,
                      rate_ghost=0.9)
-    assert work_bytes(ok) == 48 * 64
-    assert work_bytes(paper_params()) == 48 * 128 * 128
+    assert work_bytes(ok) == 24 * 64
+    assert work_bytes(ok.with_(precision="fp64")) == 48 * 64
+    assert work_bytes(paper_params()) == 24 * 128 * 128
     bad = [ok.with_(nx=1025), ok.with_(ny=0), ok.with_(rate_shear=2.0), ok.with_(kT=-1.0),
            ok.with_(cs2_0=0.0), ok.with_(kappa=0.2),
            ok.with_(cs2_0=0.55, kappa=0.0, rate_bulk=1.0, rate_ghost=1.9)]
@@ -140,10 +141,10 @@ def test_modeq_entry_points_reject_bad_pointers():
 
     from paper_1012_3632_amd._lib import FLBError, call
     from paper_1012_3632_amd.modeq import ModEqParams
-    p = ModEqParams(nx=8, ny=8, kT=1e-5, cs2_0=0.07, kappa=0.08).to_c()
+    p = ModEqParams(nx=8, ny=8, kT=1e-5, cs2_0=0.07, kappa=0.08, precision="fp32").to_c()
     A, B, Wk = C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20)
     odd = C.c_void_p((1 << 20) + 8)
-    need = 48 * 64
+    need = 24 * 64   # FP32 work bytes of 8 x 8 sites
     bad_calls = [
         ("flb_modeq_step", C.byref(p), None, B, 0, Wk, need, None),
         ("flb_modeq_step", C.byref(p), A, A, 0, Wk, need, None),
@@ -175,11 +176,12 @@ def test_modeq_noalloc_step_rejects_on_the_host():
     assert nbytes.value == 16 << 20
     ok = ModEqParams(nx=8, ny=8, kT=1e-5, cs2_0=0.07, kappa=0.08)
     A, B, odd = C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p((1 << 20) + 8)
-    big = ok.with_(nx=1024, ny=342)            # 48 V = 16.03 MiB
-    assert 48 * 1024 * 342 > nbytes.value
+    big64 = ok.with_(nx=1024, ny=342, precision="fp64")   # 48 V = 16.03 MiB
+    big32 = ok.with_(nx=1024, ny=683, precision="fp32")   # 24 V = 16.01 MiB
+    assert 48 * 1024 * 342 > nbytes.value and 24 * 1024 * 683 > nbytes.value
     bad_calls = [
         (ok.to_c(), None, B), (ok.to_c(), A, A), (ok.to_c(), odd, B),
-        (ok.with_(rate_bulk=2.5).to_c(), A, B), (big.to_c(), A, B),
+        (ok.with_(rate_bulk=2.5).to_c(), A, B), (big64.to_c(), A, B), (big32.to_c(), A, B),
     ]
     for p, fin, fout in bad_calls:
         with pytest.raises(FLBError) as e:

@@ -50,14 +50,18 @@ def test_noalloc_step_equals_the_work_buffer_step(precision):
 
 
 def test_noalloc_rejects_lattices_beyond_the_array():
+    """The fixed array holds 16 MiB: 1024 x 512 in FP64 (48 V bytes) and
+    1024 x 1024 in FP32 (24 V bytes) are rejected before anything is queued."""
     from paper_1012_3632_amd._lib import FLBError, call
     from paper_1012_3632_amd.modeq import ModEqParams
     nbytes = C.c_size_t()
     call("flb_modeq_static_work_bytes", C.byref(nbytes))
-    p = ModEqParams(**dict(W.modeq_params_of("d2q9_128_modeq"), nx=1024, ny=512, kT=1e-5))
-    assert 48 * 1024 * 512 > nbytes.value
-    a = torch.zeros((9, 512, 1024), device="cuda")
-    b = torch.zeros_like(a)
-    with pytest.raises(FLBError) as e:
-        call("flb_modeq_step_noalloc", C.byref(p.to_c()), _ptr(a), _ptr(b), 0, None)
-    assert e.value.status == -1
+    for prec, ny, per in (("fp64", 512, 48), ("fp32", 1024, 24)):
+        p = ModEqParams(**dict(W.modeq_params_of("d2q9_128_modeq", precision=prec), nx=1024,
+                               ny=ny, kT=1e-5))
+        assert per * 1024 * ny > nbytes.value
+        a = torch.zeros((9, ny, 1024), dtype=p.dtype, device="cuda")
+        b = torch.zeros_like(a)
+        with pytest.raises(FLBError) as e:
+            call("flb_modeq_step_noalloc", C.byref(p.to_c()), _ptr(a), _ptr(b), 0, None)
+        assert e.value.status == -1
