@@ -185,11 +185,17 @@ def bench_main(args):
     # FP64 step beside it
     p64 = p.with_(precision="fp64")
     s64 = Simulation(p64)
-    s64.autotune(repeats=3)
+    (_, cfg64, _, ip64), _ = s64.autotune(repeats=3)
     s64.step(args.warmup, stats_stride=1)
     ms64 = time_steps(s64, max(args.steps // 2, 10), 1, stream)
     out["fp64"] = {"ms_per_step": round(ms64, 5), "MLUPS": round(V / (ms64 * 1e-3) / 1e6, 1),
-                   "hbm_frac": round(2 * 19 * 8 * V / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                   "hbm_frac": round(2 * 19 * 8 * V / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "frac_of_measured_copy": round(2 * 19 * 8 * V / (ms64 * 1e-3) / 1e9 / copy_gbs, 4),
+                   # the 318 MB state exceeds the last-level cache: the autotuner
+                   # may prefer two buffers to the in-place pairs
+                   "launch_config": ip64 if ip64 >= 0 else cfg64,
+                   "launch_shape": list(s64.launch_shape(ip64 if ip64 >= 0 else cfg64)),
+                   "in_place_pairs": ip64 >= 0}
     s64.close()
     del s64
     torch.cuda.empty_cache()
