@@ -96,11 +96,13 @@ __device__ __forceinline__ Nbr<Real>::Nbr(uint32_t s, int x, int y, int z, const
 // offsets are formed next to their accesses instead of being hoisted out of
 // the tile loop and held.  Word 3 of the resource is the CDNA raw-buffer
 // format (32-bit data format, no swizzle, no stride).
+// The record count and the scalar offsets are unsigned 32-bit fields of the
+// hardware (V < 2^24 sites, so Q V sizeof(Real) < 2^32); the builtins take
+// them as int, so values above 2^31 pass through the cast bit for bit.
 template <int LAT, typename Real>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rep_rsrc(const Real* rep, uint32_t V) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<Real*>(rep), 0,
-                                             (int)((uint32_t)Lattice<LAT>::Q * V * sizeof(Real)),
-                                             0x00020000);
+    const uint32_t bytes = (uint32_t)Lattice<LAT>::Q * V * (uint32_t)sizeof(Real);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<Real*>(rep), 0, (int)bytes, 0x00020000);
 }
 __device__ __forceinline__ uint32_t plane_soff(uint32_t Vr, int i, uint32_t esize) {
     return (uint32_t)i * Vr * esize;
