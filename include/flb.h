@@ -465,7 +465,9 @@ flb_status flb_batch_destroy(flb_batch* b);
  * flb_autotune times every candidate launch shape of the handle's step kernel
  * (block size, sites per thread, store hints, in-place pairs; tile or
  * z-marching shape for the force kernel) the way a run uses it (ordinary
- * steps alternate the two buffers, pairs work in place) and afterwards
+ * steps alternate the two buffers over `repeats` steps; in-place pairs are
+ * timed after about 4 ms of settling steps, round-robin over at least three
+ * rounds of about 2 ms each, best round kept) and afterwards
  * restores the state and the accumulated statistics from a host copy (host
  * memory of one population buffer plus the statistics slots); it writes
  * best[4]: the fastest shape for plain steps, for steps with statistics, the
