@@ -825,6 +825,16 @@ struct SegWork {
 // Recompute S_{k0+1} .. S_{k0+k-1} (and every state's density) with the forward kernels.
 flb_status seg_recompute(const SegWork& sw, uint64_t k0, hipStream_t st) {
     flb_handle* h = sw.h;
+    if (h->spec.force && config_fused(h->spec, h->cfg)) {
+        // the step forms its input's density itself and writes it out, so a
+        // recomputed step is one launch; the last state's density is a pass
+        for (size_t j = 1; j < sw.k; ++j)
+            HIP_TRY(launch_step(h->spec, h->cfg, sw.state(j - 1), (void*)sw.state(j), nullptr,
+                                nullptr, (unsigned long long)(k0 + j - 1), nullptr, st,
+                                (void*)sw.density(j - 1)));
+        HIP_TRY(launch_density(h->spec, sw.state(sw.k - 1), sw.density(sw.k - 1), st));
+        return FLB_OK;
+    }
     if (h->spec.force) HIP_TRY(launch_density(h->spec, sw.state(0), sw.density(0), st));
     for (size_t j = 1; j < sw.k; ++j) {
         HIP_TRY(launch_step(h->spec, h->cfg, sw.state(j - 1), (void*)sw.state(j),

@@ -59,9 +59,12 @@ hipError_t launch_init(const StepSpec& s, void* f, const double* drho, hipStream
 hipError_t launch_density(const StepSpec& s, const void* fin, void* drho_out, hipStream_t st);
 // One step fin -> fout.  drho: density field of fin after streaming (force only).
 // step_dev/step_host: step index (device counter + offset).  partial: stats slots or null.
+// rho_out: for the force shapes that form their own density tile
+// (config_fused), if non-null, receives fin's density field, the bits
+// launch_density would write; ignored otherwise.
 hipError_t launch_step(const StepSpec& s, int cfg, const void* fin, void* fout, const void* drho,
                        const unsigned long long* step_dev, unsigned long long step_host,
-                       double* partial, hipStream_t st);
+                       double* partial, hipStream_t st, void* rho_out = nullptr);
 // In-place shapes: one step of a pair on the single buffer f (phase 0 then 1;
 // see push_rows_opp).  The state is in the ordinary layout after phase 1.
 bool config_in_place(const StepSpec& s, int cfg);

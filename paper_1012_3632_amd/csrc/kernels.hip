@@ -98,7 +98,8 @@ template <int LAT, typename Real, bool FORCE, bool STATS, int TX, int TY, int TZ
           bool NTS, bool FUSED = false>
 __global__ __launch_bounds__(TX* TY* TZ) void k_step(
     const Real* __restrict__ fin, Real* __restrict__ fout, const Real* __restrict__ drho, Geom g,
-    CollideParams<Real> P, ForceParams<Real> fp, StepIndex st, double* __restrict__ partial) {
+    CollideParams<Real> P, ForceParams<Real> fp, StepIndex st, double* __restrict__ partial,
+    Real* __restrict__ rho_out) {
     using L = Lattice<LAT>;
     using M = Moments<LAT, Real>;
     using FT = ForceTile<LAT, Real, TX, TY, TZ>;
@@ -136,6 +137,14 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_step(
             if (in0 && ROWS) pull_rows<LAT, Real>(fin, x, y0 + ty, z, g, fpre);
             else pull<LAT, Real>(fin, wrap_any(x, g.nx), wrap_any(y0 + ty, g.ny), z, g, fpre);
             FT::stage_pop(fin, g, fp, x0, y0, tx, ty, fpre, lds_force, lds_force + FT::NR);
+            // the density of fin at this site, as the density pass would
+            // write it (the same sum in the same order), when asked for
+            if (rho_out && in0) {
+                Real acc = Real(0);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) acc += fpre[i];
+                rho_out[site_index<LAT>(x, y0 + ty, z, g)] = acc;
+            }
         } else {
             if (in0) {
                 if constexpr (ROWS) pull_rows<LAT, Real>(fin, x, y0 + ty, z, g, fpre);
@@ -582,17 +591,18 @@ hipError_t launch_density(const StepSpec& s, const void* fin, void* out, hipStre
 template <int LAT, typename Real, bool FORCE, int TX, int TY, int TZ, int SPT = 1, bool NTS = false,
           bool FUSED = false>
 static void step_tile(const StepSpec& s, const void* fin, void* fout, const void* drho,
-                      StepIndex si, double* partial, hipStream_t st) {
+                      StepIndex si, double* partial, hipStream_t st, void* rho_out = nullptr) {
     const Geom g = make_geom(s, TileShape{TX, TY, TZ, SPT, NTS, 0, 0});
     const dim3 grid(g.nblocks), block(TX * TY * TZ);
     const CollideParams<Real> P = collide_params<Real>(s);
     const ForceParams<Real> fp = force_params<Real>(s);
+    Real* ro = FUSED ? (Real*)rho_out : nullptr;
     if (partial)
         hipLaunchKernelGGL((k_step<LAT, Real, FORCE, true, TX, TY, TZ, SPT, NTS, FUSED>), grid, block, 0, st,
-                           (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
+                           (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial, ro);
     else
         hipLaunchKernelGGL((k_step<LAT, Real, FORCE, false, TX, TY, TZ, SPT, NTS, FUSED>), grid, block, 0, st,
-                           (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
+                           (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial, ro);
 }
 
 template <typename Real, int TX, int TY, bool NTS = false>
@@ -612,7 +622,8 @@ static void step_march(const StepSpec& s, int zc, const void* fin, void* fout, c
 
 template <int LAT, typename Real>
 static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fout,
-                          const void* drho, StepIndex si, double* partial, hipStream_t st) {
+                          const void* drho, StepIndex si, double* partial, hipStream_t st,
+                          void* rho_out) {
     if (!s.force) {
         switch (cfg) {
             case 0: step_tile<LAT, Real, false, 64, 4, 1, 1>(s, fin, fout, drho, si, partial, st); break;
@@ -649,9 +660,9 @@ static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fou
             case 0: step_tile<LAT, Real, true, 64, 4, 1>(s, fin, fout, drho, si, partial, st); break;
             case 1: step_tile<LAT, Real, true, 32, 8, 1>(s, fin, fout, drho, si, partial, st); break;
             case 2: step_tile<LAT, Real, true, 128, 2, 1>(s, fin, fout, drho, si, partial, st); break;
-            case 3: step_tile<LAT, Real, true, 64, 4, 1, 1, false, true>(s, fin, fout, drho, si, partial, st); break;
-            case 4: step_tile<LAT, Real, true, 32, 8, 1, 1, false, true>(s, fin, fout, drho, si, partial, st); break;
-            default: step_tile<LAT, Real, true, 128, 2, 1, 1, false, true>(s, fin, fout, drho, si, partial, st); break;
+            case 3: step_tile<LAT, Real, true, 64, 4, 1, 1, false, true>(s, fin, fout, drho, si, partial, st, rho_out); break;
+            case 4: step_tile<LAT, Real, true, 32, 8, 1, 1, false, true>(s, fin, fout, drho, si, partial, st, rho_out); break;
+            default: step_tile<LAT, Real, true, 128, 2, 1, 1, false, true>(s, fin, fout, drho, si, partial, st, rho_out); break;
         }
     }
 }
@@ -706,12 +717,12 @@ hipError_t launch_step_in_place(const StepSpec& s, int cfg, int phase, void* f,
 
 hipError_t launch_step(const StepSpec& s, int cfg, const void* fin, void* fout, const void* drho,
                        const unsigned long long* step_dev, unsigned long long step_host,
-                       double* partial, hipStream_t st) {
+                       double* partial, hipStream_t st, void* rho_out) {
     StepIndex si{step_dev, step_host};
-    if (s.lat == 0 && s.prec == 0) step_dispatch<0, float>(s, cfg, fin, fout, drho, si, partial, st);
-    else if (s.lat == 0) step_dispatch<0, double>(s, cfg, fin, fout, drho, si, partial, st);
-    else if (s.prec == 0) step_dispatch<1, float>(s, cfg, fin, fout, drho, si, partial, st);
-    else step_dispatch<1, double>(s, cfg, fin, fout, drho, si, partial, st);
+    if (s.lat == 0 && s.prec == 0) step_dispatch<0, float>(s, cfg, fin, fout, drho, si, partial, st, rho_out);
+    else if (s.lat == 0) step_dispatch<0, double>(s, cfg, fin, fout, drho, si, partial, st, rho_out);
+    else if (s.prec == 0) step_dispatch<1, float>(s, cfg, fin, fout, drho, si, partial, st, rho_out);
+    else step_dispatch<1, double>(s, cfg, fin, fout, drho, si, partial, st, rho_out);
     return hipGetLastError();
 }
 
