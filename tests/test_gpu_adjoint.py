@@ -227,3 +227,36 @@ def test_adjoint_run_equals_segment_loop(lattice, force, precision, nsteps, ck):
     assert torch.equal(a1, a2)
     np.testing.assert_array_equal(g1, g2)
     sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_one_launch_recompute_equals_density_pass_recompute(precision):
+    """The D2Q9 force recompute in a shape that forms its own density tile
+    writes each recomputed state's density from the step itself; the
+    gradients equal, bit for bit, those of a shape whose recompute runs the
+    density pass after every step (the two forward paths are bit-identical)."""
+    from paper_1012_3632_amd import Simulation
+    shape = (1, 37, 70)
+    nsteps, ck = 23, 8
+    kw = dict(C2, lattice="D2Q9", precision=precision, nz=1, ny=37, nx=70, **LANDAU)
+    kw["kT"] = 1e-6
+    out = []
+    for cfg in (3, 0):   # 64 x 4 forming its density tile; 64 x 4 reading a density pass
+        sim = Simulation(gpu_params(**kw), drho_init=W.initial_drho(shape, 3, 0.01))
+        sim.set_launch(cfg)
+        ckpts = []
+        for k0 in range(0, nsteps, ck):
+            ckpts.append(sim.state().clone())
+            sim.step(min(ck, nsteps - k0))
+        rhobar = torch.as_tensor(W.initial_drho(shape, 4, 1.0), dtype=sim.params.dtype,
+                                 device="cuda")
+        a, g = sim.adjoint_seed(rhobar), np.zeros(4)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            sim.adjoint_run(ckpts, a, ck, nsteps, grad=g, stream=stream)
+        torch.cuda.synchronize()
+        out.append((sim.state().clone(), a.clone(), g.copy()))
+        sim.close()
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
+    np.testing.assert_array_equal(out[0][2], out[1][2])
