@@ -419,6 +419,9 @@ def extras(args, stream):
     res["d3q19_batch64"] = {"ms_per_step": round(ms, 4), "MLUPS": round(Vt / (ms * 1e-3) / 1e6, 1),
                             "sites": Vt, "grid_config": best,
                             "hbm_frac": round(152 * Vt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            # groups taken through all steps in place stay
+                            # near the last-level cache size
+                            "bound": "hbm+llc" if pair_bytes else "hbm",
                             "in_place_pair_groups": ngroups, "pair_group_bytes": pair_bytes,
                             ("ms_per_step_replica_interleaved" if pair_bytes else
                              "ms_per_step_pairs_128MiB_groups"): round(ms_other, 4),
