@@ -350,16 +350,33 @@ def extras(args, stream):
     del drho
     (_, cfg_stats, _, _), _ = s.autotune(repeats=3)
     s.step(5, stats_stride=1)
-    n = max(args.steps // 4, 10)
+    n = max(args.steps // 4, 100)
     ms = time_steps(s, n, 1, stream)
-    # a step is the density pass (19 reads + 1 write) and the force step
-    # (19 reads + 19 writes + the density): 80 + 156 = 236 B per site
+    shape = list(s.launch_shape(cfg_stats))
+    if shape[7] == 2:
+        # the march forms the next step's density itself: it moves 152 B of
+        # populations, reads the density (4 B), writes the partial density
+        # (4 B) and the x-segment edge records (40 B per 64 sites); the
+        # completion pass reads and writes the density (8 B) and reads the
+        # populations that cross the tile's y edges (5 per edge row: 40 / TY
+        # B), the plane run's z edges (40 / 16 B) and the edge records; the
+        # first step of a call adds a density pass (80 B)
+        ty = shape[1]
+        bytes_site = 152 + 8 + 40 / 64 + 8 + 40 / ty + 40 / 16 + 40 / 64
+        pattern = "march forming the next density + completion pass (a call's first step: density pass)"
+    else:
+        # the density pass (19 reads + 1 write) and the force step (19 reads +
+        # 19 writes + the density): 80 + 156 = 236 B per site
+        bytes_site = 236
+        pattern = "density pass + march"
     res["d3q19_256_landau"] = {"ms_per_step": round(ms, 4), "MLUPS": round(V / (ms * 1e-3) / 1e6, 1),
-                               "hbm_frac_algorithmic_236B": round(236 * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "steps_timed": n, "pattern": pattern,
+                               "bytes_per_site": round(bytes_site, 2),
+                               "hbm_frac_algorithmic": round(bytes_site * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                # the method's minimum: populations in and out plus
                                # one density write and read (152 + 8 B)
                                "hbm_frac_algorithmic_160B": round(160 * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                               "launch_config": cfg_stats, "launch_shape": list(s.launch_shape(cfg_stats)),
+                               "launch_config": cfg_stats, "launch_shape": shape,
                                "statistics": "every step"}
     s.close()
     del s
@@ -798,8 +815,10 @@ def profile_step(args):
 
 
 def profile_landau():
-    """The 256^3 square-gradient step (density pass + z-marching force step)
-    in the benchmark's launch shape, for kernel counters."""
+    """The 256^3 square-gradient step for kernel counters: the z-marching force
+    step that forms the next density (64 x 4 columns, launch configuration 10,
+    the shape the benchmark's autotuner picks) with its completion pass; the
+    first step of the call has a density pass."""
     import torch
 
     import flb_workloads as W
@@ -807,10 +826,10 @@ def profile_landau():
     p = Params.from_dict(dict(W.params_of("d3q19_256_landau"), precision="fp32"))
     drho = W.initial_drho(p.shape, 7, W.WORKLOADS["d3q19_256_landau"]["init_noise"])
     sim = Simulation(p, drho_init=drho)
-    sim.set_launch(8)
+    sim.set_launch(10)
     sim.step(6, stats_stride=1)
     torch.cuda.synchronize()
-    print(json.dumps({"profile_landau": 8, "steps": 6}))
+    print(json.dumps({"profile_landau": 10, "steps": 6}))
 
 
 def profile_batch():

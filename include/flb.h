@@ -100,7 +100,10 @@ typedef struct flb_handle flb_handle;
 /* Sizes (bytes) of the caller-allocated device buffers for parameters p:
  * pop_bytes for each of the two population buffers (Q V reals), scratch_bytes
  * for the work area (counters and, for the non-ideal fluid, the density and
- * adjoint fields), stats_bytes for the FP64 statistics partials.
+ * adjoint fields; for the D3Q19 non-ideal fluid in FP32 also the next-step
+ * density that the z-marching force step forms, V floats, and its x-segment
+ * edge records, 64 B per 64 sites of a row), stats_bytes for the FP64
+ * statistics partials.
  * Returns FLB_ERR_INVALID_ARG for invalid parameters (see flb_init). Host only. */
 flb_status flb_query_sizes(const flb_params* p, size_t* pop_bytes, size_t* scratch_bytes,
                            size_t* stats_bytes);
@@ -464,7 +467,12 @@ flb_status flb_batch_destroy(flb_batch* b);
  * to ordinary steps, and a lone last step of a call runs the ordinary kernel.
  * flb_autotune times every candidate launch shape of the handle's step kernel
  * (block size, sites per thread, store hints, in-place pairs; tile or
- * z-marching shape for the force kernel) the way a run uses it (ordinary
+ * z-marching shape for the force kernel, and for the D3Q19 force step in FP32
+ * z-marching shapes that form the next step's density themselves (the
+ * populations of Sec. V eq. lbe-mom after collision, summed over c_i as
+ * streaming delivers them: in-tile sources through LDS and wavefront shifts,
+ * the rest added by a completion pass), so that only the first step of a
+ * call runs a density pass) the way a run uses it (ordinary
  * steps alternate the two buffers over `repeats` steps; in-place pairs are
  * timed after about 4 ms of settling steps, round-robin over at least three
  * rounds of about 2 ms each, best round kept) and afterwards
@@ -490,7 +498,9 @@ flb_status flb_launch_configs(const flb_handle* h, int32_t* count, int32_t* curr
  * 1 if populations are stored with non-temporal hints, the number of z planes
  * a block sweeps (z-marching force step; 0 otherwise), 1 for an in-place
  * shape, and 1 for a force step that forms its density tile from the
- * populations itself (no density pass before it; D2Q9). */
+ * populations itself (no density pass before it; D2Q9), 2 for a z-marching
+ * force step that forms the next step's density (D3Q19, FP32; in FP64 such a
+ * shape runs the plain march of its tile). */
 flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape);
 /* The same for a batch: the candidates are persistent grids of 8, 4, 16 or 2
  * blocks per compute unit; best[2] / best_ms[2] as for flb_autotune.  It then

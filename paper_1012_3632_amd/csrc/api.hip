@@ -152,6 +152,7 @@ struct flb_handle {
     // scratch regions
     unsigned long long* step_dev;
     void* drho;             // V reals (force model)
+    void* rho_part;         // V reals: the march's partial next density (D3Q19 force, FP32)
     void* adj_work;
     double* gpartial;       // adjoint gradient partials
     uint32_t gslots;
@@ -171,11 +172,14 @@ void release_graphs(flb_handle* h) {
     }
 }
 
-void scratch_layout(const StepSpec& s, size_t V, size_t rb, size_t* drho_off, size_t* adj_off,
-                    size_t* gpart_off, size_t* total) {
+void scratch_layout(const StepSpec& s, size_t V, size_t rb, size_t* drho_off, size_t* part_off,
+                    size_t* adj_off, size_t* gpart_off, size_t* total) {
     size_t off = SCRATCH_HEADER;
     *drho_off = off;
     off += align_up(V * rb);
+    // the partial-density march's output (D3Q19 force steps in FP32)
+    *part_off = off;
+    off += align_up(partial_density_bytes(s));
     *adj_off = off;
     off += align_up(adjoint_work_bytes(s));
     *gpart_off = off;
@@ -183,14 +187,19 @@ void scratch_layout(const StepSpec& s, size_t V, size_t rb, size_t* drho_off, si
     *total = off;
 }
 
-// One forward step of the handle: cur -> other, then swap.
+// One forward step of the handle: cur -> other, then swap.  drho_ready: the
+// density scratch already holds cur's density (the previous step of this
+// call was a partial-density march and its completion); updated on return.
 flb_status do_step(flb_handle* h, bool sample, const unsigned long long* step_dev,
-                   unsigned long long step_host, hipStream_t st) {
+                   unsigned long long step_host, hipStream_t st, bool* drho_ready) {
     const int cfg = sample ? h->cfg_stats : h->cfg;
-    if (h->spec.force && !config_fused(h->spec, cfg))
+    const bool pd = config_partial_density(h->spec, cfg);
+    if (h->spec.force && !config_fused(h->spec, cfg) && !(pd && *drho_ready))
         HIP_TRY(launch_density(h->spec, h->cur(), h->drho, st));
     HIP_TRY(launch_step(h->spec, cfg, h->cur(), h->other(), h->drho, step_dev, step_host,
-                        sample ? h->stats : nullptr, st));
+                        sample ? h->stats : nullptr, st, nullptr, pd ? h->rho_part : nullptr));
+    if (pd) HIP_TRY(launch_density_fix(h->spec, cfg, h->other(), h->rho_part, h->drho, st));
+    *drho_ready = pd;
     h->cur_a = !h->cur_a;
     return FLB_OK;
 }
@@ -200,6 +209,7 @@ flb_status do_step(flb_handle* h, bool sample, const unsigned long long* step_de
 flb_status run_steps(flb_handle* h, int64_t nsteps, int32_t stride, bool graph_mode,
                      hipStream_t st, int64_t* samples, int64_t k0 = 0) {
     int64_t ns = 0;
+    bool drho_ready = false;   // a call starts with a density pass
     const unsigned long long* dev = graph_mode ? h->step_dev : nullptr;
     const unsigned long long base = graph_mode ? 0ull : (unsigned long long)h->step;
     for (int64_t k = 0; k < nsteps;) {
@@ -217,7 +227,7 @@ flb_status run_steps(flb_handle* h, int64_t nsteps, int32_t stride, bool graph_m
             k += 2;
             continue;
         }
-        flb_status r = do_step(h, sample, dev, base + (unsigned long long)k, st);
+        flb_status r = do_step(h, sample, dev, base + (unsigned long long)k, st, &drho_ready);
         if (r != FLB_OK) return r;
         ns += sample;
         ++k;
@@ -277,8 +287,8 @@ flb_status flb_query_sizes(const flb_params* p, size_t* pop_bytes, size_t* scrat
     const size_t V = (size_t)p->nx * p->ny * p->nz;
     const size_t rb = p->precision == FLB_FP64 ? 8 : 4;
     const int q = lattice_q(p->lattice);
-    size_t a, b, c, total;
-    scratch_layout(s, V, rb, &a, &b, &c, &total);
+    size_t a, b, c, d, total;
+    scratch_layout(s, V, rb, &a, &b, &c, &d, &total);
     if (pop_bytes) *pop_bytes = align_up((size_t)q * V * rb);
     if (scratch_bytes) *scratch_bytes = total;
     if (stats_bytes) *stats_bytes = align_up(((size_t)max_slots(s) + 1) * 2 * q * sizeof(double));
@@ -317,12 +327,13 @@ flb_status flb_init(const flb_params* p, void* f_a, void* f_b, void* scratch, vo
     h->pair_cfg = -1;
     h->graph[0] = h->graph[1] = nullptr;
     h->gexec[0] = h->gexec[1] = nullptr;
-    size_t drho_off, adj_off, gp_off, total;
-    scratch_layout(h->spec, h->V, h->real_bytes, &drho_off, &adj_off, &gp_off, &total);
+    size_t drho_off, part_off, adj_off, gp_off, total;
+    scratch_layout(h->spec, h->V, h->real_bytes, &drho_off, &part_off, &adj_off, &gp_off, &total);
     h->step_dev = (unsigned long long*)h->scratch;
     h->spec.nonfinite = (uint32_t*)(h->scratch + NONFINITE_OFF);
     h->check_every = 0;
     h->drho = h->scratch + drho_off;
+    h->rho_part = h->scratch + part_off;
     h->adj_work = h->scratch + adj_off;
     h->gpartial = (double*)(h->scratch + gp_off);
     h->gslots = adjoint_slots(h->spec);
@@ -636,16 +647,22 @@ flb_status flb_autotune(flb_handle* h, int32_t repeats, int32_t* best, double* b
         for (int c = 0; c < ncfg && e == hipSuccess; ++c) {
             if (config_in_place(h->spec, c)) continue;   // timed as pairs below
             float ms = 0.f;
-            // a force step that reads a density field pays for its pass
-            const bool pass = h->spec.force && !config_fused(h->spec, c);
+            // a force step that reads a density field pays for its pass; a
+            // partial-density march for the completion of the next density
+            const bool pd = config_partial_density(h->spec, c);
+            const bool pass = h->spec.force && !config_fused(h->spec, c) && !pd;
             e = timed([&](int k) {
                 void* in = (k & 1) ? B : A;
+                void* out = (k & 1) ? A : B;
                 if (pass) {
                     hipError_t r = launch_density(h->spec, in, h->drho, st);
                     if (r != hipSuccess) return r;
                 }
-                return launch_step(h->spec, c, in, (k & 1) ? A : B, h->drho, nullptr, h->step,
-                                   part, st);
+                hipError_t r = launch_step(h->spec, c, in, out, h->drho, nullptr, h->step, part, st,
+                                           nullptr, pd ? h->rho_part : nullptr);
+                if (r == hipSuccess && pd)
+                    r = launch_density_fix(h->spec, c, out, h->rho_part, h->drho, st);
+                return r;
             }, 1, &ms);
             if (e == hipSuccess && ms < bt[mode]) {
                 bt[mode] = ms;
@@ -760,7 +777,7 @@ flb_status flb_launch_shape(const flb_handle* h, int32_t config, int32_t* shape)
     shape[4] = t.nt;
     shape[5] = t.zc;
     shape[6] = t.ip;
-    shape[7] = t.fd;
+    shape[7] = t.fd ? 1 : (t.pd ? 2 : 0);
     return FLB_OK;
 }
 

@@ -15,6 +15,9 @@ struct TileShape {
                       //    step runs the ordinary kernel of the same tile
     int fd;           // 1: the force step forms the staged density tile from the
                       //    populations itself (no density pass; D2Q9)
+    int pd;           // 1: the z-marching force step also forms the next step's
+                      //    density from its own sources (FP32), completed by
+                      //    launch_density_fix (no density pass between steps)
 };
 
 // Candidate tiles (the autotuner picks one per handle).
@@ -24,11 +27,13 @@ constexpr TileShape IDEAL_CFG[N_IDEAL_CFG] = {
     {128, 2, 1, 2, 0}, {64, 4, 1, 2, 0},  {128, 2, 1, 4, 0}, {256, 1, 1, 2, 0},
     {128, 2, 1, 1, 1}, {256, 1, 1, 1, 1}, {128, 2, 1, 1, 0, 0, 1}, {64, 4, 1, 1, 0, 0, 1},
     {256, 1, 1, 1, 0, 0, 1}, {128, 2, 1, 2, 0, 0, 1}, {64, 4, 1, 2, 0, 0, 1}};
-constexpr int N_FORCE3_CFG = 9;
+constexpr int N_FORCE3_CFG = 12;
 constexpr TileShape FORCE3_CFG[N_FORCE3_CFG] = {
     {32, 4, 2, 1, 0},     {16, 4, 4, 1, 0},     {64, 2, 2, 1, 0},
     {64, 4, 1, 1, 0, 16}, {64, 4, 1, 1, 0, 32}, {32, 8, 1, 1, 0, 16},
-    {64, 8, 1, 1, 0, 16}, {128, 2, 1, 1, 0, 16}, {128, 2, 1, 1, 1, 16}};
+    {64, 8, 1, 1, 0, 16}, {128, 2, 1, 1, 0, 16}, {128, 2, 1, 1, 1, 16},
+    {128, 2, 1, 1, 1, 16, 0, 0, 1}, {64, 4, 1, 1, 0, 16, 0, 0, 1},
+    {64, 8, 1, 1, 0, 16, 0, 0, 1}};
 constexpr int N_FORCE2_CFG = 6;
 constexpr TileShape FORCE2_CFG[N_FORCE2_CFG] = {
     {64, 4, 1, 1, 0},          {32, 8, 1, 1, 0},          {128, 2, 1, 1, 0},
@@ -62,9 +67,22 @@ hipError_t launch_density(const StepSpec& s, const void* fin, void* drho_out, hi
 // rho_out: for the force shapes that form their own density tile
 // (config_fused), if non-null, receives fin's density field, the bits
 // launch_density would write; ignored otherwise.
+// rho_part: for the partial-density shapes (config_partial_density), if
+// non-null, receives the part of fout's density that the march forms; null
+// runs the plain march of the same shape.
 hipError_t launch_step(const StepSpec& s, int cfg, const void* fin, void* fout, const void* drho,
                        const unsigned long long* step_dev, unsigned long long step_host,
-                       double* partial, hipStream_t st, void* rho_out = nullptr);
+                       double* partial, hipStream_t st, void* rho_out = nullptr,
+                       void* rho_part = nullptr);
+// Partial-density shapes: the density of fin after streaming from the
+// march's rho_part (the step fin was written by, same shape) and the
+// populations of fin whose sources lie outside the forming block.
+bool config_partial_density(const StepSpec& s, int cfg);
+// Bytes of the partial-density work area (the partial density and the
+// march's edge records; 0 where no shape forms a partial density).
+size_t partial_density_bytes(const StepSpec& s);
+hipError_t launch_density_fix(const StepSpec& s, int cfg, const void* fin, const void* rho_part,
+                              void* out, hipStream_t st);
 // In-place shapes: one step of a pair on the single buffer f (phase 0 then 1;
 // see push_rows_opp).  The state is in the ordinary layout after phase 1.
 bool config_in_place(const StepSpec& s, int cfg);

@@ -15,6 +15,8 @@
 // force at each site from those (no extra HBM pass for mu).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.h"
 #include "internal.h"
 
@@ -302,6 +304,98 @@ __global__ __launch_bounds__(TX* TY) void k_step_ip(Real* f, Geom g, CollidePara
     }
 }
 
+// The next step's density formed inside the z-march.  After streaming, the
+// density at x is sum_i S*_i(x - c_i) over the post-collision populations S*
+// that the march has just computed.  Each thread keeps running sums for the
+// planes of its column that can still receive.  The rest population and the
+// two along z stay in the thread; the six that move along x only reach the
+// neighbouring lane through a wavefront shift (DPP); the ten with c_y != 0
+// go through LDS (NYS slots of one value per thread), written only by rows
+// whose receiver row is in the tile.  A source counts when it lies in the
+// same 64-wide x segment (one wavefront row), in the block's rows
+// [y0, min(y0 + TY, ny)) and planes [zb, ze), and in the box; k_density_fix
+// adds every other source after the launch.  TX is a multiple of 64.
+template <int TX, int TY>
+struct MarchDensity {
+    using L = Lattice<1>;
+    static_assert(TX % 64 == 0, "wavefront rows");
+    static constexpr int NT = TX * TY, PAD = TX + 1;
+    // with two rows each row sends in one direction only, so the two
+    // directions share slots
+    static constexpr int NYS = TY == 2 ? 5 : 10;
+    static constexpr int LDS = NYS * NT + 2 * PAD;
+    static constexpr int WAVE_SHL1 = 0x130, WAVE_SHR1 = 0x138;
+    // slot of population i (c_y != 0): its rank among the five of its c_y sign
+    static constexpr int yslot(int i) {
+        return (i == 3 || i == 4) ? 0 : (i == 7 || i == 8) ? 1 : (i == 9 || i == 10) ? 2
+             : (i == 15 || i == 17) ? 3 : 4;
+    }
+    static constexpr int ybase(int i) { return (TY == 2 || L::cy[i] == 1) ? 0 : 5; }
+    // the in-plane exchange of the plane just computed: the x-only movers
+    // into the sums (am: plane below, a0: this plane, ap: plane above), the
+    // others into LDS.  Called by every lane (f of lanes outside the box is
+    // never counted); up / down: this row has a receiver row above / below.
+    static __device__ __forceinline__ void put(float* lx, const float (&f)[L::Q], bool vxm, bool vxp,
+                                               bool up, bool down, float& am, float& a0, float& ap) {
+        // lane l receives from l - 1 (c_x = +1) and from l + 1 (c_x = -1)
+        const float r1 = dpp_shift<WAVE_SHR1>(f[1]), r2 = dpp_shift<WAVE_SHL1>(f[2]);
+        const float r11 = dpp_shift<WAVE_SHR1>(f[11]), r13 = dpp_shift<WAVE_SHL1>(f[13]);
+        const float r12 = dpp_shift<WAVE_SHR1>(f[12]), r14 = dpp_shift<WAVE_SHL1>(f[14]);
+        a0 += (vxm ? r1 : 0.f) + (vxp ? r2 : 0.f);
+        ap += (vxm ? r11 : 0.f) + (vxp ? r13 : 0.f);
+        am += (vxm ? r12 : 0.f) + (vxp ? r14 : 0.f);
+#pragma unroll
+        for (int i = 3; i < L::Q; ++i) {
+            if (L::cy[i] == 0) continue;
+            if (L::cy[i] == 1 ? up : down)
+                lx[PAD + (ybase(i) + yslot(i)) * NT + (int)threadIdx.x] = f[i];
+        }
+    }
+    // Edge records, one per (z, y, 64-wide x segment), EDGE floats: [0, 5)
+    // the populations (1, 7, 8, 11, 12) (c_x = +1) of the segment's last
+    // site (x & 63 == 63, or the box's last x), [8, 13) the populations
+    // (2, 9, 10, 13, 14) (c_x = -1) of its first site.  These are the
+    // sources that a segment's neighbours need and MarchDensity leaves out.
+    static constexpr int EDGE = 16;
+    static __device__ __forceinline__ uint32_t edge_record(int x, int y, int z, const Geom& g) {
+        const uint32_t nseg = ((uint32_t)g.nx + 63u) >> 6;
+        return (((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * nseg + ((uint32_t)x >> 6)) * EDGE;
+    }
+    static __device__ __forceinline__ void put_edge(float* edge, const float (&f)[L::Q], int x, int y,
+                                                    int z, const Geom& g) {
+        if ((x & 63) == 63 || x == g.nx - 1) {
+            float* r = edge + edge_record(x, y, z, g);
+            *(float4*)r = make_float4(f[1], f[7], f[8], f[11]);
+            r[4] = f[12];
+        }
+        if ((x & 63) == 0) {
+            float* r = edge + edge_record(x, y, z, g) + 8;
+            *(float4*)r = make_float4(f[2], f[9], f[10], f[13]);
+            r[4] = f[14];
+        }
+    }
+    // the previous plane's c_y != 0 movers from the rows below (vym) and
+    // above (vyp), into am (c_z = -1), a0 (c_z = 0) and ap (c_z = +1)
+    static __device__ __forceinline__ void take(const float* lx, bool vxm, bool vxp, bool vym,
+                                                bool vyp, float& am, float& a0, float& ap) {
+#pragma unroll
+        for (int i = 3; i < L::Q; ++i) {
+            if (L::cy[i] == 0) continue;
+            if (!(L::cy[i] == 1 ? vym : vyp)) continue;
+            const float v = lx[PAD + (ybase(i) + yslot(i)) * NT + (int)threadIdx.x - L::cy[i] * TX - L::cx[i]];
+            const float u = L::cx[i] == 1 ? (vxm ? v : 0.f) : (L::cx[i] == -1 ? (vxp ? v : 0.f) : v);
+            if (L::cz[i] == -1) am += u;
+            else if (L::cz[i] == 0) a0 += u;
+            else ap += u;
+        }
+    }
+};
+
+template <bool PD, int TX, int TY>
+struct MarchDensityLds { static constexpr int value = 1; };
+template <int TX, int TY>
+struct MarchDensityLds<true, TX, TY> { static constexpr int value = MarchDensity<TX, TY>::LDS; };
+
 // D3Q19 force step, z-marching form: block b owns the column tile (x0, y0)
 // of TX x TY sites and the planes [zb, zb + ZC) of it (ZC = g.zc).  The density
 // and chemical potential live in LDS ring buffers (ForceMarch); the density
@@ -309,19 +403,27 @@ __global__ __launch_bounds__(TX* TY) void k_step_ip(Real* f, Geom g, CollidePara
 // populations of the current plane are requested before the barriers, so
 // global loads overlap the LDS work.  NTS: populations stored with
 // non-temporal hints (the state of a large lattice does not stay in the cache).
-template <typename Real, bool STATS, int TX, int TY, bool NTS = false>
+// PD: the block also writes the next step's density from its own sources to
+// rho_part (MarchDensity), and the outflow of each 64-wide x segment's first
+// and last site to edge records (MarchDensity::EDGE), which k_density_fix
+// uses to complete it.
+template <typename Real, bool STATS, int TX, int TY, bool NTS = false, bool PD = false>
 __global__ __launch_bounds__(TX* TY) void k_step_march(
     const Real* __restrict__ fin, Real* __restrict__ fout, const Real* __restrict__ drho, Geom g,
-    CollideParams<Real> P, ForceParams<Real> fp, StepIndex st, double* __restrict__ partial) {
+    CollideParams<Real> P, ForceParams<Real> fp, StepIndex st, double* __restrict__ partial,
+    Real* __restrict__ rho_part, Real* __restrict__ edge) {
     using L = Lattice<1>;
     using M = Moments<1, Real>;
     using FM = ForceMarch<Real, TX, TY>;
+    using MD = MarchDensity<TX, TY>;
+    static_assert(!PD || std::is_same<Real, float>::value, "partial density: FP32");
     constexpr int Q = L::Q, NT = TX * TY;
     constexpr bool ROWS = (TX % 64) == 0;
     constexpr int LDS_S = STATS ? 4 * ((NT + 63) / 64) * 2 * Q : 1;
     __shared__ Real lds_r[5 * FM::NRP];
     __shared__ Real lds_m[3 * FM::NMP];
     __shared__ double lds_stats[LDS_S];
+    __shared__ Real lds_x[MarchDensityLds<PD, TX, TY>::value];
 
     const uint32_t b = xcd_remap(blockIdx.x, g.nblocks);
     const uint32_t ncol = (uint32_t)g.nbx * (uint32_t)g.nby;
@@ -353,6 +455,14 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(
 #pragma unroll
         for (int k = 0; k < 2 * Q; ++k) v[k] = Real(0);
     }
+    // PD: sums of the next density at planes z - 2 .. z + 1 of this column
+    // (at the top of iteration z); which in-plane neighbours are sources
+    // (x - 1, x + 1 in this wavefront row, y - 1, y + 1 in the tile, in the
+    // box) and which neighbour rows of the tile receive from this one
+    Real a_m2 = Real(0), a_m1 = Real(0), a_0 = Real(0), a_p1 = Real(0);
+    const bool vxm = (x & 63) != 0, vxp = (x & 63) != 63 && x + 1 < g.nx;
+    const bool vym = ty >= 1, vyp = ty + 1 < TY && y + 1 < g.ny;
+    const bool up = ty + 1 < TY, down = ty >= 1;
     const uint32_t step = st.get();
 #pragma unroll 1
     for (int z = zb; z < ze; ++z) {
@@ -374,6 +484,14 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(
         }
         __syncthreads();
         FM::mu_plane(lds_r, lds_m, z + 1, zb, fp);
+        if constexpr (PD) {
+            // plane z - 1's exchange; plane z - 2 then has all its sources
+            if (z > zb) {
+                MD::take(lds_x, vxm, vxp, vym, vyp, a_m2, a_m1, a_0);
+                if (z - 2 >= zb && inxy)
+                    plane_st(rho_part + (size_t)(uint32_t)(((z - 2) * g.ny + y) * g.nx), (uint32_t)xl, a_m2);
+            }
+        }
         __syncthreads();
         if (inxy) {
             Real F[3];
@@ -393,6 +511,13 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(
                 site_normals<L::NPAIR, Real>(site, step, 0u, P.replica, P.key0, P.key1, zn);
             collide_moments<1, Real, true>(m, F, zn, P);
             M::inverse(m, f);
+            if constexpr (PD) {
+                a_m1 += f[6];   // (0, 0, -1) reaches plane z - 1
+                a_0 += f[0];
+                a_p1 = f[5];    // (0, 0, +1) reaches plane z + 1
+                MD::put(lds_x, f, vxm, vxp, up, down, a_m1, a_0, a_p1);
+                MD::put_edge(edge, f, x, y, z, g);
+            }
             if constexpr (ROWS) {
                 const size_t row = (size_t)(uint32_t)((z * g.ny + y) * g.nx);
 #pragma unroll
@@ -405,8 +530,142 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(
                 for (int i = 0; i < Q; ++i) plane_st(fout + (size_t)i * gz.V, site, f[i]);
             }
         }
+        if constexpr (PD) {
+            a_m2 = a_m1;
+            a_m1 = a_0;
+            a_0 = a_p1;
+        }
+    }
+    if constexpr (PD) {
+        // the last plane's exchange completes planes ze - 2 and ze - 1 (the
+        // sources of ze - 1 in plane ze belong to the next block in z)
+        __syncthreads();
+        MD::take(lds_x, vxm, vxp, vym, vyp, a_m2, a_m1, a_0);
+        if (inxy) {
+            if (ze - 2 >= zb)
+                plane_st(rho_part + (size_t)(uint32_t)(((ze - 2) * g.ny + y) * g.nx), (uint32_t)x, a_m2);
+            plane_st(rho_part + (size_t)(uint32_t)(((ze - 1) * g.ny + y) * g.nx), (uint32_t)x, a_m1);
+        }
     }
     if constexpr (STATS) block_accumulate<2 * Q, NT>(v, partial + (size_t)b * 2 * Q, lds_stats);
+}
+
+// Elements from the start of the partial-density work area to its edge
+// records (the partial density comes first, V floats, 256-byte aligned).
+__host__ __device__ inline size_t pd_edge_offset(uint32_t V) { return ((size_t)V + 63) / 64 * 64; }
+
+// Completes the march's partial density: adds to rho_part(x) the streamed
+// populations S*_i(x - c_i) whose source the forming block left out (outside
+// the 64-wide x segment of x, the TY rows of its tile from the origin, its
+// run of g.zc planes, as in k_step_march / MarchDensity), in the order
+// i = 1 .. Q - 1.  A block of four wavefronts covers 64 SPL sites of x
+// (from 64 SPL bx) in RY rows of plane z, each wavefront RY / 4 rows, SPL
+// sites per lane.  Whether a population crosses the row's tile or plane-run edge is
+// uniform, so those loads read whole rows under scalar branches; a
+// segment's first lane (x & 63 == 0) and last lane (x & 63 == 63, or the
+// box's last x) take the x movers from the neighbouring segments' edge
+// records instead of scattered single loads.
+constexpr int FIX_SPL = 2;   // sites per lane of k_density_fix (2 measured best of 1, 2, 4)
+template <int TY>
+__global__ __launch_bounds__(256) void k_density_fix(const float* __restrict__ fin,
+                                                     const float* __restrict__ rho_part,
+                                                     const float* __restrict__ edge,
+                                                     float* __restrict__ out, Geom g) {
+    using L = Lattice<1>;
+    constexpr int SPL = FIX_SPL, RY = 16;
+    const int z = (int)blockIdx.z;
+    const int zb = z - z % g.zc;
+    const bool zlo = z == zb, zhi = z + 1 == min(zb + g.zc, g.nz);
+    const uint32_t nxy = (uint32_t)g.nx * (uint32_t)g.ny;
+    const uint32_t nseg = ((uint32_t)g.nx + 63u) >> 6;
+    const uint32_t szm = z == 0 ? (uint32_t)(g.nz - 1) * nxy : 0u - nxy;
+    const uint32_t szp = z == g.nz - 1 ? 0u - (uint32_t)(g.nz - 1) * nxy : nxy;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+    const int lane = (int)threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    // lanes past the box's last x read at the last x (valid addresses) and
+    // store nothing
+    int xs[SPL];
+    uint32_t sxm[SPL], sxp[SPL];
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) {
+        const int x = min((int)(blockIdx.x * (64u * SPL)) + 64 * k + lane, g.nx - 1);
+        xs[k] = x;
+        sxm[k] = x == 0 ? (uint32_t)(g.nx - 1) : 0u - 1u;
+        sxp[k] = x == g.nx - 1 ? 0u - (uint32_t)(g.nx - 1) : 1u;
+    }
+#pragma unroll 1
+    for (int y = (int)blockIdx.y * RY + wave; y < min((int)(blockIdx.y + 1) * RY, g.ny); y += 4) {
+        const int y0 = y - y % TY;
+        const bool ylo = y == y0, yhi = y + 1 == min(y0 + TY, g.ny);
+        const uint32_t row = (uint32_t)z * nxy + (uint32_t)y * (uint32_t)g.nx;
+        const uint32_t sym = y == 0 ? (uint32_t)(g.ny - 1) * (uint32_t)g.nx : 0u - (uint32_t)g.nx;
+        const uint32_t syp = y == g.ny - 1 ? 0u - (uint32_t)(g.ny - 1) * (uint32_t)g.nx : (uint32_t)g.nx;
+        const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+        auto src = [&](int i, int k) {
+            return row + (uint32_t)xs[k] + (L::cx[i] == 0 ? 0u : (L::cx[i] > 0 ? sxm[k] : sxp[k])) +
+                   (L::cy[i] == 0 ? 0u : (L::cy[i] > 0 ? sym : syp)) +
+                   (L::cz[i] == 0 ? 0u : (L::cz[i] > 0 ? szm : szp));
+        };
+        // the edge record of the source of population i (c_x != 0) at x
+        auto rec = [&](int i, int x) {
+            const int sx = L::cx[i] > 0 ? (x == 0 ? g.nx - 1 : x - 1) : (x == g.nx - 1 ? 0 : x + 1);
+            const int sy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? ym : yp);
+            const int sz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zm : zp);
+            constexpr int slot[L::Q] = {0, 0, 8, 0, 0, 0, 0, 1, 2, 9, 10, 3, 4, 11, 12, 0, 0, 0, 0};
+            return ((uint32_t)sz * (uint32_t)g.ny + (uint32_t)sy) * nseg * 16u +
+                   ((uint32_t)sx >> 6) * 16u + (uint32_t)slot[i];
+        };
+        float v[SPL][L::Q];
+#pragma unroll
+        for (int k = 0; k < SPL; ++k)
+#pragma unroll
+            for (int i = 1; i < L::Q; ++i) v[k][i] = 0.f;
+        // whole rows: sources across the tile's y edge or the plane run's z edge
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            const bool oy = (L::cy[i] == 1 && ylo) || (L::cy[i] == -1 && yhi);
+            const bool oz = (L::cz[i] == 1 && zlo) || (L::cz[i] == -1 && zhi);
+            if (oy || oz) {
+#pragma unroll
+                for (int k = 0; k < SPL; ++k) v[k][i] = plane_ld(fin + (size_t)i * g.V, src(i, k));
+            }
+        }
+        // segment edges, for the x movers not already read as whole rows
+        if (lane == 0) {
+#pragma unroll
+            for (int i = 1; i < L::Q; ++i) {
+                if (L::cx[i] != 1) continue;
+                const bool oy = (L::cy[i] == 1 && ylo) || (L::cy[i] == -1 && yhi);
+                const bool oz = (L::cz[i] == 1 && zlo) || (L::cz[i] == -1 && zhi);
+                if (!(oy || oz)) {
+#pragma unroll
+                    for (int k = 0; k < SPL; ++k) v[k][i] = edge[rec(i, xs[k])];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) {
+            if (lane == 63 || xs[k] + 1 == g.nx) {
+#pragma unroll
+                for (int i = 1; i < L::Q; ++i) {
+                    if (L::cx[i] != -1) continue;
+                    const bool oy = (L::cy[i] == 1 && ylo) || (L::cy[i] == -1 && yhi);
+                    const bool oz = (L::cz[i] == 1 && zlo) || (L::cz[i] == -1 && zhi);
+                    if (!(oy || oz)) v[k][i] = edge[rec(i, xs[k])];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) {
+            if ((int)(blockIdx.x * (64u * SPL)) + 64 * k + lane >= g.nx) break;
+            const uint32_t site = row + (uint32_t)xs[k];
+            float acc = plane_ld(rho_part, site);
+#pragma unroll
+            for (int i = 1; i < L::Q; ++i) acc += v[k][i];
+            plane_st(out, site, acc);
+        }
+    }
 }
 
 // rho and rho u = sum c f + F/2 after streaming of state fin.
@@ -605,25 +864,42 @@ static void step_tile(const StepSpec& s, const void* fin, void* fout, const void
                            (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial, ro);
 }
 
+// rho_part: the partial next density (partial-density shapes: FP32, TX a
+// multiple of 64; null runs the plain march of the same shape).
 template <typename Real, int TX, int TY, bool NTS = false>
 static void step_march(const StepSpec& s, int zc, const void* fin, void* fout, const void* drho,
-                       StepIndex si, double* partial, hipStream_t st) {
+                       StepIndex si, double* partial, hipStream_t st, void* rho_part = nullptr) {
     const Geom g = make_geom(s, TileShape{TX, TY, 1, 1, NTS, zc, 0});
     const dim3 grid(g.nblocks), block(TX * TY);
     const CollideParams<Real> P = collide_params<Real>(s);
     const ForceParams<Real> fp = force_params<Real>(s);
-    if (partial)
+    if constexpr (std::is_same<Real, float>::value && TX % 64 == 0) {
+        Real* rp = (Real*)rho_part;
+        Real* ed = rp ? rp + pd_edge_offset(g.V) : nullptr;
+        if (rp && partial) {
+            hipLaunchKernelGGL((k_step_march<Real, true, TX, TY, NTS, true>), grid, block, 0, st,
+                               (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial, rp, ed);
+            return;
+        }
+        if (rp) {
+            hipLaunchKernelGGL((k_step_march<Real, false, TX, TY, NTS, true>), grid, block, 0, st,
+                               (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial, rp, ed);
+            return;
+        }
+    }
+    if (partial) {
         hipLaunchKernelGGL((k_step_march<Real, true, TX, TY, NTS>), grid, block, 0, st, (const Real*)fin,
-                           (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
-    else
+                           (Real*)fout, (const Real*)drho, g, P, fp, si, partial, (Real*)nullptr, (Real*)nullptr);
+    } else {
         hipLaunchKernelGGL((k_step_march<Real, false, TX, TY, NTS>), grid, block, 0, st, (const Real*)fin,
-                           (Real*)fout, (const Real*)drho, g, P, fp, si, partial);
+                           (Real*)fout, (const Real*)drho, g, P, fp, si, partial, (Real*)nullptr, (Real*)nullptr);
+    }
 }
 
 template <int LAT, typename Real>
 static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fout,
                           const void* drho, StepIndex si, double* partial, hipStream_t st,
-                          void* rho_out) {
+                          void* rho_out, void* rho_part) {
     if (!s.force) {
         switch (cfg) {
             case 0: step_tile<LAT, Real, false, 64, 4, 1, 1>(s, fin, fout, drho, si, partial, st); break;
@@ -653,7 +929,11 @@ static void step_dispatch(const StepSpec& s, int cfg, const void* fin, void* fou
             case 5: step_march<Real, 32, 8>(s, 16, fin, fout, drho, si, partial, st); break;
             case 6: step_march<Real, 64, 8>(s, 16, fin, fout, drho, si, partial, st); break;
             case 7: step_march<Real, 128, 2>(s, 16, fin, fout, drho, si, partial, st); break;
-            default: step_march<Real, 128, 2, true>(s, 16, fin, fout, drho, si, partial, st); break;
+            case 8: step_march<Real, 128, 2, true>(s, 16, fin, fout, drho, si, partial, st); break;
+            // the march also forms the next density (rho_part, completed by k_density_fix)
+            case 9: step_march<Real, 128, 2, true>(s, 16, fin, fout, drho, si, partial, st, rho_part); break;
+            case 10: step_march<Real, 64, 4>(s, 16, fin, fout, drho, si, partial, st, rho_part); break;
+            default: step_march<Real, 64, 8>(s, 16, fin, fout, drho, si, partial, st, rho_part); break;
         }
     } else {
         switch (cfg) {
@@ -694,6 +974,37 @@ static void ip_dispatch(const StepSpec& s, int cfg, int phase, void* f, StepInde
     }
 }
 
+bool config_partial_density(const StepSpec& s, int cfg) {
+    // the completion pass launches one block per plane in grid z (below 2^16)
+    return s.force && s.prec == 0 && s.nz <= 65535 && cfg >= 0 &&
+           cfg < n_configs(s.lat, s.force) && config_shape(s.lat, s.force, cfg).pd;
+}
+
+size_t partial_density_bytes(const StepSpec& s) {
+    if (!(s.force && s.lat == 1 && s.prec == 0)) return 0;
+    const size_t V = (size_t)s.nx * s.ny * s.nz;
+    const size_t nseg = ((size_t)s.nx + 63) / 64;
+    return pd_edge_offset((uint32_t)V) * 4 + (size_t)s.nz * s.ny * nseg * 16 * 4;
+}
+
+hipError_t launch_density_fix(const StepSpec& s, int cfg, const void* fin, const void* rho_part,
+                              void* out, hipStream_t st) {
+    if (!config_partial_density(s, cfg)) return hipErrorInvalidValue;
+    const TileShape t = config_shape(s.lat, s.force, cfg);
+    const Geom g = make_geom(s, t);
+    const dim3 grid((s.nx + 64 * FIX_SPL - 1) / (64 * FIX_SPL), (s.ny + 15) / 16, s.nz), block(256);
+    const float* f = (const float*)fin;
+    const float* rp = (const float*)rho_part;
+    const float* ed = rp + pd_edge_offset(g.V);
+    float* o = (float*)out;
+    if (t.tx % 64 != 0) return hipErrorInvalidValue;
+    if (t.ty == 2) hipLaunchKernelGGL((k_density_fix<2>), grid, block, 0, st, f, rp, ed, o, g);
+    else if (t.ty == 4) hipLaunchKernelGGL((k_density_fix<4>), grid, block, 0, st, f, rp, ed, o, g);
+    else if (t.ty == 8) hipLaunchKernelGGL((k_density_fix<8>), grid, block, 0, st, f, rp, ed, o, g);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 bool config_fused(const StepSpec& s, int cfg) {
     return s.force && cfg >= 0 && cfg < n_configs(s.lat, s.force) &&
            config_shape(s.lat, s.force, cfg).fd;
@@ -717,12 +1028,12 @@ hipError_t launch_step_in_place(const StepSpec& s, int cfg, int phase, void* f,
 
 hipError_t launch_step(const StepSpec& s, int cfg, const void* fin, void* fout, const void* drho,
                        const unsigned long long* step_dev, unsigned long long step_host,
-                       double* partial, hipStream_t st, void* rho_out) {
+                       double* partial, hipStream_t st, void* rho_out, void* rho_part) {
     StepIndex si{step_dev, step_host};
-    if (s.lat == 0 && s.prec == 0) step_dispatch<0, float>(s, cfg, fin, fout, drho, si, partial, st, rho_out);
-    else if (s.lat == 0) step_dispatch<0, double>(s, cfg, fin, fout, drho, si, partial, st, rho_out);
-    else if (s.prec == 0) step_dispatch<1, float>(s, cfg, fin, fout, drho, si, partial, st, rho_out);
-    else step_dispatch<1, double>(s, cfg, fin, fout, drho, si, partial, st, rho_out);
+    if (s.lat == 0 && s.prec == 0) step_dispatch<0, float>(s, cfg, fin, fout, drho, si, partial, st, rho_out, rho_part);
+    else if (s.lat == 0) step_dispatch<0, double>(s, cfg, fin, fout, drho, si, partial, st, rho_out, rho_part);
+    else if (s.prec == 0) step_dispatch<1, float>(s, cfg, fin, fout, drho, si, partial, st, rho_out, rho_part);
+    else step_dispatch<1, double>(s, cfg, fin, fout, drho, si, partial, st, rho_out, rho_part);
     return hipGetLastError();
 }
 

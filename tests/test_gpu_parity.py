@@ -464,9 +464,11 @@ def test_full_size_landau_256_windows():
     """d3q19_256_landau at full size (256^3, FP32) in the launch shape the
     autotuner picks (the one the benchmark times).  A site's update depends on
     the state within three sites (pull, density, chemical potential, force),
-    so 14^3 windows of the GPU state S_n (periodic in the big box, some across
-    its edges) are advanced by the oracle with the noise of their global site
-    indices, and the inner 8^3 sites are compared with the GPU's S_{n+1}."""
+    so 20^3 windows of the GPU state S_n (periodic in the big box, some across
+    its edges) are advanced two steps by the oracle with the noise of their
+    global site indices, and the inner 8^3 sites are compared with the GPU's
+    S_{n+2}, both steps run in one call: the second step's density is the one
+    the march forms itself where the shape does so."""
     from oracle import flb, philox
     from paper_1012_3632_amd import Simulation, lattice_tables
     wl = W.WORKLOADS["d3q19_256_landau"]
@@ -479,7 +481,7 @@ def test_full_size_landau_256_windows():
     rng = np.random.default_rng(11)
     starts = [(0, 0, 0), (n - 7, n - 7, n - 7), (120, 3, 250)] + \
              [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(3)]
-    Wd, M = 14, 3
+    Wd, M, NS = 20, 6, 2
     wins = []
     for (z0, y0, x0) in starts:
         iz, iy, ix = (torch.as_tensor(_window_ids(n, s0, Wd), device="cuda") for s0 in (z0, y0, x0))
@@ -487,7 +489,7 @@ def test_full_size_landau_256_windows():
     before = [sim.state()[:, iz][:, :, iy][:, :, :, ix].to("cpu", torch.float64) + w * kw["rho0"]
               for iz, iy, ix in wins]
     step_n = sim.step_index
-    sim.step(1, stats_stride=1)
+    sim.step(NS, stats_stride=1)
     after = [sim.state()[:, iz][:, :, iy][:, :, :, ix].to("cpu", torch.float64) + w * kw["rho0"]
              for iz, iy, ix in wins]
     pw = oracle_params(**dict(kw, nx=Wd, ny=Wd, nz=Wd))
@@ -497,14 +499,73 @@ def test_full_size_landau_256_windows():
     for (iz, iy, ix), S0, S1 in zip(wins, before, after):
         gz, gy, gx = (t.cpu().numpy().astype(np.int64) for t in (iz, iy, ix))
         sites = ((gz[:, None, None] * n + gy[None, :, None]) * n + gx[None, None, :]).reshape(-1)
-        z = torch.as_tensor(philox.normals(None, step_n, K, kw["seed"], sites=sites)).reshape(K, Wd, Wd, Wd)
-        f = flb.pull(S0, lat)
-        F = flb.landau_force(flb.density(f), pw, lat)
-        ref = flb.collide(f, F, step_n, pw, lat, z=z)
+        ref = S0
+        for k in range(NS):
+            z = torch.as_tensor(philox.normals(None, step_n + k, K, kw["seed"], sites=sites)).reshape(K, Wd, Wd, Wd)
+            f = flb.pull(ref, lat)
+            F = flb.landau_force(flb.density(f), pw, lat)
+            ref = flb.collide(f, F, step_n + k, pw, lat, z=z)
         inner = (slice(None), slice(M, Wd - M), slice(M, Wd - M), slice(M, Wd - M))
         worst = max(worst, rel_err(S1[inner].numpy(), ref[inner].numpy()))
     assert worst < 1e-5, worst
     sim.close()
+
+
+@pytest.mark.parametrize("eta", [0, 1])
+@pytest.mark.parametrize("shape", [(18, 7, 130), (5, 3, 64)])
+def test_partial_density_march_d3q19(shape, eta):
+    """D3Q19 force shapes whose march forms the next step's density itself
+    (in-tile sources through LDS and wavefront shifts, the rest added by a
+    completion pass from whole rows and the segments' edge records): over a
+    box of several x tiles with a ragged last tile and segment, ragged y tiles
+    and z runs, and over several calls (each starts with a density pass),
+    FP32 states stay within the oracle's tolerance and equal the plain march
+    of the same tile to FP32 rounding; statistics likewise.  In FP64 the
+    shapes run the plain march, bit for bit."""
+    from oracle import flb
+    from paper_1012_3632_amd import Simulation
+    nz, ny, nx = shape
+    kw = dict(W.params_of("d3q19_256_landau", nx=nx, ny=ny, nz=nz), precision="fp32", eta=eta)
+    drho = W.initial_drho(shape, 3, 0.01)
+    probe = Simulation(gpu_params(**kw))
+    shapes = [probe.launch_shape(c) for c in range(probe.launch_configs()[0])]
+    probe.close()
+    pd = [c for c, sh in enumerate(shapes) if sh[7] == 2]
+    assert len(pd) == 3
+    calls = (2, 4, 4)   # even calls keep every call's samples on the oracle's steps
+    po = oracle_params(**kw)
+    S, st = flb.run(flb.initial_state(po, drho), po, sum(calls), stats_stride=2)
+    ref = S.numpy()
+    for c in pd:
+        twin = next(u for u, sh in enumerate(shapes) if sh[:7] == shapes[c][:7] and sh[7] == 0)
+        got = {}
+        for cfg in (c, twin):
+            sim = Simulation(gpu_params(**kw), drho_init=drho)
+            sim.set_launch(cfg)
+            for n in calls:
+                sim.step(n, stats_stride=2)
+            torch.cuda.synchronize()
+            got[cfg] = (sim.populations().numpy(), sim.moments())
+            sim.close()
+        f_pd, (s_pd, s2_pd, ns_pd) = got[c]
+        f_tw, (s_tw, s2_tw, _) = got[twin]
+        assert rel_err(f_pd, ref) < tol(kw), c
+        assert rel_err(f_pd, f_tw) < 1e-6, (c, twin)
+        np.testing.assert_allclose(s2_pd, st["sumsq"], rtol=5e-5, err_msg=str(c))
+        np.testing.assert_allclose(s2_pd, s2_tw, rtol=1e-6, err_msg=str(c))
+    kw64 = dict(kw, precision="fp64")
+    for c in pd:
+        twin = next(u for u, sh in enumerate(shapes) if sh[:7] == shapes[c][:7] and sh[7] == 0)
+        a = Simulation(gpu_params(**kw64), drho_init=drho)
+        b = Simulation(gpu_params(**kw64), drho_init=drho)
+        a.set_launch(c)
+        b.set_launch(twin)
+        a.step(6, stats_stride=1)
+        b.step(6, stats_stride=1)
+        torch.cuda.synchronize()
+        assert torch.equal(a.state(), b.state()), c
+        a.close()
+        b.close()
 
 
 @pytest.mark.parametrize("eta", [0, 1])
