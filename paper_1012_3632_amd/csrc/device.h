@@ -428,11 +428,17 @@ struct ForceMarch {
             const int mx = l % MX, my = l / MX;
             const int c = (my + 1) * RX + (mx + 1);
             const Real rc = rp[1][c];
-            Real lap = Real(0);
+            // (2 / cs2) sum_i w_i (rho(x + c_i) - rho(x)) with the D3Q19
+            // weights 1/18 (6 faces) and 1/36 (12 edges):
+            // faces / 3 + edges / 6 - 4 rho(x)
+            Real faces = Real(0), edges = Real(0);
 #pragma unroll
-            for (int i = 1; i < L::Q; ++i)
-                lap += Real(L::w[i]) * (rp[1 + L::cz[i]][c + L::cy[i] * RX + L::cx[i]] - rc);
-            lap *= Real(6);   // 2 / cs2
+            for (int i = 1; i < L::Q; ++i) {
+                const Real r = rp[1 + L::cz[i]][c + L::cy[i] * RX + L::cx[i]];
+                if (i <= 6) faces += r;
+                else edges += r;
+            }
+            const Real lap = faces * Real(1.0 / 3) + edges * Real(1.0 / 6) - Real(4) * rc;
             const Real d = rc + fp.shift;
             mo[l] = Real(2) * fp.a * d + Real(4) * fp.b * d * d * d - fp.kappa * lap;
         }
@@ -447,23 +453,36 @@ struct ForceMarch {
                              lds_m + mslot(z + 1, zb) * NMP};
         const int cm = (ty + 1) * MX + (tx + 1);
         const int cr = (ty + 2) * RX + (tx + 2);
-        Real gm[3] = {Real(0), Real(0), Real(0)}, gr[3] = {Real(0), Real(0), Real(0)};
+        Real gm[3] = {Real(0), Real(0), Real(0)};
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) {
             const Real mu = mp[1 + L::cz[i]][cm + L::cy[i] * MX + L::cx[i]];
-            const Real rn = rp[1 + L::cz[i]][cr + L::cy[i] * RX + L::cx[i]];
             const int c3[3] = {L::cx[i], L::cy[i], L::cz[i]};
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 if (c3[a] == 0) continue;
-                const Real wc = Real(L::w[i] * c3[a]);
-                gm[a] += wc * mu;
-                gr[a] += wc * rn;
+                gm[a] += Real(L::w[i] * c3[a]) * mu;
             }
         }
         const Real rho = rho0 + rp[1][cr];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) F[a] = -rho * Real(3) * gm[a] + fp.eta * gr[a];
+        for (int a = 0; a < 3; ++a) F[a] = -rho * Real(3) * gm[a];
+        // eta = 1 adds the density gradient (eta is uniform: a scalar branch)
+        if (fp.eta != Real(0)) {
+            Real gr[3] = {Real(0), Real(0), Real(0)};
+#pragma unroll
+            for (int i = 1; i < L::Q; ++i) {
+                const Real rn = rp[1 + L::cz[i]][cr + L::cy[i] * RX + L::cx[i]];
+                const int c3[3] = {L::cx[i], L::cy[i], L::cz[i]};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (c3[a] == 0) continue;
+                    gr[a] += Real(L::w[i] * c3[a]) * rn;
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) F[a] += fp.eta * gr[a];
+        }
     }
 };
 
