@@ -975,8 +975,9 @@ static void ip_dispatch(const StepSpec& s, int cfg, int phase, void* f, StepInde
 }
 
 bool config_partial_density(const StepSpec& s, int cfg) {
-    // the completion pass launches one block per plane in grid z (below 2^16)
-    return s.force && s.prec == 0 && s.nz <= 65535 && cfg >= 0 &&
+    // the completion pass launches one block per plane in grid z and one per
+    // 16 rows in grid y (each below 2^16); otherwise the plain march runs
+    return s.force && s.prec == 0 && s.nz <= 65535 && (s.ny + 15) / 16 <= 65535 && cfg >= 0 &&
            cfg < n_configs(s.lat, s.force) && config_shape(s.lat, s.force, cfg).pd;
 }
 
