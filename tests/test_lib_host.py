@@ -38,6 +38,18 @@ def test_sizes_and_validation():
     pop64, _, _ = query_sizes(Params(lattice="D3Q19", precision="fp64", nx=128, ny=128, nz=128))
     assert pop64 == 2 * pop
     assert sta >= 2 * 19 * 8
+    # the D3Q19 force step in FP32 also holds a second density field (the
+    # march forms the next step's density there) and one 64 B edge record
+    # per 64-wide x segment of every row; FP64 does not
+    landau = dict(lattice="D3Q19", nx=130, ny=7, nz=5, force_model=1, a=-0.01, b=0.1,
+                  rho_c=1.0, kappa=0.05)
+    _, scr32, _ = query_sizes(Params(precision="fp32", **landau))
+    _, scr64, _ = query_sizes(Params(precision="fp64", **landau))
+    V = 130 * 7 * 5
+    assert scr32 >= 2 * V * 4 + 3 * 7 * 5 * 64
+    # the rest of the work area (density, adjoint fields) scales with the
+    # precision, so FP32 exceeds half of FP64 by at least the second field
+    assert scr32 - scr64 // 2 >= V * 4
     bad = [dict(kT=1 / 3), dict(kT=-1e-9), dict(rate_shear=2.0), dict(rate_ghost=0.0),
            dict(nz=2), dict(nx=0), dict(rho0=0.0), dict(lattice="D3Q19", nx=2048, ny=2048, nz=1024),
            dict(force_model=1, kappa=-1.0), dict(force_model=1, eta=2), dict(force_model=3)]
