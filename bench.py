@@ -717,7 +717,8 @@ def main():
                     help="only run the d3q19_128 step (fixed launch shape, statistics on)")
     ap.add_argument("--profile-landau", action="store_true",
                     help="only run the d3q19_256_landau step (FP32, statistics every step) in "
-                         "launch configuration 8 (z-marching 128 x 2 columns, 16 planes), 6 steps")
+                         "launch configuration 10 (z-marching 64 x 4 columns, 16 planes, forming "
+                         "the next density), 6 steps")
     ap.add_argument("--profile-batch", action="store_true",
                     help="only run the d3q19_batch64 replicas (FP32, statistics every step), "
                          "in-place groups of up to 256 MiB, 4 steps")
