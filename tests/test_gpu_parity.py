@@ -568,6 +568,40 @@ def test_partial_density_march_d3q19(shape, eta):
         b.close()
 
 
+def test_partial_density_march_graph_replays():
+    """A captured graph of the march that forms the next density (4 steps:
+    the density pass, then march and completion pass per step) replayed
+    three times, with eager work and synchronizations between the replays,
+    gives the bits of eager calls of 4 steps after every replay: states and
+    statistics."""
+    from paper_1012_3632_amd import Simulation
+    shape = (18, 7, 130)
+    kw = dict(W.params_of("d3q19_256_landau", nx=shape[2], ny=shape[1], nz=shape[0]),
+              precision="fp32")
+    drho = W.initial_drho(shape, 3, 0.01)
+    a = Simulation(gpu_params(**kw), drho_init=drho)
+    b = Simulation(gpu_params(**kw), drho_init=drho)
+    pd = next(c for c in range(a.launch_configs()[0]) if a.launch_shape(c)[7] == 2)
+    a.set_launch(pd)
+    b.set_launch(pd)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b.graph_capture(4, stats_stride=2)
+        for rep in range(3):
+            b.graph_launch()
+            a.step(4, stats_stride=2)
+            torch.cuda.synchronize()
+            assert torch.equal(a.state(), b.state()), rep
+            sa, qa, na = a.moments()
+            sb, qb, nb = b.moments()
+            assert na == nb == 2 * (rep + 1)
+            np.testing.assert_array_equal(sa, sb)
+            np.testing.assert_array_equal(qa, qb)
+            torch.cuda.synchronize()
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("eta", [0, 1])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("shape", [(13, 37), (64, 64), (1, 1), (3, 200)])
