@@ -507,8 +507,14 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(
             }
             const uint32_t site = (uint32_t)((z * g.ny + y) * g.nx + xl);
             Real zn[2 * L::NPAIR];
-            if (P.noise_on)
-                site_normals<L::NPAIR, Real>(site, step, 0u, P.replica, P.key0, P.key1, zn);
+            if (P.noise_on) {
+                // the key is re-read each plane, so that Philox's round keys are
+                // formed next to their use instead of being held in SGPRs through
+                // the loop (which spills them to VGPR lanes)
+                uint32_t k0 = P.key0, k1 = P.key1;
+                asm volatile("" : "+s"(k0), "+s"(k1));
+                site_normals<L::NPAIR, Real>(site, step, 0u, P.replica, k0, k1, zn);
+            }
             collide_moments<1, Real, true>(m, F, zn, P);
             M::inverse(m, f);
             if constexpr (PD) {
