@@ -20,6 +20,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -31,10 +32,14 @@ HBM_PEAK_GBS = 8000.0
 
 def src_hash():
     h = hashlib.sha256()
-    # the step kernel's device sources: kernels.hip and the headers it includes
+    # the step kernel's device sources: kernels.hip and the headers it
+    # includes, with comments left out and white space collapsed (an edit of
+    # comments or layout leaves the counters valid)
     csrc = os.path.join(ROOT, "paper_1012_3632_amd", "csrc")
     for p in [os.path.join(csrc, "kernels.hip")] + sorted(glob.glob(os.path.join(csrc, "*.h"))):
-        h.update(open(p, "rb").read())
+        text = re.sub(r"/\*.*?\*/", " ", open(p).read(), flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -333,8 +333,10 @@ struct MarchDensity {
     static constexpr int ybase(int i) { return (TY == 2 || L::cy[i] == 1) ? 0 : 5; }
     // the in-plane exchange of the plane just computed: the x-only movers
     // into the sums (am: plane below, a0: this plane, ap: plane above), the
-    // others into LDS.  Called by every lane (f of lanes outside the box is
-    // never counted); up / down: this row has a receiver row above / below.
+    // others into LDS.  Called by the lanes inside the box; a lane discards
+    // what the shift brings from a neighbour outside its wavefront row or the
+    // box (vxm, vxp false); up / down: this row has a receiver row above /
+    // below in the tile.
     static __device__ __forceinline__ void put(float* lx, const float (&f)[L::Q], bool vxm, bool vxp,
                                                bool up, bool down, float& am, float& a0, float& ap) {
         // lane l receives from l - 1 (c_x = +1) and from l + 1 (c_x = -1)
