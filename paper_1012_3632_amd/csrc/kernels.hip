@@ -313,8 +313,29 @@ __global__ __launch_bounds__(TX* TY) void k_step_ip(Real* f, Geom g, CollidePara
 // go through LDS (NYS slots of one value per thread), written only by rows
 // whose receiver row is in the tile.  A source counts when it lies in the
 // same 64-wide x segment (one wavefront row), in the block's rows
-// [y0, min(y0 + TY, ny)) and planes [zb, ze), and in the box; k_density_fix
-// adds every other source after the launch.  TX is a multiple of 64.
+// [y0, min(y0 + TY, ny)) and planes [zb, ze), and in the box.  The tile's
+// first and last rows also sum, for each receiver of the row just outside
+// the tile, the movers that cross into it (ghost rows, by the same shifts
+// and running sums; the same segment and plane-run rules).  k_density_fix
+// adds the ghost rows and every other source after the launch.  TX is a
+// multiple of 64.
+// Partial-density work area, element offsets from its start: the partial
+// density (V floats), the edge records (16 floats per (z, y, 64-wide x
+// segment)), then the two ghost-row arrays (receivers below a tile's first
+// row, then above its last row), each sized for tiles of two rows
+// (nz ceil(ny / 2) nx floats, indexed (z, tile row, x)).
+struct PdLayout {
+    size_t edge, ghost_bot, ghost_top, total;
+};
+__host__ __device__ inline PdLayout pd_layout(int nx, int ny, int nz) {
+    const size_t V = (size_t)nx * ny * nz;
+    const size_t nseg = ((size_t)nx + 63) / 64;
+    const size_t e = (V + 63) / 64 * 64;
+    const size_t gb = e + ((size_t)nz * ny * nseg * 16 + 63) / 64 * 64;
+    const size_t gn = ((size_t)nz * ((ny + 1) / 2) * nx + 63) / 64 * 64;
+    return PdLayout{e, gb, gb + gn, gb + 2 * gn};
+}
+
 template <int TX, int TY>
 struct MarchDensity {
     using L = Lattice<1>;
@@ -376,6 +397,28 @@ struct MarchDensity {
             r[4] = f[14];
         }
     }
+    // Ghost-row sums of this row's plane z: bottom (the tile's first row):
+    // the c_y = -1 movers for the row below, (0,-1,0) here, (+1,-1,0) from
+    // x - 1 and (-1,-1,0) from x + 1 by the shifts, (0,-1,+1) into the next
+    // plane's sum and (0,-1,-1) into the previous one's; top (the tile's last
+    // row in the box) likewise with the c_y = +1 movers.  g: sums of planes
+    // z - 1, z, z + 1 (the last assigned here).
+    static __device__ __forceinline__ void put_ghost(const float (&f)[L::Q], bool vxm, bool vxp,
+                                                     bool bottom, bool top, float (&gb)[3],
+                                                     float (&gt)[3]) {
+        if (bottom) {
+            const float r8 = dpp_shift<WAVE_SHR1>(f[8]), r10 = dpp_shift<WAVE_SHL1>(f[10]);
+            gb[0] += f[18];
+            gb[1] += f[4] + ((vxm ? r8 : 0.f) + (vxp ? r10 : 0.f));
+            gb[2] = f[17];
+        }
+        if (top) {
+            const float r7 = dpp_shift<WAVE_SHR1>(f[7]), r9 = dpp_shift<WAVE_SHL1>(f[9]);
+            gt[0] += f[16];
+            gt[1] += f[3] + ((vxm ? r7 : 0.f) + (vxp ? r9 : 0.f));
+            gt[2] = f[15];
+        }
+    }
     // the previous plane's c_y != 0 movers from the rows below (vym) and
     // above (vyp), into am (c_z = -1), a0 (c_z = 0) and ap (c_z = +1)
     static __device__ __forceinline__ void take(const float* lx, bool vxm, bool vxp, bool vym,
@@ -413,7 +456,8 @@ template <typename Real, bool STATS, int TX, int TY, bool NTS = false, bool PD =
 __global__ __launch_bounds__(TX* TY) void k_step_march(
     const Real* __restrict__ fin, Real* __restrict__ fout, const Real* __restrict__ drho, Geom g,
     CollideParams<Real> P, ForceParams<Real> fp, StepIndex st, double* __restrict__ partial,
-    Real* __restrict__ rho_part, Real* __restrict__ edge) {
+    Real* __restrict__ rho_part, Real* __restrict__ edge, Real* __restrict__ ghost_bot,
+    Real* __restrict__ ghost_top) {
     using L = Lattice<1>;
     using M = Moments<1, Real>;
     using FM = ForceMarch<Real, TX, TY>;
@@ -465,6 +509,10 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(
     const bool vxm = (x & 63) != 0, vxp = (x & 63) != 63 && x + 1 < g.nx;
     const bool vym = ty >= 1, vyp = ty + 1 < TY && y + 1 < g.ny;
     const bool up = ty + 1 < TY, down = ty >= 1;
+    // ghost rows: this row is the tile's first / last row in the box
+    const bool gbot = ty == 0, gtop = ty == min(TY, g.ny - y0) - 1;
+    Real gsb[3] = {Real(0), Real(0), Real(0)}, gst[3] = {Real(0), Real(0), Real(0)};
+    const uint32_t grow = (uint32_t)(y0 / TY);
     const uint32_t step = st.get();
 #pragma unroll 1
     for (int z = zb; z < ze; ++z) {
@@ -525,6 +573,13 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(
                 a_p1 = f[5];    // (0, 0, +1) reaches plane z + 1
                 MD::put(lds_x, f, vxm, vxp, up, down, a_m1, a_0, a_p1);
                 MD::put_edge(edge, f, x, y, z, g);
+                MD::put_ghost(f, vxm, vxp, gbot, gtop, gsb, gst);
+                // ghost plane z - 1 has all its sources
+                if (z - 1 >= zb) {
+                    const uint32_t gi = ((uint32_t)(z - 1) * (uint32_t)g.nby + grow) * (uint32_t)g.nx + (uint32_t)x;
+                    if (gbot) ghost_bot[gi] = gsb[0];
+                    if (gtop) ghost_top[gi] = gst[0];
+                }
             }
             if constexpr (ROWS) {
                 const size_t row = (size_t)(uint32_t)((z * g.ny + y) * g.nx);
@@ -542,6 +597,10 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(
             a_m2 = a_m1;
             a_m1 = a_0;
             a_0 = a_p1;
+            gsb[0] = gsb[1];
+            gsb[1] = gsb[2];
+            gst[0] = gst[1];
+            gst[1] = gst[2];
         }
     }
     if constexpr (PD) {
@@ -553,31 +612,36 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(
             if (ze - 2 >= zb)
                 plane_st(rho_part + (size_t)(uint32_t)(((ze - 2) * g.ny + y) * g.nx), (uint32_t)x, a_m2);
             plane_st(rho_part + (size_t)(uint32_t)(((ze - 1) * g.ny + y) * g.nx), (uint32_t)x, a_m1);
+            // ghost plane ze - 1 (its sources in plane ze belong to the next block)
+            const uint32_t gi = ((uint32_t)(ze - 1) * (uint32_t)g.nby + grow) * (uint32_t)g.nx + (uint32_t)x;
+            if (gbot) ghost_bot[gi] = gsb[0];
+            if (gtop) ghost_top[gi] = gst[0];
         }
     }
     if constexpr (STATS) block_accumulate<2 * Q, NT>(v, partial + (size_t)b * 2 * Q, lds_stats);
 }
 
-// Elements from the start of the partial-density work area to its edge
-// records (the partial density comes first, V floats, 256-byte aligned).
-__host__ __device__ inline size_t pd_edge_offset(uint32_t V) { return ((size_t)V + 63) / 64 * 64; }
-
 // Completes the march's partial density: adds to rho_part(x) the streamed
 // populations S*_i(x - c_i) whose source the forming block left out (outside
 // the 64-wide x segment of x, the TY rows of its tile from the origin, its
-// run of g.zc planes, as in k_step_march / MarchDensity), in the order
-// i = 1 .. Q - 1.  A block of four wavefronts covers 64 SPL sites of x
-// (from 64 SPL bx) in RY rows of plane z, each wavefront RY / 4 rows, SPL
-// sites per lane.  Whether a population crosses the row's tile or plane-run edge is
-// uniform, so those loads read whole rows under scalar branches; a
-// segment's first lane (x & 63 == 0) and last lane (x & 63 == 63, or the
-// box's last x) take the x movers from the neighbouring segments' edge
-// records instead of scattered single loads.
+// run of g.zc planes, as in k_step_march / MarchDensity).  A block of four
+// wavefronts covers 64 SPL sites of x (from 64 SPL bx) in RY rows of plane z,
+// each wavefront RY / 4 rows, SPL sites per lane.  A tile's first (last) row
+// adds the ghost row that the march of the tile below (above) formed for it:
+// the sources across the y edge in the same segment and plane run.  Whether
+// a population crosses the plane run's edge is uniform, so those
+// populations are read as whole rows under scalar branches.  A segment's
+// first lane (x & 63 == 0) and last lane (x & 63 == 63, or the box's last x)
+// take the other x movers from the neighbouring segments' edge records.
+// The sum runs over the partial density, the ghost rows, then the
+// populations in the order i = 1 .. Q - 1.
 constexpr int FIX_SPL = 2;   // sites per lane of k_density_fix (2 measured best of 1, 2, 4)
 template <int TY>
 __global__ __launch_bounds__(256) void k_density_fix(const float* __restrict__ fin,
                                                      const float* __restrict__ rho_part,
                                                      const float* __restrict__ edge,
+                                                     const float* __restrict__ ghost_bot,
+                                                     const float* __restrict__ ghost_top,
                                                      float* __restrict__ out, Geom g) {
     using L = Lattice<1>;
     constexpr int SPL = FIX_SPL, RY = 16;
@@ -624,29 +688,42 @@ __global__ __launch_bounds__(256) void k_density_fix(const float* __restrict__ f
             return ((uint32_t)sz * (uint32_t)g.ny + (uint32_t)sy) * nseg * 16u +
                    ((uint32_t)sx >> 6) * 16u + (uint32_t)slot[i];
         };
-        float v[SPL][L::Q];
+        float v[SPL][L::Q], gv[SPL][2];
 #pragma unroll
-        for (int k = 0; k < SPL; ++k)
+        for (int k = 0; k < SPL; ++k) {
+            gv[k][0] = gv[k][1] = 0.f;
 #pragma unroll
             for (int i = 1; i < L::Q; ++i) v[k][i] = 0.f;
-        // whole rows: sources across the tile's y edge or the plane run's z edge
+        }
+        // a tile's edge row: the ghost row that the neighbouring tile's march
+        // formed for it (sources across the y edge, same segment and run)
+        if (ylo) {
+            const uint32_t gi = ((uint32_t)z * (uint32_t)g.nby + (uint32_t)(ym / TY)) * (uint32_t)g.nx;
+#pragma unroll
+            for (int k = 0; k < SPL; ++k) gv[k][0] = ghost_top[gi + (uint32_t)xs[k]];
+        }
+        if (yhi) {
+            const uint32_t gi = ((uint32_t)z * (uint32_t)g.nby + (uint32_t)(yp / TY)) * (uint32_t)g.nx;
+#pragma unroll
+            for (int k = 0; k < SPL; ++k) gv[k][1] = ghost_bot[gi + (uint32_t)xs[k]];
+        }
+        // whole rows: sources across the plane run's z edge
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) {
-            const bool oy = (L::cy[i] == 1 && ylo) || (L::cy[i] == -1 && yhi);
             const bool oz = (L::cz[i] == 1 && zlo) || (L::cz[i] == -1 && zhi);
-            if (oy || oz) {
+            if (oz) {
 #pragma unroll
                 for (int k = 0; k < SPL; ++k) v[k][i] = plane_ld(fin + (size_t)i * g.V, src(i, k));
             }
         }
-        // segment edges, for the x movers not already read as whole rows
+        // segment edges, for the x movers not read as whole rows (also those
+        // crossing the y edge: the ghost rows leave them out)
         if (lane == 0) {
 #pragma unroll
             for (int i = 1; i < L::Q; ++i) {
                 if (L::cx[i] != 1) continue;
-                const bool oy = (L::cy[i] == 1 && ylo) || (L::cy[i] == -1 && yhi);
                 const bool oz = (L::cz[i] == 1 && zlo) || (L::cz[i] == -1 && zhi);
-                if (!(oy || oz)) {
+                if (!oz) {
 #pragma unroll
                     for (int k = 0; k < SPL; ++k) v[k][i] = edge[rec(i, xs[k])];
                 }
@@ -658,9 +735,8 @@ __global__ __launch_bounds__(256) void k_density_fix(const float* __restrict__ f
 #pragma unroll
                 for (int i = 1; i < L::Q; ++i) {
                     if (L::cx[i] != -1) continue;
-                    const bool oy = (L::cy[i] == 1 && ylo) || (L::cy[i] == -1 && yhi);
                     const bool oz = (L::cz[i] == 1 && zlo) || (L::cz[i] == -1 && zhi);
-                    if (!(oy || oz)) v[k][i] = edge[rec(i, xs[k])];
+                    if (!oz) v[k][i] = edge[rec(i, xs[k])];
                 }
             }
         }
@@ -668,7 +744,7 @@ __global__ __launch_bounds__(256) void k_density_fix(const float* __restrict__ f
         for (int k = 0; k < SPL; ++k) {
             if ((int)(blockIdx.x * (64u * SPL)) + 64 * k + lane >= g.nx) break;
             const uint32_t site = row + (uint32_t)xs[k];
-            float acc = plane_ld(rho_part, site);
+            float acc = plane_ld(rho_part, site) + gv[k][0] + gv[k][1];
 #pragma unroll
             for (int i = 1; i < L::Q; ++i) acc += v[k][i];
             plane_st(out, site, acc);
@@ -883,24 +959,30 @@ static void step_march(const StepSpec& s, int zc, const void* fin, void* fout, c
     const ForceParams<Real> fp = force_params<Real>(s);
     if constexpr (std::is_same<Real, float>::value && TX % 64 == 0) {
         Real* rp = (Real*)rho_part;
-        Real* ed = rp ? rp + pd_edge_offset(g.V) : nullptr;
+        const PdLayout lay = pd_layout(s.nx, s.ny, s.nz);
+        Real* ed = rp ? rp + lay.edge : nullptr;
+        Real* gb = rp ? rp + lay.ghost_bot : nullptr;
+        Real* gt = rp ? rp + lay.ghost_top : nullptr;
         if (rp && partial) {
             hipLaunchKernelGGL((k_step_march<Real, true, TX, TY, NTS, true>), grid, block, 0, st,
-                               (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial, rp, ed);
+                               (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial, rp, ed,
+                               gb, gt);
             return;
         }
         if (rp) {
             hipLaunchKernelGGL((k_step_march<Real, false, TX, TY, NTS, true>), grid, block, 0, st,
-                               (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial, rp, ed);
+                               (const Real*)fin, (Real*)fout, (const Real*)drho, g, P, fp, si, partial, rp, ed,
+                               gb, gt);
             return;
         }
     }
+    Real* const none = nullptr;
     if (partial) {
         hipLaunchKernelGGL((k_step_march<Real, true, TX, TY, NTS>), grid, block, 0, st, (const Real*)fin,
-                           (Real*)fout, (const Real*)drho, g, P, fp, si, partial, (Real*)nullptr, (Real*)nullptr);
+                           (Real*)fout, (const Real*)drho, g, P, fp, si, partial, none, none, none, none);
     } else {
         hipLaunchKernelGGL((k_step_march<Real, false, TX, TY, NTS>), grid, block, 0, st, (const Real*)fin,
-                           (Real*)fout, (const Real*)drho, g, P, fp, si, partial, (Real*)nullptr, (Real*)nullptr);
+                           (Real*)fout, (const Real*)drho, g, P, fp, si, partial, none, none, none, none);
     }
 }
 
@@ -991,9 +1073,7 @@ bool config_partial_density(const StepSpec& s, int cfg) {
 
 size_t partial_density_bytes(const StepSpec& s) {
     if (!(s.force && s.lat == 1 && s.prec == 0)) return 0;
-    const size_t V = (size_t)s.nx * s.ny * s.nz;
-    const size_t nseg = ((size_t)s.nx + 63) / 64;
-    return pd_edge_offset((uint32_t)V) * 4 + (size_t)s.nz * s.ny * nseg * 16 * 4;
+    return pd_layout(s.nx, s.ny, s.nz).total * 4;
 }
 
 hipError_t launch_density_fix(const StepSpec& s, int cfg, const void* fin, const void* rho_part,
@@ -1004,12 +1084,15 @@ hipError_t launch_density_fix(const StepSpec& s, int cfg, const void* fin, const
     const dim3 grid((s.nx + 64 * FIX_SPL - 1) / (64 * FIX_SPL), (s.ny + 15) / 16, s.nz), block(256);
     const float* f = (const float*)fin;
     const float* rp = (const float*)rho_part;
-    const float* ed = rp + pd_edge_offset(g.V);
+    const PdLayout lay = pd_layout(s.nx, s.ny, s.nz);
+    const float* ed = rp + lay.edge;
+    const float* gb = rp + lay.ghost_bot;
+    const float* gt = rp + lay.ghost_top;
     float* o = (float*)out;
     if (t.tx % 64 != 0) return hipErrorInvalidValue;
-    if (t.ty == 2) hipLaunchKernelGGL((k_density_fix<2>), grid, block, 0, st, f, rp, ed, o, g);
-    else if (t.ty == 4) hipLaunchKernelGGL((k_density_fix<4>), grid, block, 0, st, f, rp, ed, o, g);
-    else if (t.ty == 8) hipLaunchKernelGGL((k_density_fix<8>), grid, block, 0, st, f, rp, ed, o, g);
+    if (t.ty == 2) hipLaunchKernelGGL((k_density_fix<2>), grid, block, 0, st, f, rp, ed, gb, gt, o, g);
+    else if (t.ty == 4) hipLaunchKernelGGL((k_density_fix<4>), grid, block, 0, st, f, rp, ed, gb, gt, o, g);
+    else if (t.ty == 8) hipLaunchKernelGGL((k_density_fix<8>), grid, block, 0, st, f, rp, ed, gb, gt, o, g);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
