@@ -353,7 +353,7 @@ def extras(args, stream):
     drho = W.initial_drho(p.shape, 7, W.WORKLOADS["d3q19_256_landau"]["init_noise"])
     s = Simulation(p, drho_init=drho)
     del drho
-    (_, cfg_stats, _, _), _ = s.autotune(repeats=3)
+    (cfg_plain, cfg_stats, _, _), _ = s.autotune(repeats=3)
     s.step(5, stats_stride=1)
     n = max(args.steps // 4, 100)
     ms = time_steps(s, n, 1, stream)
@@ -375,14 +375,20 @@ def extras(args, stream):
         # 19 writes + the density): 80 + 156 = 236 B per site
         bytes_site = 236
         pattern = "density pass + march"
+    # the same steps without statistics (the autotuner's plain shape)
+    ms_plain = time_steps(s, n, 0, stream)
     res["d3q19_256_landau"] = {"ms_per_step": round(ms, 4), "MLUPS": round(V / (ms * 1e-3) / 1e6, 1),
                                "steps_timed": n, "pattern": pattern,
+                               "ms_per_step_without_statistics": round(ms_plain, 4),
+                               "hbm_frac_algorithmic_160B_without_statistics":
+                                   round(160 * V / (ms_plain * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                "bytes_per_site": round(bytes_site, 2),
                                "hbm_frac_algorithmic": round(bytes_site * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                # the method's minimum: populations in and out plus
                                # one density write and read (152 + 8 B)
                                "hbm_frac_algorithmic_160B": round(160 * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                "launch_config": cfg_stats, "launch_shape": shape,
+                               "launch_config_without_statistics": cfg_plain,
                                "statistics": "every step"}
     s.close()
     del s
