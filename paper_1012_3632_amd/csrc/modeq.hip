@@ -34,7 +34,7 @@
 // (blockIdx.y = step within the batch): at small lattices a single step's
 // lines are far fewer blocks than the chip has CUs.
 // Each line sits in LDS with its twiddles.  Power-of-two extents use an
-// in-place radix-2 FFT, the butterfly stages taken two per pass through LDS
+// in-place radix-2 FFT, the butterfly stages taken three per pass through LDS
 // and shared by all lines of a block: decimation in time from bit-reversed
 // input for the rows, and for the columns decimation in frequency forward
 // (bit-reversed output), the mix in that order, then decimation in time back.
@@ -120,15 +120,43 @@ __device__ __forceinline__ void bfly(cx_t<R>& a, cx_t<R>& x, cx_t<R> w, bool inv
 // In place, the NL lines b[L n .. (L + 1) n) (n = 2^logn), each loaded in
 // bit-reversed order, become their transforms in natural order
 // (exp(-+ 2 pi i j k / n), sign - forward, + inverse): decimation in time.
-// Radix-2 stages are taken two at a time: stages s and s + 1 (half
-// h = 2^(s-1)) combine the four elements a, a + h, a + 2h, a + 3h of a group,
-// so a thread loads them once, applies both stages in registers and stores
-// them; the quads of a pass are disjoint.  An odd last stage is a plain
-// radix-2 pass.  Ends with a barrier.
+// Radix-2 stages are taken three at a time: stages s, s + 1, s + 2 (half
+// h = 2^(s-1)) combine the eight elements a + k h (k = 0 .. 7) of a group, so
+// a thread loads them once, applies the three stages in registers and stores
+// them; the groups of a pass are disjoint.  The one or two stages left over
+// take a pass of four-element groups or a plain radix-2 pass.  Every
+// butterfly is the one of the stage-by-stage transform.  Ends with a barrier.
 template <typename R>
 __device__ __forceinline__ void fft_lines_dit(cx_t<R>* b, const cx_t<R>* __restrict__ tw, int NL,
                                               int n, int logn, bool inverse) {
     int s = 1;
+    for (; s + 2 <= logn; s += 3) {
+        const int h = 1 << (s - 1);
+        const int st1 = n >> s, st2 = n >> (s + 1), st3 = n >> (s + 2);
+        const int ng = n >> 3;
+        for (int t = threadIdx.x; t < NL * ng; t += blockDim.x) {
+            const int L = t >> (logn - 3);
+            const int q = t - L * ng;
+            const int pos = q & (h - 1);
+            const int a = L * n + ((q >> (s - 1)) << (s + 2)) + pos;
+            cx_t<R> x[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[k] = b[a + k * h];
+            const cx_t<R> w1 = tw[pos * st1];
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) bfly<R>(x[k], x[k + 1], w1, inverse);   // stage s
+            const cx_t<R> w20 = tw[pos * st2], w21 = tw[(pos + h) * st2];
+            bfly<R>(x[0], x[2], w20, inverse);                                    // stage s + 1
+            bfly<R>(x[1], x[3], w21, inverse);
+            bfly<R>(x[4], x[6], w20, inverse);
+            bfly<R>(x[5], x[7], w21, inverse);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bfly<R>(x[k], x[k + 4], tw[(pos + k * h) * st3], inverse);   // stage s + 2
+#pragma unroll
+            for (int k = 0; k < 8; ++k) b[a + k * h] = x[k];
+        }
+        __syncthreads();
+    }
     for (; s + 1 <= logn; s += 2) {
         const int h = 1 << (s - 1);
         const int st1 = n >> s, st2 = n >> (s + 1);
@@ -185,13 +213,42 @@ __device__ __forceinline__ void bfly_dif(cx_t<R>& u, cx_t<R>& v, cx_t<R> w) {
 
 // In place, the NL lines of b (natural order) become their forward
 // transforms in bit-reversed order: decimation in frequency, stages from
-// half n/2 down to 1, two per pass (halves 2 q and q combine the elements a,
-// a + q, a + 2q, a + 3q of a group of 4q); an odd last stage (half 1) alone.
-// Ends with a barrier.
+// half n/2 down to 1, three per pass (halves 4 q, 2 q and q combine the
+// elements a + k q, k = 0 .. 7, of a group of 8 q); one or two stages left
+// over take a pass of four-element groups (halves 2 q, q) or the last stage
+// (half 1) alone.  Every butterfly is the one of the stage-by-stage
+// transform.  Ends with a barrier.
 template <typename R>
 __device__ __forceinline__ void fft_lines_dif(cx_t<R>* b, const cx_t<R>* __restrict__ tw, int NL,
                                               int n, int logn) {
     int s = logn;
+    for (; s >= 3; s -= 3) {
+        const int q8 = 1 << (s - 3);
+        const int stA = n >> s, stB = n >> (s - 1), stC = n >> (s - 2);
+        const int ng = n >> 3;
+        for (int t = threadIdx.x; t < NL * ng; t += blockDim.x) {
+            const int L = t >> (logn - 3);
+            const int qq = t - L * ng;
+            const int pos = qq & (q8 - 1);
+            const int a = L * n + ((qq >> (s - 3)) << s) + pos;
+            cx_t<R> x[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[k] = b[a + k * q8];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bfly_dif<R>(x[k], x[k + 4], tw[(pos + k * q8) * stA]);   // half 4 q8
+            const cx_t<R> wB0 = tw[pos * stB], wB1 = tw[(pos + q8) * stB];
+            bfly_dif<R>(x[0], x[2], wB0);                                                      // half 2 q8
+            bfly_dif<R>(x[1], x[3], wB1);
+            bfly_dif<R>(x[4], x[6], wB0);
+            bfly_dif<R>(x[5], x[7], wB1);
+            const cx_t<R> wC = tw[pos * stC];                                                  // half q8
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) bfly_dif<R>(x[k], x[k + 1], wC);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) b[a + k * q8] = x[k];
+        }
+        __syncthreads();
+    }
     for (; s >= 2; s -= 2) {
         const int q4 = 1 << (s - 2);
         const int stA = n >> s, stC = n >> (s - 1);
