@@ -706,6 +706,64 @@ def test_maximum_size_windows(precision, dims):
     torch.cuda.empty_cache()
 
 
+def test_maximum_size_landau_march_windows():
+    """The largest FP32 lattice the 32-bit plane offsets allow (1024 x 1024 x
+    1023; the populations take 163 GB, the work area 35 GB) for the
+    square-gradient fluid, in the z-marching shape that forms the next
+    density (partial sums, edge records, ghost rows: the largest of their
+    32-bit indices here).  The density fluctuations come from the noise
+    (kT = 1e-4, four steps).  20^3 windows of the state (at the origin,
+    across the periodic wrap of the far corner, at the last sites, at random
+    places) are advanced two steps by the oracle with the noise of their
+    global site indices and the inner 8^3 compared with the GPU's, both
+    steps in one call (the second uses the density the march formed)."""
+    from oracle import flb, philox
+    from paper_1012_3632_amd import Simulation, lattice_tables
+    nx, ny, nz = 1024, 1024, 1023
+    assert nx * ny * nz * 4 < 2 ** 32 <= nx * ny * (nz + 1) * 4
+    kw = dict(W.params_of("d3q19_256_landau", nx=nx, ny=ny, nz=nz), precision="fp32", kT=1e-4)
+    sim = Simulation(gpu_params(**kw))
+    pd = next(c for c in range(sim.launch_configs()[0]) if sim.launch_shape(c)[7] == 2)
+    sim.set_launch(pd)
+    sim.step(4, stats_stride=1)
+    w = torch.as_tensor(lattice_tables("D3Q19")["w"]).view(-1, 1, 1, 1)
+    rng = np.random.default_rng(9)
+    Wd, M, NS = 20, 6, 2
+    starts = [(0, 0, 0), (nz - 10, ny - 10, nx - 10), (nz - Wd, ny - Wd, nx - Wd)] + \
+             [(int(rng.integers(0, nz)), int(rng.integers(0, ny)), int(rng.integers(0, nx)))
+              for _ in range(2)]
+    ids = [tuple(torch.as_tensor(_window_ids(n, s0, Wd), device="cuda")
+                 for n, s0 in zip((nz, ny, nx), st)) for st in starts]
+
+    def windows():
+        S = sim.state()
+        return [S[:, iz[:, None, None], iy[None, :, None], ix[None, None, :]]
+                .to("cpu", torch.float64) + w * kw["rho0"] for iz, iy, ix in ids]
+
+    before = windows()
+    n0 = sim.step_index
+    sim.step(NS, stats_stride=1)
+    after = windows()
+    pw = oracle_params(**dict(kw, nx=Wd, ny=Wd, nz=Wd))
+    lat = flb.lattice_of(pw)
+    K = len(lat.noncons())
+    inner = (slice(None),) + (slice(M, Wd - M),) * 3
+    for win, S0, S1 in zip(ids, before, after):
+        iz, iy, ix = (t.cpu().numpy().astype(np.int64) for t in win)
+        sites = ((iz[:, None, None] * ny + iy[None, :, None]) * nx + ix[None, None, :]).reshape(-1)
+        ref = S0
+        for k in range(NS):
+            z = torch.as_tensor(philox.normals(None, n0 + k, K, kw["seed"], sites=sites)).reshape(K, Wd, Wd, Wd)
+            f = flb.pull(ref, lat)
+            ref = flb.collide(f, flb.landau_force(flb.density(f), pw, lat), n0 + k, pw, lat, z=z)
+        assert rel_err(S1[inner].numpy(), ref[inner].numpy()) < 1e-5, int(win[0][0])
+    s1, s2, ns = sim.moments()
+    assert ns == 6 and np.all(np.isfinite(s1)) and np.all(np.isfinite(s2))
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+
 def test_full_size_batch64_replicas():
     """d3q19_batch64 at full size (64 replicas, 21.6 M sites) with the grid the
     autotuner picks, stepped through a captured graph as in the benchmark;
