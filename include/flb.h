@@ -127,6 +127,13 @@ flb_status flb_init(const flb_params* p, void* f_a, void* f_b, void* scratch, vo
  * this call) with (k + 1) % stats_stride == 0 are accumulated into the FP64
  * statistics (sum and sum of squares per mode over sites, with m_0 taken as
  * rho - rho0): the equal-time mode variances that Sec. IV.A eq. G-ideal fixes.
+ * Identical calls give identical bits.  With a launch shape that forms the
+ * next step's density in the force step (flb_launch_shape shape[7] == 2), the
+ * first step of a call (and of each flb_set_check chunk) takes its density
+ * from a density pass and the later ones from the step's own sums, which
+ * agree to FP32 rounding: splitting the same steps into other calls changes
+ * the state at that level (every other shape gives the same bits however
+ * the steps are split).
  * Returns FLB_ERR_INVALID_ARG for nsteps < 0 or stats_stride < 0 (nothing
  * queued), FLB_ERR_HIP if a launch fails.  Asynchronous. */
 flb_status flb_step(flb_handle* h, int64_t nsteps, int32_t stats_stride, void* stream);
