@@ -575,6 +575,31 @@ def test_partial_density_march_d3q19(shape, eta):
         b.close()
 
 
+def test_partial_density_march_call_splits():
+    """Shapes that form the next density: the same calls give the same bits;
+    the same steps split into other calls (each call's first step takes the
+    density pass's density) agree to FP32 rounding."""
+    from paper_1012_3632_amd import Simulation
+    shape = (18, 7, 130)
+    kw = dict(W.params_of("d3q19_256_landau", nx=shape[2], ny=shape[1], nz=shape[0]),
+              precision="fp32")
+    drho = W.initial_drho(shape, 3, 0.01)
+    probe = Simulation(gpu_params(**kw))
+    pd = next(c for c in range(probe.launch_configs()[0]) if probe.launch_shape(c)[7] == 2)
+    probe.close()
+    states = []
+    for calls in ((8,), (8,), (3, 5)):
+        sim = Simulation(gpu_params(**kw), drho_init=drho)
+        sim.set_launch(pd)
+        for n in calls:
+            sim.step(n)
+        torch.cuda.synchronize()
+        states.append(sim.populations().numpy())
+        sim.close()
+    assert np.array_equal(states[0], states[1])
+    assert rel_err(states[2], states[0]) < 1e-6
+
+
 def test_partial_density_march_graph_replays():
     """A captured graph of the march that forms the next density (4 steps:
     the density pass, then march and completion pass per step) replayed
