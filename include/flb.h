@@ -479,7 +479,9 @@ flb_status flb_batch_destroy(flb_batch* b);
  * populations of Sec. V eq. lbe-mom after collision, summed over c_i as
  * streaming delivers them: in-tile sources through LDS and wavefront shifts,
  * the rest added by a completion pass), so that only the first step of a
- * call runs a density pass) the way a run uses it (ordinary
+ * call runs a density pass; the trials time steady steps, so for calls of a
+ * few steps the plain march of the same tile, which needs no such first
+ * pass, can be the faster choice) the way a run uses it (ordinary
  * steps alternate the two buffers over `repeats` steps; in-place pairs are
  * timed after about 4 ms of settling steps, round-robin over at least three
  * rounds of about 2 ms each, best round kept) and afterwards
